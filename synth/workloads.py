@@ -1,0 +1,50 @@
+"""Named workloads: field recipe + DBP shape, after the systems of Sec. IV-A.
+
+Each entry gives the transmitted WDM signal, the forward link used to make the
+received field, and the CB-ESSFM shape run on it.  Names state what the
+workload is.  ``n_overlap`` is in full-field samples; ``n_sub`` is N' = N/N_sb.
+"""
+from __future__ import annotations
+
+from .field import ChannelSpec, WdmSpec, received_field
+
+WORKLOADS = {
+    # single channel, one span, one DBP step: the small parity case
+    "1ch-32GBd-16QAM-2^14sym-1x80km": dict(
+        wdm=WdmSpec(n_symbols=2 ** 14, n_channels=1, baud=32e9, spacing=100e9, rolloff=0.1,
+                    qam_order=16, sample_rate=64e9, power_dbm_per_channel=2.0),
+        ch=ChannelSpec(n_spans=1, span_km=80.0, steps_per_span=200, nf_db=5.0),
+        dbp=dict(n_sb=1, n_sub=1024, n_overlap=128, n_steps=1, rho=0.5, n_taps=11),
+    ),
+    # five 64-GBd channels on a 100-GHz grid, 15 spans, 15 asymmetric steps
+    "5ch-64GBd-64QAM-2^16sym-15x80km": dict(
+        wdm=WdmSpec(n_symbols=2 ** 16, n_channels=5, baud=64e9, spacing=100e9, rolloff=0.05,
+                    qam_order=64, sample_rate=640e9, power_dbm_per_channel=2.0),
+        ch=ChannelSpec(n_spans=15, span_km=80.0, steps_per_span=1000, nf_db=5.0),
+        dbp=dict(n_sb=5, n_sub=4096, n_overlap=2560, n_steps=15, rho=0.3, n_taps=21),
+    ),
+    # single channel, one span, 15 fractional-span DBP steps (gradient workload)
+    "1ch-32GBd-16QAM-2^14sym-1x80km-15steps": dict(
+        wdm=WdmSpec(n_symbols=2 ** 14, n_channels=1, baud=32e9, spacing=100e9, rolloff=0.1,
+                    qam_order=16, sample_rate=64e9, power_dbm_per_channel=2.0),
+        ch=ChannelSpec(n_spans=1, span_km=80.0, steps_per_span=200, nf_db=5.0),
+        dbp=dict(n_sb=1, n_sub=1024, n_overlap=128, n_steps=15, rho=0.5, n_taps=11),
+    ),
+}
+
+
+def workload(name: str, seed: int, steps_per_span: int | None = None, ase: bool = True):
+    """Seeded received field (2, T), symbols and the workload entry.
+
+    ``steps_per_span`` overrides the forward simulator's step count (the
+    received field's fine structure does not change the cost or the parity of
+    the backpropagation, only its SNR).
+    """
+    w = WORKLOADS[name]
+    ch = w["ch"]
+    if steps_per_span is not None or not ase:
+        ch = ChannelSpec(**{**ch.__dict__,
+                            "steps_per_span": steps_per_span or ch.steps_per_span,
+                            "ase": ase})
+    field, syms = received_field(w["wdm"], ch, seed)
+    return field, syms, w
