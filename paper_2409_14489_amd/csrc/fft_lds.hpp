@@ -1,0 +1,297 @@
+// Register-resident radix-16/8/4/2 complex FP32 FFT of one subband block, with
+// LDS used only to exchange data between Stockham passes.
+//
+// Layout contract (the whole kernel is built around it): a workgroup of NT
+// threads handles an N-point transform; thread t owns the RR = N / NT
+// samples at positions t + NT * o, o in [0, RR), both on input and output.
+// The first pass reads its butterfly inputs straight from those registers and
+// the last pass leaves its outputs in them, so pointwise work before and
+// after a transform (GVD filter, intensity, rotation) never touches LDS.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace cbessfm {
+
+// ---------------------------------------------------------------- complex ops
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// a * (-j) for the forward transform, a * (+j) for the inverse
+template <bool INV>
+__device__ __forceinline__ float2 mul_mj(float2 a) {
+  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+template <bool INV>
+__device__ __forceinline__ float2 twmul(float2 a, float2 w) {  // a * w (fwd) or a * conj(w) (inv)
+  return INV ? cmulc(a, w) : cmul(a, w);
+}
+
+// cos / sin of 2 pi k / 16
+__host__ __device__ constexpr float cos16(int k) {
+  constexpr float c[16] = {1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f,
+                           0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f,
+                           -1.0f, -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508977f,
+                           0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f};
+  return c[k & 15];
+}
+__host__ __device__ constexpr float sin16(int k) { return cos16(k + 12); }
+
+// a * exp(-+ j 2 pi K / 16): '-' forward, '+' inverse
+template <int K, bool INV>
+__device__ __forceinline__ float2 w16(float2 a) {
+  constexpr int k = K & 15;
+  if constexpr (k == 0) {
+    return a;
+  } else if constexpr (k == 4) {
+    return mul_mj<INV>(a);
+  } else if constexpr (k == 8) {
+    return make_float2(-a.x, -a.y);
+  } else if constexpr (k == 12) {
+    return mul_mj<!INV>(a);
+  } else {
+    constexpr float c = cos16(k), s = sin16(k);
+    if constexpr (!INV) return make_float2(a.x * c + a.y * s, a.y * c - a.x * s);
+    else return make_float2(a.x * c - a.y * s, a.y * c + a.x * s);
+  }
+}
+
+// ------------------------------------------------------------- small DFTs
+template <bool INV>
+__device__ __forceinline__ void dft2(float2& a, float2& b) {
+  float2 t = a;
+  a = cadd(t, b);
+  b = csub(t, b);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
+  float2 t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), t3 = mul_mj<INV>(csub(a1, a3));
+  a0 = cadd(t0, t2);
+  a2 = csub(t0, t2);
+  a1 = cadd(t1, t3);
+  a3 = csub(t1, t3);
+}
+
+// 8-point DFT, natural order in and out (n = 2 n1 + n2, k = k1 + 4 k2)
+template <bool INV>
+__device__ __forceinline__ void dft8(float2 (&v)[8]) {
+  dft4<INV>(v[0], v[2], v[4], v[6]);
+  dft4<INV>(v[1], v[3], v[5], v[7]);
+  v[3] = w16<2, INV>(v[3]);
+  v[5] = w16<4, INV>(v[5]);
+  v[7] = w16<6, INV>(v[7]);
+  dft2<INV>(v[0], v[1]);
+  dft2<INV>(v[2], v[3]);
+  dft2<INV>(v[4], v[5]);
+  dft2<INV>(v[6], v[7]);
+  // v[2 k1 + k2] = X[k1 + 4 k2]
+  float2 o[8];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    o[k1] = v[2 * k1];
+    o[k1 + 4] = v[2 * k1 + 1];
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = o[i];
+}
+
+// 16-point DFT, natural order in and out (n = 4 n1 + n2, k = k1 + 4 k2)
+template <bool INV>
+__device__ __forceinline__ void dft16(float2 (&v)[16]) {
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) dft4<INV>(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
+  // v[4 k1 + n2] = A_n2[k1]; multiply by W16^(n2 k1)
+  v[5] = w16<1, INV>(v[5]);
+  v[6] = w16<2, INV>(v[6]);
+  v[7] = w16<3, INV>(v[7]);
+  v[9] = w16<2, INV>(v[9]);
+  v[10] = w16<4, INV>(v[10]);
+  v[11] = w16<6, INV>(v[11]);
+  v[13] = w16<3, INV>(v[13]);
+  v[14] = w16<6, INV>(v[14]);
+  v[15] = w16<9, INV>(v[15]);
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) dft4<INV>(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+  // v[4 k1 + k2] = X[k1 + 4 k2]
+  float2 o[16];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) o[k1 + 4 * k2] = v[4 * k1 + k2];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = o[i];
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft(float2 (&v)[R]) {
+  if constexpr (R == 2) {
+    dft2<INV>(v[0], v[1]);
+  } else if constexpr (R == 4) {
+    dft4<INV>(v[0], v[1], v[2], v[3]);
+  } else if constexpr (R == 8) {
+    dft8<INV>(v);
+  } else {
+    static_assert(R == 16, "radix");
+    dft16<INV>(v);
+  }
+}
+
+// ------------------------------------------------------------- plan (constexpr)
+// LDS index padding that breaks the power-of-two strides of the exchanges.
+__device__ __forceinline__ int pad_c(int i) { return i + (i >> 4) + (i >> 8); }
+__host__ __device__ constexpr int pad_c_size(int n) { return n + (n >> 4) + (n >> 8) + 1; }
+__device__ __forceinline__ int pad_f(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int pad_f_size(int n) { return n + (n >> 4) + 1; }
+
+template <int N>
+struct FftShape {
+  static_assert(N >= 256 && N <= 8192 && (N & (N - 1)) == 0, "N' must be a power of two in [256, 8192]");
+  static constexpr int RR = N >= 1024 ? 16 : N / 64;  // samples per thread per polarisation
+  static constexpr int NT = N / RR;                   // threads per workgroup
+  static constexpr int radix(int p) {
+    int rem = N;
+    for (int q = 0; q < p; ++q) rem /= (rem < RR ? rem : RR);
+    return rem < RR ? rem : RR;
+  }
+  static constexpr int stride(int p) {  // L_p = product of the radices before pass p
+    int l = 1;
+    for (int q = 0; q < p; ++q) l *= radix(q);
+    return l;
+  }
+  static constexpr int passes() {
+    int p = 0, rem = N;
+    while (rem > 1) {
+      rem /= (rem < RR ? rem : RR);
+      ++p;
+    }
+    return p;
+  }
+  // twiddle registers of pass p (>= 1): (RR / R_p) butterflies x (R_p - 1)
+  static constexpr int tw_offset(int p) {
+    int off = 0;
+    for (int q = 1; q < p; ++q) off += (RR / radix(q)) * (radix(q) - 1);
+    return off;
+  }
+  static constexpr int TWC = tw_offset(passes());
+  static constexpr int LDS_C = pad_c_size(N);  // float2 entries per exchange buffer
+};
+
+// Loads this thread's twiddles W_{L R}^{k m} (k = j mod L) for every pass >= 1
+// from the table tw[n] = exp(-j 2 pi n / N) (rounded from FP64 on the host).
+template <int N, int P>
+__device__ __forceinline__ void load_twiddles_pass(float2 (&tw)[FftShape<N>::TWC > 0 ? FftShape<N>::TWC : 1],
+                                                   const float2* __restrict__ table, int t) {
+  using S = FftShape<N>;
+  if constexpr (P < S::passes()) {
+    constexpr int R = S::radix(P), L = S::stride(P), NB = S::RR / R, SCALE = N / (L * R);
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      const int k = (t + S::NT * a) % L;
+#pragma unroll
+      for (int m = 1; m < R; ++m) tw[S::tw_offset(P) + a * (R - 1) + (m - 1)] = table[(k * m * SCALE) % N];
+    }
+    load_twiddles_pass<N, P + 1>(tw, table, t);
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void load_twiddles(float2 (&tw)[FftShape<N>::TWC > 0 ? FftShape<N>::TWC : 1],
+                                              const float2* __restrict__ table, int t) {
+  load_twiddles_pass<N, 1>(tw, table, t);
+}
+
+// One Stockham pass p of radix R over both polarisations.
+//   FIRST: inputs come from the owned registers (positions t + NT o)
+//   LAST : outputs go to the owned registers
+// Otherwise inputs are read from / outputs written to LDS.
+template <int N, int P, bool INV>
+__device__ __forceinline__ void fft_pass(float2 (&x)[FftShape<N>::RR], float2 (&y)[FftShape<N>::RR],
+                                         float2* __restrict__ lx, float2* __restrict__ ly,
+                                         const float2 (&tw)[FftShape<N>::TWC > 0 ? FftShape<N>::TWC : 1],
+                                         int t) {
+  using S = FftShape<N>;
+  constexpr int R = S::radix(P);
+  constexpr int L = S::stride(P);
+  constexpr int NB = S::RR / R;           // butterflies per thread
+  constexpr bool FIRST = (P == 0);
+  constexpr bool LAST = (P == S::passes() - 1);
+  constexpr int NR = N / R;
+  // gather inputs: vx[a][m] = x[j + m N/R], j = t + NT a
+  float2 vx[NB][R], vy[NB][R];
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      if constexpr (FIRST) {
+        vx[a][m] = x[a + m * NB];
+        vy[a][m] = y[a + m * NB];
+      } else {
+        const int idx = pad_c(t + S::NT * a + m * NR);
+        vx[a][m] = lx[idx];
+        vy[a][m] = ly[idx];
+      }
+    }
+  if constexpr (!FIRST && !LAST) __syncthreads();  // everyone has read before anyone writes
+#pragma unroll
+  for (int a = 0; a < NB; ++a) {
+    if constexpr (!FIRST) {
+#pragma unroll
+      for (int m = 1; m < R; ++m) {
+        const float2 w = tw[S::tw_offset(P) + a * (R - 1) + (m - 1)];
+        vx[a][m] = twmul<INV>(vx[a][m], w);
+        vy[a][m] = twmul<INV>(vy[a][m], w);
+      }
+    }
+    dft<R, INV>(vx[a]);
+    dft<R, INV>(vy[a]);
+  }
+#pragma unroll
+  for (int a = 0; a < NB; ++a) {
+    const int j = t + S::NT * a;
+    const int k = j % L;
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      if constexpr (LAST) {  // j < L here, so the output position is j + m L
+        x[a + m * NB] = vx[a][m];
+        y[a + m * NB] = vy[a][m];
+      } else {
+        const int idx = pad_c((j - k) * R + k + m * L);
+        lx[idx] = vx[a][m];
+        ly[idx] = vy[a][m];
+      }
+    }
+  }
+  if constexpr (!LAST) __syncthreads();
+}
+
+template <int N, int P, bool INV>
+__device__ __forceinline__ void fft_passes(float2 (&x)[FftShape<N>::RR], float2 (&y)[FftShape<N>::RR],
+                                           float2* lx, float2* ly,
+                                           const float2 (&tw)[FftShape<N>::TWC > 0 ? FftShape<N>::TWC : 1],
+                                           int t) {
+  if constexpr (P < FftShape<N>::passes()) {
+    fft_pass<N, P, INV>(x, y, lx, ly, tw, t);
+    fft_passes<N, P + 1, INV>(x, y, lx, ly, tw, t);
+  }
+}
+
+// Unnormalised size-N DFT (INV = false: exp(-j...), INV = true: exp(+j...))
+// of the two owned register sets.  Starts with a barrier so that earlier LDS
+// readers are done before the first pass overwrites the exchange buffers.
+template <int N, bool INV>
+__device__ __forceinline__ void fft(float2 (&x)[FftShape<N>::RR], float2 (&y)[FftShape<N>::RR],
+                                    float2* lx, float2* ly,
+                                    const float2 (&tw)[FftShape<N>::TWC > 0 ? FftShape<N>::TWC : 1], int t) {
+  __syncthreads();
+  fft_passes<N, 0, INV>(x, y, lx, ly, tw, t);
+}
+
+}  // namespace cbessfm

@@ -1,0 +1,83 @@
+// Internal plan layout and kernel-argument blocks shared by the host code and
+// the HIP kernels of libcbessfm.  Nothing here crosses the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cbessfm.h"
+
+namespace cbessfm {
+
+constexpr int kMaxSubbands = 8;
+constexpr int kTapChunk = 8;          // FIR taps are processed in chunks of 8
+constexpr int kMaxTaps = 255;
+constexpr int kBarStride = 64;        // uint32 words between team barrier counters (256 B)
+constexpr int kXcds = 8;              // MI355X: 8 accelerator complex dies, round-robin dispatch
+
+// Device tables of one plan (all FP32 values are FP64 results rounded once).
+struct Tables {
+  const float2* h_first;  // [N] exp(+j phi (1 - rho) L) / N,  phi = 2 pi^2 beta2 f^2, subband order
+  const float2* h_mid;    // [N] exp(+j phi L) / N'
+  const float2* h_last;   // [N] exp(+j phi rho L) / N'
+  const float2* tw;       // [N'] exp(-j 2 pi n / N')
+  const float2* poly_tw;  // [n_sb][N'] exp(-j 2 pi i k / N)
+  const float* cpad;      // [steps][n_sb][n_sb][tap_pad] applied coefficients, zero padded
+  float2 wsb[kMaxSubbands];  // exp(-j 2 pi a / n_sb)
+};
+
+// Everything a forward launch needs.
+struct FwdArgs {
+  const float2* in;   // [batch][2][T]
+  float2* out;        // [batch][2][T]
+  long long T;
+  int n_items;        // batch * blocks per instance
+  int nblk;           // overlap-and-save blocks per instance
+  int n_sb, steps, n_chunks, nc, n_ov, hop, boundary;
+  int n_teams;        // persistent teams of n_sb workgroups
+  Tables tab;
+  float2* xspec;      // [n_teams][2 slots][n_sb][2 pol][N']   subband spectra exchange
+  float* xp;          // [n_teams][2 slots][n_sb][N']          intensity exchange
+  unsigned* bar;      // [n_teams * kBarStride] team barrier counters (zeroed per launch)
+  unsigned* abort;    // set when a barrier of this launch gave up (zeroed per launch)
+  int* err;           // sticky device error flag
+  unsigned spin_limit;
+};
+
+}  // namespace cbessfm
+
+struct cbessfm_plan {
+  cbessfm_link link;
+  cbessfm_subbands sb;
+  int steps;
+  int n_taps, tap_pad, n_chunks;
+  int N, Np, hop, log_np;
+  double step_km, rho;
+  int device;
+  int cu_count;
+  int threads;
+  int team_capacity;  // teams whose workgroups can all be resident at once
+  // device memory
+  double* d_phase;    // [N] 2 pi^2 beta2 f^2 per km, subband order (FP64)
+  float2* d_h;        // [3][N]
+  float2* d_tw;       // [N']
+  float2* d_poly;     // [n_sb][N']
+  float* d_c;         // [steps][n_sb][n_sb][n_taps] as given
+  float* d_cpad;      // padded copy used by the kernels
+  double* d_rho;      // current split ratio
+  float2* d_xspec;
+  float* d_xp;
+  unsigned* d_bar;
+  int* d_err;
+  float2 wsb[cbessfm::kMaxSubbands];
+};
+
+namespace cbessfm {
+// kernels.hip
+int launch_forward(cbessfm_plan_t* p, const void* in, void* out, long long T, int batch, hipStream_t s);
+int launch_tables(cbessfm_plan_t* p, hipStream_t s);
+int launch_pad_coeffs(cbessfm_plan_t* p, const float* src, hipStream_t s);
+int launch_copy_rho(cbessfm_plan_t* p, const float* src, hipStream_t s);
+int occupancy_per_cu(int log_np, int* blocks);
+int threads_for(int log_np);
+}  // namespace cbessfm

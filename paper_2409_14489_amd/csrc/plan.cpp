@@ -1,0 +1,383 @@
+// Host side of libcbessfm: argument validation, plan construction (FP64
+// tables rounded once to FP32), analytic coefficients, error reporting.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "cbessfm.h"
+#include "internal.hpp"
+
+using cbessfm::kMaxSubbands;
+using cbessfm::kMaxTaps;
+using cbessfm::kTapChunk;
+using cd = std::complex<double>;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int log2i(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+int check_link(const cbessfm_link* link) {
+  if (!link) return CBESSFM_EINVAL;
+  if (link->n_spans < 1 || !(link->span_km > 0.0) || !std::isfinite(link->span_km)) return CBESSFM_EINVAL;
+  if (!(link->sample_rate_hz > 0.0) || !std::isfinite(link->sample_rate_hz)) return CBESSFM_EINVAL;
+  if (!std::isfinite(link->beta2_ps2_km) || !std::isfinite(link->alpha_db_km) ||
+      !std::isfinite(link->gamma_w_km) || link->alpha_db_km < 0.0)
+    return CBESSFM_EINVAL;
+  return CBESSFM_OK;
+}
+
+int check_layout(const cbessfm_subbands* sb) {
+  if (!sb) return CBESSFM_EINVAL;
+  if (sb->n_sb < 1 || sb->n_sb > kMaxSubbands) return CBESSFM_EINVAL;
+  if (!is_pow2(sb->block_sb) || sb->block_sb < 256 || sb->block_sb > 8192) return CBESSFM_EUNSUPPORTED;
+  const long long n = (long long)sb->n_sb * sb->block_sb;
+  if (sb->overlap < 0 || sb->overlap >= n || (sb->overlap & 1)) return CBESSFM_EINVAL;
+  if (sb->boundary != 0 && sb->boundary != 1) return CBESSFM_EINVAL;
+  return CBESSFM_OK;
+}
+
+int check_taps(int n_taps, int grid_m, int block_sb) {
+  if (n_taps < 1 || (n_taps & 1) == 0) return CBESSFM_EINVAL;
+  if (n_taps > block_sb) return CBESSFM_EINVAL;
+  if (n_taps > kMaxTaps) return CBESSFM_EUNSUPPORTED;
+  if (grid_m != 0 && (grid_m < n_taps || (grid_m & 1) == 0)) return CBESSFM_EINVAL;
+  return CBESSFM_OK;
+}
+
+// ---------------------------------------------------------------- analytic coefficients
+// Kernel of eq. (6) in the form of App. C (eq. kernel_b):
+//   K(b) = gamma int_{z_lo}^{z_hi} g(z) exp(-j 2 b (z - z0)) dz,
+// g(z) = exp(-alpha (z - position of the last amplifier)).  Each piece between
+// amplifiers integrates in closed form: exp(-(alpha + j 2 b) l) terms.
+cd step_kernel(double b, double z_lo, double z_hi, double z0, double alpha, double span, double gamma) {
+  const cd kappa(alpha, 2.0 * b);
+  cd acc(0.0, 0.0);
+  double a = z_lo;
+  const double tol = 1e-12 * std::max(1.0, std::fabs(z_hi));
+  while (a < z_hi - tol) {
+    const double amp = std::floor(a / span + 1e-12) * span;  // last amplifier
+    const double c = std::min(z_hi, amp + span);
+    const double len = c - a;
+    const cd x = kappa * len;
+    cd frac;  // (1 - exp(-kappa len)) / kappa
+    if (std::abs(x) < 1e-6)
+      frac = len * (1.0 - x / 2.0 + x * x / 6.0);
+    else
+      frac = (1.0 - std::exp(-x)) / kappa;
+    acc += std::exp(-alpha * (a - amp)) * std::exp(cd(0.0, -2.0 * b * (a - z0))) * frac;
+    a = c;
+  }
+  return gamma * acc;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cbessfm_strerror(int code) {
+  switch (code) {
+    case CBESSFM_OK: return "success";
+    case CBESSFM_EINVAL: return "invalid argument";
+    case CBESSFM_EUNSUPPORTED: return "unsupported size";
+    case CBESSFM_ENOMEM: return "out of memory";
+    case CBESSFM_EHIP: return "HIP runtime error";
+    case CBESSFM_ESYNC: return "device team barrier timed out";
+    case CBESSFM_EWORKSPACE: return "workspace too small";
+    default: return "unknown error";
+  }
+}
+
+int cbessfm_plan_check(const cbessfm_link* link, const cbessfm_subbands* sb, int32_t steps, double split_ratio,
+                       const cbessfm_coeffs* coeffs) {
+  int rc = check_link(link);
+  if (rc) return rc;
+  rc = check_layout(sb);
+  if (rc) return rc;
+  if (!coeffs) return CBESSFM_EINVAL;
+  rc = check_taps(coeffs->n_taps, coeffs->grid_m, sb->block_sb);
+  if (rc) return rc;
+  if (!(split_ratio >= 0.0 && split_ratio <= 1.0)) return CBESSFM_EINVAL;
+  if (steps < 1) return CBESSFM_EINVAL;
+  return CBESSFM_OK;
+}
+
+int cbessfm_analytic_coeffs(const cbessfm_link* link, const cbessfm_subbands* sb, int32_t steps,
+                            double split_ratio, int32_t n_taps, int32_t grid_m, double* out_host) {
+  int rc = check_link(link);
+  if (rc) return rc;
+  if (!sb || sb->n_sb < 1 || sb->n_sb > kMaxSubbands || !out_host) return CBESSFM_EINVAL;
+  if (n_taps < 1 || (n_taps & 1) == 0 || (grid_m != 0 && (grid_m < n_taps || (grid_m & 1) == 0)))
+    return CBESSFM_EINVAL;
+  if (!(split_ratio >= 0.0 && split_ratio <= 1.0) || steps < 1) return CBESSFM_EINVAL;
+  const int nsb = sb->n_sb;
+  const int m_grid = grid_m ? grid_m : n_taps;
+  const int half = m_grid / 2, nc = n_taps / 2;
+  const double alpha = link->alpha_db_km * std::log(10.0) / 10.0;  // power, 1/km
+  const double beta2 = link->beta2_ps2_km * 1e-24;                  // s^2/km
+  const double gamma = link->gamma_w_km * (link->manakov_8_9 ? 8.0 / 9.0 : 1.0);
+  const double step = link->span_km * link->n_spans / steps;
+  const double rp = link->sample_rate_hz / nsb;                      // subband rate R'
+  // phase factors exp(j 2 pi m d / M) for d = p - q in [-(M-1), M-1]
+  std::vector<cd> kgrid((size_t)m_grid * m_grid);
+  for (int s = 0; s < steps; ++s) {
+    const int j = steps - s;  // physical step undone by DBP step s (1-based)
+    const double z_lo = (j - 1) * step, z_hi = j * step, z0 = z_lo + split_ratio * step;
+    for (int i = 0; i < nsb; ++i)
+      for (int l = 0; l < nsb; ++l) {
+        const double f_il = (l - i) * rp;  // f_l - f_i for equally spaced subbands
+        for (int p = 0; p < m_grid; ++p)
+          for (int q = 0; q < m_grid; ++q) {
+            const double mu = f_il + (p - half) * rp / m_grid;
+            const double nu = f_il + (q - half) * rp / m_grid;
+            const double b = 2.0 * kPi * kPi * beta2 * nu * (mu - nu);
+            kgrid[(size_t)p * m_grid + q] = step_kernel(b, z_lo, z_hi, z0, alpha, link->span_km, gamma);
+          }
+        const double xpm = (i == l) ? 1.0 : 1.5;
+        for (int tau = 0; tau < n_taps; ++tau) {
+          const int m = tau - nc;
+          // c[m] = Re (1/M^2) sum_{p,q} K(mu_p, nu_q) exp(j 2 pi m (p - q) / M)
+          cd acc(0.0, 0.0);
+          for (int p = 0; p < m_grid; ++p) {
+            cd row(0.0, 0.0);
+            for (int q = 0; q < m_grid; ++q) {
+              const double ang = 2.0 * kPi * (double)m * (double)(p - q) / m_grid;
+              row += kgrid[(size_t)p * m_grid + q] * cd(std::cos(ang), std::sin(ang));
+            }
+            acc += row;
+          }
+          const double c = acc.real() / ((double)m_grid * m_grid);
+          out_host[(((size_t)s * nsb + i) * nsb + l) * n_taps + tau] = -xpm * c;
+        }
+      }
+  }
+  return CBESSFM_OK;
+}
+
+void cbessfm_destroy(cbessfm_plan_t* p) {
+  if (!p) return;
+  int prev = 0;
+  hipGetDevice(&prev);
+  hipSetDevice(p->device);
+  void* bufs[] = {p->d_phase, p->d_h, p->d_tw, p->d_poly, p->d_c, p->d_cpad, p->d_rho,
+                  p->d_xspec, p->d_xp, p->d_bar, p->d_err};
+  for (void* b : bufs)
+    if (b) hipFree(b);
+  hipSetDevice(prev);
+  delete p;
+}
+
+int cbessfm_plan(cbessfm_plan_t** out, const cbessfm_link* link, const cbessfm_subbands* sb, int32_t steps,
+                 double split_ratio, const cbessfm_coeffs* coeffs) {
+  if (!out) return CBESSFM_EINVAL;
+  *out = nullptr;
+  int rc = cbessfm_plan_check(link, sb, steps, split_ratio, coeffs);
+  if (rc) return rc;
+  cbessfm_plan_t* p = new (std::nothrow) cbessfm_plan_t();
+  if (!p) return CBESSFM_ENOMEM;
+  std::memset(p, 0, sizeof(*p));
+  p->link = *link;
+  p->sb = *sb;
+  p->steps = steps;
+  p->n_taps = coeffs->n_taps;
+  p->n_chunks = (coeffs->n_taps + kTapChunk - 1) / kTapChunk;
+  p->tap_pad = p->n_chunks * kTapChunk;
+  p->Np = sb->block_sb;
+  p->N = sb->n_sb * sb->block_sb;
+  p->hop = p->N - sb->overlap;
+  p->log_np = log2i(p->Np);
+  p->step_km = link->span_km * link->n_spans / steps;
+  p->rho = split_ratio;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return CBESSFM_EHIP;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, p->device) != hipSuccess) {
+    delete p;
+    return CBESSFM_EHIP;
+  }
+  p->cu_count = prop.multiProcessorCount;
+  p->threads = cbessfm::threads_for(p->log_np);
+  int per_cu = 0;
+  if (cbessfm::occupancy_per_cu(p->log_np, &per_cu) != CBESSFM_OK || per_cu < 1) {
+    delete p;
+    return CBESSFM_EHIP;
+  }
+  // teams are placed as groups of n_sb workgroups per XCD; keep the whole
+  // (padded) grid resident
+  const int capacity = per_cu * p->cu_count;
+  p->team_capacity = (capacity / (cbessfm::kXcds * sb->n_sb)) * cbessfm::kXcds;
+  if (p->team_capacity < 1) {
+    delete p;
+    return CBESSFM_EUNSUPPORTED;
+  }
+
+  const int N = p->N, Np = p->Np, nsb = sb->n_sb;
+  const size_t crows = (size_t)steps * nsb * nsb;
+  // ---- host tables in FP64
+  std::vector<double> phase(N);
+  const double beta2 = link->beta2_ps2_km * 1e-24;
+  for (int q = 0; q < N; ++q) {  // subband order: q' = i N' + j  <->  bin q' - N/2
+    const double f = (double)(q - N / 2) * link->sample_rate_hz / N;
+    phase[q] = 2.0 * kPi * kPi * beta2 * f * f;
+  }
+  std::vector<float2> tw(Np), poly((size_t)nsb * Np);
+  for (int n = 0; n < Np; ++n) {
+    const double a = -2.0 * kPi * n / Np;
+    tw[n] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+  for (int i = 0; i < nsb; ++i)
+    for (int k = 0; k < Np; ++k) {
+      const double a = -2.0 * kPi * (double)((long long)i * k % N) / N;
+      poly[(size_t)i * Np + k] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+  for (int a = 0; a < kMaxSubbands; ++a) {
+    const double ang = -2.0 * kPi * a / nsb;
+    p->wsb[a] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+  }
+  std::vector<float> c(crows * p->n_taps);
+  if (coeffs->c) {
+    std::memcpy(c.data(), coeffs->c, c.size() * sizeof(float));
+  } else {
+    std::vector<double> cd64(c.size());
+    rc = cbessfm_analytic_coeffs(link, sb, steps, split_ratio, p->n_taps, coeffs->grid_m, cd64.data());
+    if (rc) {
+      delete p;
+      return rc;
+    }
+    for (size_t k = 0; k < c.size(); ++k) c[k] = (float)cd64[k];
+  }
+
+  // ---- device memory
+  const size_t teams = (size_t)p->team_capacity;
+  bool ok = true;
+  auto alloc = [&](void** ptr, size_t bytes) {
+    if (ok && hipMalloc(ptr, bytes) != hipSuccess) ok = false;
+  };
+  alloc((void**)&p->d_phase, sizeof(double) * N);
+  alloc((void**)&p->d_h, sizeof(float2) * 3 * N);
+  alloc((void**)&p->d_tw, sizeof(float2) * Np);
+  alloc((void**)&p->d_poly, sizeof(float2) * nsb * Np);
+  alloc((void**)&p->d_c, sizeof(float) * crows * p->n_taps);
+  alloc((void**)&p->d_cpad, sizeof(float) * crows * p->tap_pad);
+  alloc((void**)&p->d_rho, sizeof(double));
+  alloc((void**)&p->d_xspec, sizeof(float2) * teams * 2 * nsb * 2 * Np);
+  alloc((void**)&p->d_xp, sizeof(float) * teams * 2 * nsb * Np);
+  alloc((void**)&p->d_bar, sizeof(unsigned) * (teams * cbessfm::kBarStride + 64));
+  alloc((void**)&p->d_err, sizeof(int));
+  if (!ok) {
+    cbessfm_destroy(p);
+    return CBESSFM_ENOMEM;
+  }
+  bool hip_ok = hipMemcpy(p->d_phase, phase.data(), sizeof(double) * N, hipMemcpyHostToDevice) == hipSuccess &&
+                hipMemcpy(p->d_tw, tw.data(), sizeof(float2) * Np, hipMemcpyHostToDevice) == hipSuccess &&
+                hipMemcpy(p->d_poly, poly.data(), sizeof(float2) * nsb * Np, hipMemcpyHostToDevice) == hipSuccess &&
+                hipMemcpy(p->d_c, c.data(), sizeof(float) * c.size(), hipMemcpyHostToDevice) == hipSuccess &&
+                hipMemcpy(p->d_rho, &split_ratio, sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+                hipMemset(p->d_err, 0, sizeof(int)) == hipSuccess &&
+                hipMemset(p->d_bar, 0, sizeof(unsigned) * (teams * cbessfm::kBarStride + 64)) == hipSuccess;
+  if (!hip_ok || cbessfm::launch_tables(p, nullptr) || cbessfm::launch_pad_coeffs(p, p->d_c, nullptr) ||
+      hipDeviceSynchronize() != hipSuccess) {
+    cbessfm_destroy(p);
+    return CBESSFM_EHIP;
+  }
+  *out = p;
+  return CBESSFM_OK;
+}
+
+int cbessfm_set_coeffs(cbessfm_plan_t* p, const float* dev_c, const float* dev_rho, void* stream) {
+  if (!p) return CBESSFM_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (dev_c) {
+    const size_t bytes = sizeof(float) * (size_t)p->steps * p->sb.n_sb * p->sb.n_sb * p->n_taps;
+    if (hipMemcpyAsync(p->d_c, dev_c, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) return CBESSFM_EHIP;
+    int rc = cbessfm::launch_pad_coeffs(p, p->d_c, s);
+    if (rc) return rc;
+  }
+  if (dev_rho) {
+    int rc = cbessfm::launch_copy_rho(p, dev_rho, s);
+    if (rc) return rc;
+    rc = cbessfm::launch_tables(p, s);
+    if (rc) return rc;
+  }
+  return CBESSFM_OK;
+}
+
+int cbessfm_set_split_ratio(cbessfm_plan_t* p, double split_ratio, void* stream) {
+  if (!p) return CBESSFM_EINVAL;
+  if (!(split_ratio >= 0.0 && split_ratio <= 1.0)) return CBESSFM_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  p->rho = split_ratio;
+  // the value is staged through the plan-owned host copy, so wait for it
+  if (hipMemcpyAsync(p->d_rho, &p->rho, sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+    return CBESSFM_EHIP;
+  int rc = cbessfm::launch_tables(p, s);
+  if (rc) return rc;
+  return hipStreamSynchronize(s) == hipSuccess ? CBESSFM_OK : CBESSFM_EHIP;
+}
+
+int cbessfm_run(cbessfm_plan_t* p, const void* field_in, void* field_out, int64_t T, int32_t batch,
+                void* stream) {
+  if (!p || !field_in || !field_out || T < 1 || batch < 1) return CBESSFM_EINVAL;
+  const char* a = static_cast<const char*>(field_in);
+  const char* b = static_cast<const char*>(field_out);
+  const long long bytes = (long long)batch * 2 * T * 8;
+  if (a < b + bytes && b < a + bytes) return CBESSFM_EINVAL;  // in and out must not overlap
+  return cbessfm::launch_forward(p, field_in, field_out, T, batch, static_cast<hipStream_t>(stream));
+}
+
+int cbessfm_plan_info(const cbessfm_plan_t* p, cbessfm_info* out) {
+  if (!p || !out) return CBESSFM_EINVAL;
+  out->n_sb = p->sb.n_sb;
+  out->block_sb = p->Np;
+  out->block = p->N;
+  out->overlap = p->sb.overlap;
+  out->hop = p->hop;
+  out->steps = p->steps;
+  out->n_taps = p->n_taps;
+  out->threads_per_group = p->threads;
+  out->team_capacity = p->team_capacity;
+  out->step_km = p->step_km;
+  out->split_ratio = p->rho;
+  return CBESSFM_OK;
+}
+
+int cbessfm_status(cbessfm_plan_t* p) {
+  if (!p) return CBESSFM_EINVAL;
+  if (hipSetDevice(p->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return CBESSFM_EHIP;
+  int err = 0;
+  if (hipMemcpy(&err, p->d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return CBESSFM_EHIP;
+  if (err && hipMemset(p->d_err, 0, sizeof(int)) != hipSuccess) return CBESSFM_EHIP;
+  return err;
+}
+
+int cbessfm_backward_workspace(const cbessfm_plan_t* p, int64_t T, int32_t batch, int32_t checkpoint_every,
+                               size_t* bytes) {
+  (void)checkpoint_every;
+  if (!p || !bytes || T < 1 || batch < 1) return CBESSFM_EINVAL;
+  *bytes = 0;
+  return CBESSFM_EUNSUPPORTED;
+}
+
+int cbessfm_backward(cbessfm_plan_t* p, const void* field_in, const void* grad_out, void* grad_in, float* grad_c,
+                     float* grad_rho, int64_t T, int32_t batch, int32_t checkpoint_every, void* workspace,
+                     size_t workspace_bytes, void* stream) {
+  (void)p, (void)field_in, (void)grad_out, (void)grad_in, (void)grad_c, (void)grad_rho, (void)T, (void)batch;
+  (void)checkpoint_every, (void)workspace, (void)workspace_bytes, (void)stream;
+  return CBESSFM_EUNSUPPORTED;
+}
+
+}  // extern "C"

@@ -1,0 +1,178 @@
+"""Python face of libcbessfm: a CB-ESSFM plan bound to device tensors.
+
+PyTorch supplies device memory and the current stream; every step of the
+backpropagation runs in the library's HIP kernels (see ``include/cbessfm.h``
+for the operation, Sec. III-A / III-C of the paper).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import Coeffs, Info, Link, Subbands, check, lib
+
+
+@dataclass
+class LinkSpec:
+    """Fibre link (Sec. IV-A); fields follow ``cbessfm_link``."""
+    alpha_db_km: float = 0.2
+    beta2_ps2_km: float = -21.7
+    gamma_w_km: float = 1.3
+    span_km: float = 80.0
+    n_spans: int = 1
+    sample_rate_hz: float = 64e9
+    manakov_8_9: bool = False
+
+    def c(self) -> Link:
+        return Link(self.alpha_db_km, self.beta2_ps2_km, self.gamma_w_km, self.span_km,
+                    int(self.n_spans), self.sample_rate_hz, int(bool(self.manakov_8_9)))
+
+    @property
+    def length_km(self) -> float:
+        return self.span_km * self.n_spans
+
+
+_BOUNDARY = {"circular": 0, "zero": 1}
+
+
+def _subbands(n_sb: int, block_sb: int, overlap: int, boundary: str) -> Subbands:
+    if boundary not in _BOUNDARY:
+        raise ValueError("boundary must be 'circular' or 'zero'")
+    return Subbands(int(n_sb), int(block_sb), int(overlap), _BOUNDARY[boundary])
+
+
+def _coeff_struct(coeffs, n_taps, grid_m):
+    if coeffs is None:
+        return Coeffs(int(n_taps), None, int(grid_m)), None
+    host = np.ascontiguousarray(np.asarray(coeffs, dtype=np.float32))
+    ptr = host.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    return Coeffs(int(host.shape[-1]), ptr, int(grid_m)), host
+
+
+def plan_check(link: LinkSpec, n_sb: int, block_sb: int, overlap: int, steps: int, split_ratio: float,
+               n_taps: int, boundary: str = "circular", grid_m: int = 0) -> int:
+    """Host-only validation (``cbessfm_plan_check``); returns the C error code."""
+    lk, sb = link.c(), _subbands(n_sb, block_sb, overlap, boundary)
+    co = Coeffs(int(n_taps), None, int(grid_m))
+    return lib.cbessfm_plan_check(ctypes.byref(lk), ctypes.byref(sb), int(steps), float(split_ratio),
+                                  ctypes.byref(co))
+
+
+def analytic_coeffs(link: LinkSpec, n_sb: int, steps: int, split_ratio: float, n_taps: int,
+                    grid_m: int = 0) -> np.ndarray:
+    """Applied analytic coefficients [steps][n_sb][n_sb][n_taps] in FP64 (host)."""
+    out = np.empty((steps, n_sb, n_sb, n_taps), dtype=np.float64)
+    lk = link.c()
+    sb = Subbands(int(n_sb), 256, 0, 0)
+    check(lib.cbessfm_analytic_coeffs(ctypes.byref(lk), ctypes.byref(sb), int(steps), float(split_ratio),
+                                      int(n_taps), int(grid_m),
+                                      out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+          "cbessfm_analytic_coeffs")
+    return out
+
+
+def _stream_ptr(stream=None) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """A CB-ESSFM plan on the current HIP device.
+
+    coeffs: applied coefficients [steps][n_sb][n_sb][n_taps] (rad/W, 3/2 and
+    DBP sign included), or None for the analytic ones (then ``n_taps`` is
+    required).
+    """
+
+    def __init__(self, link: LinkSpec, n_sb: int, block_sb: int, overlap: int, steps: int,
+                 split_ratio: float, coeffs=None, n_taps: int | None = None, grid_m: int = 0,
+                 boundary: str = "circular"):
+        if coeffs is None and n_taps is None:
+            raise ValueError("give coeffs or n_taps")
+        self.link = link
+        self.n_sb, self.block_sb, self.overlap, self.steps = int(n_sb), int(block_sb), int(overlap), int(steps)
+        self.boundary = boundary
+        lk, sb = link.c(), _subbands(n_sb, block_sb, overlap, boundary)
+        co, keep = _coeff_struct(coeffs, n_taps, grid_m)
+        self.n_taps = co.n_taps
+        handle = ctypes.c_void_p()
+        rc = lib.cbessfm_plan(ctypes.byref(handle), ctypes.byref(lk), ctypes.byref(sb), int(steps),
+                              float(split_ratio), ctypes.byref(co))
+        del keep
+        check(rc, "cbessfm_plan")
+        self._h = handle
+
+    # -------------------------------------------------------------- geometry
+    def info(self) -> Info:
+        out = Info()
+        check(lib.cbessfm_plan_info(self._h, ctypes.byref(out)), "cbessfm_plan_info")
+        return out
+
+    @property
+    def block(self) -> int:
+        return self.n_sb * self.block_sb
+
+    @property
+    def hop(self) -> int:
+        return self.block - self.overlap
+
+    def n_blocks(self, t_len: int) -> int:
+        return -(-t_len // self.hop)
+
+    # -------------------------------------------------------------- calls
+    @staticmethod
+    def _field(x: torch.Tensor) -> torch.Tensor:
+        if not (x.is_cuda and x.dtype == torch.complex64):
+            raise TypeError("field must be a complex64 CUDA tensor")
+        if x.dim() not in (2, 3) or x.shape[-2] != 2:
+            raise ValueError("field must have shape (2, T) or (B, 2, T)")
+        return x.contiguous()
+
+    def run(self, field_in: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        x = self._field(field_in)
+        bsz = 1 if x.dim() == 2 else x.shape[0]
+        t_len = x.shape[-1]
+        if out is None:
+            out = torch.empty_like(x)
+        elif out.shape != x.shape or out.dtype != x.dtype or not out.is_contiguous():
+            raise ValueError("out must be a contiguous complex64 tensor shaped like field_in")
+        check(lib.cbessfm_run(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                              int(t_len), int(bsz), _stream_ptr(stream)), "cbessfm_run")
+        return out
+
+    def set_coeffs(self, coeffs: torch.Tensor | None = None, rho: torch.Tensor | None = None, stream=None):
+        """Device-side update of coefficients (float32 [steps][n_sb][n_sb][n_taps]) and/or rho (float32 scalar)."""
+        cp = ctypes.c_void_p(0)
+        rp = ctypes.c_void_p(0)
+        if coeffs is not None:
+            if not (coeffs.is_cuda and coeffs.dtype == torch.float32 and coeffs.is_contiguous()):
+                raise TypeError("coeffs must be a contiguous float32 CUDA tensor")
+            if tuple(coeffs.shape) != (self.steps, self.n_sb, self.n_sb, self.n_taps):
+                raise ValueError("coeffs shape does not match the plan")
+            cp = ctypes.c_void_p(coeffs.data_ptr())
+        if rho is not None:
+            if not (rho.is_cuda and rho.dtype == torch.float32 and rho.numel() == 1):
+                raise TypeError("rho must be a one-element float32 CUDA tensor")
+            rp = ctypes.c_void_p(rho.data_ptr())
+        check(lib.cbessfm_set_coeffs(self._h, cp, rp, _stream_ptr(stream)), "cbessfm_set_coeffs")
+
+    def set_split_ratio(self, rho: float, stream=None):
+        check(lib.cbessfm_set_split_ratio(self._h, float(rho), _stream_ptr(stream)), "cbessfm_set_split_ratio")
+
+    def status(self) -> int:
+        return lib.cbessfm_status(self._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.cbessfm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
