@@ -154,7 +154,7 @@ __host__ __device__ constexpr int pad_f_size(int n) { return n + (n >> 4) + 1; }
 template <int N>
 struct FftShape {
   static_assert(N >= 256 && N <= 8192 && (N & (N - 1)) == 0, "N' must be a power of two in [256, 8192]");
-  static constexpr int RR = N >= 1024 ? 16 : N / 64;  // samples per thread per polarisation
+  static constexpr int RR = N >= 8192 ? 16 : (N >= 512 ? 8 : N / 64);  // samples per thread per polarisation
   static constexpr int NT = N / RR;                   // threads per workgroup
   static constexpr int radix(int p) {
     int rem = N;
@@ -184,30 +184,6 @@ struct FftShape {
   static constexpr int LDS_C = pad_c_size(N);  // float2 entries per exchange buffer
 };
 
-// Loads this thread's twiddles W_{L R}^{k m} (k = j mod L) for every pass >= 1
-// from the table tw[n] = exp(-j 2 pi n / N) (rounded from FP64 on the host).
-template <int N, int P>
-__device__ __forceinline__ void load_twiddles_pass(float2 (&tw)[FftShape<N>::TWC > 0 ? FftShape<N>::TWC : 1],
-                                                   const float2* __restrict__ table, int t) {
-  using S = FftShape<N>;
-  if constexpr (P < S::passes()) {
-    constexpr int R = S::radix(P), L = S::stride(P), NB = S::RR / R, SCALE = N / (L * R);
-#pragma unroll
-    for (int a = 0; a < NB; ++a) {
-      const int k = (t + S::NT * a) % L;
-#pragma unroll
-      for (int m = 1; m < R; ++m) tw[S::tw_offset(P) + a * (R - 1) + (m - 1)] = table[(k * m * SCALE) % N];
-    }
-    load_twiddles_pass<N, P + 1>(tw, table, t);
-  }
-}
-
-template <int N>
-__device__ __forceinline__ void load_twiddles(float2 (&tw)[FftShape<N>::TWC > 0 ? FftShape<N>::TWC : 1],
-                                              const float2* __restrict__ table, int t) {
-  load_twiddles_pass<N, 1>(tw, table, t);
-}
-
 // One Stockham pass p of radix R over both polarisations.
 //   FIRST: inputs come from the owned registers (positions t + NT o)
 //   LAST : outputs go to the owned registers
@@ -215,8 +191,7 @@ __device__ __forceinline__ void load_twiddles(float2 (&tw)[FftShape<N>::TWC > 0 
 template <int N, int P, bool INV>
 __device__ __forceinline__ void fft_pass(float2 (&x)[FftShape<N>::RR], float2 (&y)[FftShape<N>::RR],
                                          float2* __restrict__ lx, float2* __restrict__ ly,
-                                         const float2 (&tw)[FftShape<N>::TWC > 0 ? FftShape<N>::TWC : 1],
-                                         int t) {
+                                         const float2* __restrict__ twt, int t) {
   using S = FftShape<N>;
   constexpr int R = S::radix(P);
   constexpr int L = S::stride(P);
@@ -224,6 +199,16 @@ __device__ __forceinline__ void fft_pass(float2 (&x)[FftShape<N>::RR], float2 (&
   constexpr bool FIRST = (P == 0);
   constexpr bool LAST = (P == S::passes() - 1);
   constexpr int NR = N / R;
+  // twiddles W_{L R}^{k m} = table[k m N / (L R)], k = j mod L, issued first
+  float2 w[NB][R > 1 ? R - 1 : 1];
+  if constexpr (!FIRST) {
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      const int k = (t + S::NT * a) % L;
+#pragma unroll
+      for (int m = 1; m < R; ++m) w[a][m - 1] = twt[(k * m * (N / (L * R))) % N];
+    }
+  }
   // gather inputs: vx[a][m] = x[j + m N/R], j = t + NT a
   float2 vx[NB][R], vy[NB][R];
 #pragma unroll
@@ -245,9 +230,8 @@ __device__ __forceinline__ void fft_pass(float2 (&x)[FftShape<N>::RR], float2 (&
     if constexpr (!FIRST) {
 #pragma unroll
       for (int m = 1; m < R; ++m) {
-        const float2 w = tw[S::tw_offset(P) + a * (R - 1) + (m - 1)];
-        vx[a][m] = twmul<INV>(vx[a][m], w);
-        vy[a][m] = twmul<INV>(vy[a][m], w);
+        vx[a][m] = twmul<INV>(vx[a][m], w[a][m - 1]);
+        vy[a][m] = twmul<INV>(vy[a][m], w[a][m - 1]);
       }
     }
     dft<R, INV>(vx[a]);
@@ -274,24 +258,22 @@ __device__ __forceinline__ void fft_pass(float2 (&x)[FftShape<N>::RR], float2 (&
 
 template <int N, int P, bool INV>
 __device__ __forceinline__ void fft_passes(float2 (&x)[FftShape<N>::RR], float2 (&y)[FftShape<N>::RR],
-                                           float2* lx, float2* ly,
-                                           const float2 (&tw)[FftShape<N>::TWC > 0 ? FftShape<N>::TWC : 1],
-                                           int t) {
+                                           float2* lx, float2* ly, const float2* twt, int t) {
   if constexpr (P < FftShape<N>::passes()) {
-    fft_pass<N, P, INV>(x, y, lx, ly, tw, t);
-    fft_passes<N, P + 1, INV>(x, y, lx, ly, tw, t);
+    fft_pass<N, P, INV>(x, y, lx, ly, twt, t);
+    fft_passes<N, P + 1, INV>(x, y, lx, ly, twt, t);
   }
 }
 
 // Unnormalised size-N DFT (INV = false: exp(-j...), INV = true: exp(+j...))
-// of the two owned register sets.  Starts with a barrier so that earlier LDS
+// of the two owned register sets; twt[n] = exp(-j 2 pi n / N) (FP64 values
+// rounded once, read through the L1/L2 caches at the start of each pass).  Starts with a barrier so that earlier LDS
 // readers are done before the first pass overwrites the exchange buffers.
 template <int N, bool INV>
 __device__ __forceinline__ void fft(float2 (&x)[FftShape<N>::RR], float2 (&y)[FftShape<N>::RR],
-                                    float2* lx, float2* ly,
-                                    const float2 (&tw)[FftShape<N>::TWC > 0 ? FftShape<N>::TWC : 1], int t) {
+                                    float2* lx, float2* ly, const float2* twt, int t) {
   __syncthreads();
-  fft_passes<N, 0, INV>(x, y, lx, ly, tw, t);
+  fft_passes<N, 0, INV>(x, y, lx, ly, twt, t);
 }
 
 }  // namespace cbessfm

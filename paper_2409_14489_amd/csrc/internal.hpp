@@ -12,7 +12,6 @@ namespace cbessfm {
 constexpr int kMaxSubbands = 8;
 constexpr int kTapChunk = 8;          // FIR taps are processed in chunks of 8
 constexpr int kMaxTaps = 255;
-constexpr int kBarStride = 64;        // uint32 words between team barrier counters (256 B)
 constexpr int kXcds = 8;              // MI355X: 8 accelerator complex dies, round-robin dispatch
 
 // Device tables of one plan (all FP32 values are FP64 results rounded once).
@@ -26,22 +25,26 @@ struct Tables {
   float2 wsb[kMaxSubbands];  // exp(-j 2 pi a / n_sb)
 };
 
+struct XchgCtl {
+  unsigned* abort;      // sticky: some exchange wait of this plan gave up
+  int* err;             // sticky error code for cbessfm_status()
+  unsigned spin_limit;  // polls before a wait gives up
+};
+
 // Everything a forward launch needs.
 struct FwdArgs {
   const float2* in;   // [batch][2][T]
   float2* out;        // [batch][2][T]
-  long long T;
+  int T;
   int n_items;        // batch * blocks per instance
   int nblk;           // overlap-and-save blocks per instance
   int n_sb, steps, n_chunks, nc, n_ov, hop, boundary;
   int n_teams;        // persistent teams of n_sb workgroups
+  unsigned tag_base;  // first exchange-round tag of this launch
   Tables tab;
-  float2* xspec;      // [n_teams][2 slots][n_sb][2 pol][N']   subband spectra exchange
-  float* xp;          // [n_teams][2 slots][n_sb][N']          intensity exchange
-  unsigned* bar;      // [n_teams * kBarStride] team barrier counters (zeroed per launch)
-  unsigned* abort;    // set when a barrier of this launch gave up (zeroed per launch)
-  int* err;           // sticky device error flag
-  unsigned spin_limit;
+  uint64_t* xspec;    // [team_capacity][2 slots][n_sb][4 comps][N']  tagged spectra
+  uint64_t* xp;       // [team_capacity][2 slots][n_sb][N']           tagged intensities
+  XchgCtl ctl;
 };
 
 }  // namespace cbessfm
@@ -65,15 +68,17 @@ struct cbessfm_plan {
   float* d_c;         // [steps][n_sb][n_sb][n_taps] as given
   float* d_cpad;      // padded copy used by the kernels
   double* d_rho;      // current split ratio
-  float2* d_xspec;
-  float* d_xp;
-  unsigned* d_bar;
+  uint64_t* d_xspec;  // tagged exchange words
+  uint64_t* d_xp;
+  unsigned* d_abort;  // sticky exchange-timeout word
   int* d_err;
+  unsigned next_tag;  // next unused exchange-round tag (host copy)
   float2 wsb[cbessfm::kMaxSubbands];
 };
 
 namespace cbessfm {
 // kernels.hip
+unsigned take_tags(cbessfm_plan_t* p, unsigned rounds, hipStream_t s);
 int launch_forward(cbessfm_plan_t* p, const void* in, void* out, long long T, int batch, hipStream_t s);
 int launch_tables(cbessfm_plan_t* p, hipStream_t s);
 int launch_pad_coeffs(cbessfm_plan_t* p, const float* src, hipStream_t s);

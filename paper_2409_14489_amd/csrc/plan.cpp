@@ -83,7 +83,32 @@ cd step_kernel(double b, double z_lo, double z_hi, double z0, double alpha, doub
   return gamma * acc;
 }
 
+size_t xspec_bytes(const cbessfm_plan_t* p) {
+  return sizeof(uint64_t) * (size_t)p->team_capacity * 2 * p->sb.n_sb * 4 * p->Np;
+}
+size_t xp_bytes(const cbessfm_plan_t* p) {
+  return sizeof(uint64_t) * (size_t)p->team_capacity * 2 * p->sb.n_sb * p->Np;
+}
+
 }  // namespace
+
+namespace cbessfm {
+// Reserves `rounds` consecutive exchange tags for one launch.  Tags only grow,
+// so no word left by an earlier launch can match; when the 32-bit range runs
+// out every exchange word is cleared (stream-ordered) and numbering restarts.
+unsigned take_tags(cbessfm_plan_t* p, unsigned rounds, hipStream_t s) {
+  if (rounds == 0) rounds = 1;
+  if ((unsigned long long)p->next_tag + rounds >= 0xFFFFFF00ull) {
+    if (hipMemsetAsync(p->d_xspec, 0, xspec_bytes(p), s) != hipSuccess ||
+        hipMemsetAsync(p->d_xp, 0, xp_bytes(p), s) != hipSuccess)
+      return 0u;
+    p->next_tag = 1;
+  }
+  const unsigned base = p->next_tag;
+  p->next_tag += rounds;
+  return base;
+}
+}  // namespace cbessfm
 
 extern "C" {
 
@@ -172,7 +197,7 @@ void cbessfm_destroy(cbessfm_plan_t* p) {
   hipGetDevice(&prev);
   hipSetDevice(p->device);
   void* bufs[] = {p->d_phase, p->d_h, p->d_tw, p->d_poly, p->d_c, p->d_cpad, p->d_rho,
-                  p->d_xspec, p->d_xp, p->d_bar, p->d_err};
+                  p->d_xspec, p->d_xp, p->d_abort, p->d_err};
   for (void* b : bufs)
     if (b) hipFree(b);
   hipSetDevice(prev);
@@ -274,9 +299,9 @@ int cbessfm_plan(cbessfm_plan_t** out, const cbessfm_link* link, const cbessfm_s
   alloc((void**)&p->d_c, sizeof(float) * crows * p->n_taps);
   alloc((void**)&p->d_cpad, sizeof(float) * crows * p->tap_pad);
   alloc((void**)&p->d_rho, sizeof(double));
-  alloc((void**)&p->d_xspec, sizeof(float2) * teams * 2 * nsb * 2 * Np);
-  alloc((void**)&p->d_xp, sizeof(float) * teams * 2 * nsb * Np);
-  alloc((void**)&p->d_bar, sizeof(unsigned) * (teams * cbessfm::kBarStride + 64));
+  alloc((void**)&p->d_xspec, xspec_bytes(p));
+  alloc((void**)&p->d_xp, xp_bytes(p));
+  alloc((void**)&p->d_abort, sizeof(unsigned));
   alloc((void**)&p->d_err, sizeof(int));
   if (!ok) {
     cbessfm_destroy(p);
@@ -288,7 +313,10 @@ int cbessfm_plan(cbessfm_plan_t** out, const cbessfm_link* link, const cbessfm_s
                 hipMemcpy(p->d_c, c.data(), sizeof(float) * c.size(), hipMemcpyHostToDevice) == hipSuccess &&
                 hipMemcpy(p->d_rho, &split_ratio, sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
                 hipMemset(p->d_err, 0, sizeof(int)) == hipSuccess &&
-                hipMemset(p->d_bar, 0, sizeof(unsigned) * (teams * cbessfm::kBarStride + 64)) == hipSuccess;
+                hipMemset(p->d_abort, 0, sizeof(unsigned)) == hipSuccess &&
+                hipMemset(p->d_xspec, 0, xspec_bytes(p)) == hipSuccess &&
+                hipMemset(p->d_xp, 0, xp_bytes(p)) == hipSuccess;
+  p->next_tag = 1;
   if (!hip_ok || cbessfm::launch_tables(p, nullptr) || cbessfm::launch_pad_coeffs(p, p->d_c, nullptr) ||
       hipDeviceSynchronize() != hipSuccess) {
     cbessfm_destroy(p);
@@ -360,7 +388,11 @@ int cbessfm_status(cbessfm_plan_t* p) {
   if (hipSetDevice(p->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return CBESSFM_EHIP;
   int err = 0;
   if (hipMemcpy(&err, p->d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return CBESSFM_EHIP;
-  if (err && hipMemset(p->d_err, 0, sizeof(int)) != hipSuccess) return CBESSFM_EHIP;
+  if (err) {  // an exchange wait gave up: clear the sticky words
+    if (hipMemset(p->d_err, 0, sizeof(int)) != hipSuccess ||
+        hipMemset(p->d_abort, 0, sizeof(unsigned)) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+      return CBESSFM_EHIP;
+  }
   return err;
 }
 

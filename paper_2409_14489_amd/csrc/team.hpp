@@ -1,0 +1,142 @@
+// Team-level helpers shared by the forward and adjoint kernels: the tagged
+// exchange between the workgroups of a team, and the overlap-and-save framing.
+//
+// Exchange protocol.  Every exchanged float travels in its own 64-bit word
+// whose high half is a round tag; words are written and read with relaxed
+// device-scope atomics (single-copy atomic, coherent across the XCDs' L2s).
+// A reader polls a word until it carries the tag of the round it needs, so it
+// can never consume stale data, and no cache write-back / invalidate fences
+// are needed.  Tags grow monotonically across rounds and launches.
+//
+// Reuse of a buffer slot is safe when two uses of the same slot are separated
+// by at least one other all-to-all round: a member writes round r + 1 only
+// after it has consumed round r, so a member that has consumed round r + 1 from
+// everybody knows that everybody is done reading round r.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft_lds.hpp"
+#include "internal.hpp"
+
+namespace cbessfm {
+
+// The thread index, hidden from the optimiser so that index arithmetic derived
+// from it is recomputed where it is used instead of being hoisted into
+// long-lived registers.
+__device__ __forceinline__ int opaque_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
+__device__ __forceinline__ void xput(uint64_t* dst, float v, unsigned tag) {
+  const uint64_t w = ((uint64_t)tag << 32) | (uint64_t)__float_as_uint(v);
+  __hip_atomic_store(dst, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t xload(const uint64_t* src) {
+  return __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Issues the CNT loads row[t + stride * o].
+template <int CNT>
+__device__ __forceinline__ void xissue(const uint64_t* row, int t, int stride, uint64_t (&w)[CNT]) {
+#pragma unroll
+  for (int o = 0; o < CNT; ++o) w[o] = xload(row + t + stride * o);
+}
+
+// Re-polls every word (straight-line code), keeping the ones that already
+// carry `tag`.
+template <int O, int CNT>
+__device__ __forceinline__ void repoll(const uint64_t* row, int t, int stride, unsigned tag, uint64_t (&w)[CNT]) {
+  if constexpr (O < CNT) {
+    const uint64_t nw = xload(row + t + stride * O);
+    w[O] = ((unsigned)(w[O] >> 32) == tag) ? w[O] : nw;
+    repoll<O + 1, CNT>(row, t, stride, tag, w);
+  }
+}
+
+// Completes reads started with xissue(): re-polls the words that do not yet
+// carry `tag` until all do, then returns the payloads.  Bounded: on timeout
+// the sticky abort word and the error flag are set and every later wait falls
+// through (results are then invalid until cbessfm_status() clears the flag).
+template <int CNT>
+__device__ __forceinline__ void xcomplete(const uint64_t* row, int t, int stride, unsigned tag, const XchgCtl& c,
+                                          uint64_t (&w)[CNT], float (&v)[CNT]) {
+  unsigned n = 0;
+  while (true) {
+    unsigned bad = 0u;
+#pragma unroll
+    for (int o = 0; o < CNT; ++o) bad |= (unsigned)(w[o] >> 32) ^ tag;
+    if (bad == 0u) break;
+    if (__hip_atomic_load(c.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+    if (++n > c.spin_limit) {
+      __hip_atomic_store(c.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(c.err, (int)CBESSFM_ESYNC, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    repoll<0, CNT>(row, t, stride, tag, w);
+  }
+#pragma unroll
+  for (int o = 0; o < CNT; ++o) v[o] = __uint_as_float((unsigned)w[o]);
+}
+
+// Reads the CNT words row[t + stride * o] of round `tag`.
+template <int CNT>
+__device__ __forceinline__ void xget(const uint64_t* row, int t, int stride, unsigned tag, const XchgCtl& c,
+                                     float (&v)[CNT]) {
+  uint64_t w[CNT];
+  xissue<CNT>(row, t, stride, w);
+  xcomplete<CNT>(row, t, stride, tag, c, w, v);
+}
+
+// Position in [0, T) of block sample n, or -1 for a zero.  `first` is the
+// position of sample 0: reduced mod T for the circular boundary (a single
+// subtraction then wraps unless the sequence is shorter than the block), raw
+// for the zero boundary.
+__device__ __forceinline__ int frame_pos(int first, int n, int T, int boundary, bool short_seq) {
+  const int pos = first + n;
+  if (boundary == 0) {
+    if (short_seq) return pos % T;
+    return pos >= T ? pos - T : pos;
+  }
+  return (pos < 0 || pos >= T) ? -1 : pos;
+}
+
+__device__ __forceinline__ int frame_first(int blk, int hop, int n_ov, int T, int boundary) {
+  int first = blk * hop - n_ov / 2;
+  if (boundary == 0) first = ((first % T) + T) % T;
+  return first;
+}
+
+// LDS of the nonlinear stage (aliases the FFT exchange buffers): two rows of
+// circularly extended intensities and one row of phases, in floats.
+template <int N>
+struct NlprLds {
+  static constexpr int PB = pad_f_size(N + kMaxTaps + 2 * kTapChunk);
+  static constexpr int TH = pad_f_size(N);
+  static constexpr int FLOATS = 2 * PB + TH;
+};
+template <int N>
+constexpr int lds_floats() {
+  return 4 * FftShape<N>::LDS_C > NlprLds<N>::FLOATS ? 4 * FftShape<N>::LDS_C : NlprLds<N>::FLOATS;
+}
+
+// Writes values held at positions t + NT o (o < RR) into a circularly extended
+// LDS row: row[pad_f(k + hl)] = v[k], plus the wrapped copies for the left
+// halo (hl samples) and the right halo (hr samples).
+template <int N, int RR, int NT>
+__device__ __forceinline__ void stage_row(float* row, const float (&v)[RR], int t, int hl, int hr) {
+#pragma unroll
+  for (int o = 0; o < RR; ++o) {
+    const int k = t + NT * o;
+    row[pad_f(k + hl)] = v[o];
+    if (k >= N - hl) row[pad_f(k - N + hl)] = v[o];
+    if (k < hr) row[pad_f(k + N + hl)] = v[o];
+  }
+}
+
+}  // namespace cbessfm
