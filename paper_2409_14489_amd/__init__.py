@@ -3,7 +3,22 @@
 The operation and its C ABI are described in ``include/cbessfm.h``.  This
 package is a thin binding: PyTorch provides device memory and streams, the
 library ``libcbessfm.so`` (built in-tree by ``paper_2409_14489_amd.build``)
-does all of the arithmetic.
+does all of the arithmetic.  The public names are resolved on first use, so
+the build module can be imported before the library exists; using any of
+them without the library raises ImportError.
 """
-from .plan import LinkSpec, Plan, analytic_coeffs, plan_check  # noqa: F401
-from ._lib import CbessfmError, EXPORTED, LIB_PATH  # noqa: F401
+_PUBLIC = {
+    "LinkSpec": "plan", "Plan": "plan", "analytic_coeffs": "plan", "plan_check": "plan",
+    "CbessfmError": "_lib", "EXPORTED": "_lib", "LIB_PATH": "_lib",
+    "CBESSFMFunction": "autograd", "cbessfm": "autograd",
+}
+
+__all__ = sorted(_PUBLIC)
+
+
+def __getattr__(name):
+    mod = _PUBLIC.get(name)
+    if mod is None:
+        raise AttributeError(f"module {__name__!r} has no attribute {name!r}")
+    import importlib
+    return getattr(importlib.import_module(f"{__name__}.{mod}"), name)

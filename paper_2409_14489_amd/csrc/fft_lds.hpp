@@ -34,15 +34,29 @@ __device__ __forceinline__ float2 twmul(float2 a, float2 w) {  // a * w (fwd) or
   return INV ? cmulc(a, w) : cmul(a, w);
 }
 
-// cos / sin of 2 pi k / 16
+// cos / sin of 2 pi k / 16 split into an FP32 leading part and an FP32
+// remainder.  Every leading pair has |w| slightly below 1; since every
+// butterfly reuses the same constants, that shortfall would compound into a
+// systematic loss of amplitude over the many transforms of a step loop, so
+// the products below add the remainder term with an FMA.
 __host__ __device__ constexpr float cos16(int k) {
-  constexpr float c[16] = {1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f,
-                           0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f,
-                           -1.0f, -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508977f,
-                           0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f};
+  constexpr float c[16] = {1.0f, 0.92387950420379638671875f, 0.707106769084930419921875f,
+                           0.3826834261417388916015625f, 0.0f, -0.3826834261417388916015625f,
+                           -0.707106769084930419921875f, -0.92387950420379638671875f, -1.0f,
+                           -0.92387950420379638671875f, -0.707106769084930419921875f,
+                           -0.3826834261417388916015625f, 0.0f, 0.3826834261417388916015625f,
+                           0.707106769084930419921875f, 0.92387950420379638671875f};
+  return c[k & 15];
+}
+__host__ __device__ constexpr float cos16_lo(int k) {
+  constexpr float c[16] = {0.0f, 2.830748968563057e-08f, 1.2101617485882343e-08f, 6.2233507236442165e-09f,
+                           0.0f, -6.2233507236442165e-09f, -1.2101617485882343e-08f, -2.830748968563057e-08f,
+                           0.0f, -2.830748968563057e-08f, -1.2101617485882343e-08f, -6.2233507236442165e-09f,
+                           0.0f, 6.2233507236442165e-09f, 1.2101617485882343e-08f, 2.830748968563057e-08f};
   return c[k & 15];
 }
 __host__ __device__ constexpr float sin16(int k) { return cos16(k + 12); }
+__host__ __device__ constexpr float sin16_lo(int k) { return cos16_lo(k + 12); }
 
 // a * exp(-+ j 2 pi K / 16): '-' forward, '+' inverse
 template <int K, bool INV>
@@ -57,9 +71,12 @@ __device__ __forceinline__ float2 w16(float2 a) {
   } else if constexpr (k == 12) {
     return mul_mj<!INV>(a);
   } else {
-    constexpr float c = cos16(k), s = sin16(k);
-    if constexpr (!INV) return make_float2(a.x * c + a.y * s, a.y * c - a.x * s);
-    else return make_float2(a.x * c - a.y * s, a.y * c + a.x * s);
+    constexpr float c = cos16(k), s = sin16(k), cl = cos16_lo(k), sl = sin16_lo(k);
+    // forward: (x c + y s, y c - x s); inverse: (x c - y s, y c + x s)
+    const float ss = INV ? -s : s, ssl = INV ? -sl : sl;
+    const float re_lo = fmaf(a.x, cl, a.y * ssl);
+    const float im_lo = fmaf(a.y, cl, -a.x * ssl);
+    return make_float2(fmaf(a.x, c, fmaf(a.y, ss, re_lo)), fmaf(a.y, c, fmaf(-a.x, ss, im_lo)));
   }
 }
 

@@ -273,6 +273,25 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void fwd_kernel(FwdArgs 
 }
 
 // ------------------------------------------------------------------ tables
+// FP32 rounding of (c, s) keeping the magnitude (see round_pair in plan.cpp).
+__device__ float2 round_pair_dev(double c, double s) {
+  const float c0 = (float)c, s0 = (float)s;
+  const float c1 = (double)c0 < c ? nextafterf(c0, 2.0f) : nextafterf(c0, -2.0f);
+  const float s1 = (double)s0 < s ? nextafterf(s0, 2.0f) : nextafterf(s0, -2.0f);
+  const double target = c * c + s * s;
+  float2 best = make_float2(c0, s0);
+  double err = fabs((double)c0 * c0 + (double)s0 * s0 - target);
+  const float2 cand[3] = {make_float2(c0, s1), make_float2(c1, s0), make_float2(c1, s1)};
+  for (int i = 0; i < 3; ++i) {
+    const double e = fabs((double)cand[i].x * cand[i].x + (double)cand[i].y * cand[i].y - target);
+    if (e < err) {
+      err = e;
+      best = cand[i];
+    }
+  }
+  return best;
+}
+
 // h tables from the FP64 phase-per-km table and the current split ratio.
 __global__ void tables_kernel(const double* __restrict__ phase, const double* __restrict__ rho_p, double L,
                               double inv_n, double inv_np, int n, float2* __restrict__ h) {
@@ -282,11 +301,11 @@ __global__ void tables_kernel(const double* __restrict__ phase, const double* __
   const double ph = phase[q];
   double s, c;
   sincos(ph * (1.0 - rho) * L, &s, &c);
-  h[q] = make_float2((float)(c * inv_n), (float)(s * inv_n));
+  h[q] = round_pair_dev(c * inv_n, s * inv_n);
   sincos(ph * L, &s, &c);
-  h[n + q] = make_float2((float)(c * inv_np), (float)(s * inv_np));
+  h[n + q] = round_pair_dev(c * inv_np, s * inv_np);
   sincos(ph * rho * L, &s, &c);
-  h[2 * n + q] = make_float2((float)(c * inv_np), (float)(s * inv_np));
+  h[2 * n + q] = round_pair_dev(c * inv_np, s * inv_np);
 }
 
 __global__ void pad_coeffs_kernel(const float* __restrict__ src, float* __restrict__ dst, int rows, int n_taps,

@@ -83,6 +83,35 @@ cd step_kernel(double b, double z_lo, double z_hi, double z0, double alpha, doub
   return gamma * acc;
 }
 
+}  // namespace
+
+namespace cbessfm {
+// FP32 rounding of (c, s) that keeps the magnitude: of the (at most) four
+// pairs of FP32 neighbours of c and s, the one whose squared magnitude is
+// closest to c^2 + s^2.  Unit-magnitude tables reused by every transform and
+// step would otherwise bias the signal amplitude.
+float2 round_pair(double c, double s) {
+  const float c0 = (float)c, s0 = (float)s;
+  const float cs[2] = {c0, (double)c0 < c ? std::nextafter(c0, 2.0f) : std::nextafter(c0, -2.0f)};
+  const float ss[2] = {s0, (double)s0 < s ? std::nextafter(s0, 2.0f) : std::nextafter(s0, -2.0f)};
+  const double target = c * c + s * s;
+  float2 best = make_float2(c0, s0);
+  double err = 1e300;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      const double m = (double)cs[i] * cs[i] + (double)ss[j] * ss[j];
+      const double e = std::fabs(m - target);
+      if (e < err) {
+        err = e;
+        best = make_float2(cs[i], ss[j]);
+      }
+    }
+  return best;
+}
+}  // namespace cbessfm
+
+namespace {
+
 size_t xspec_bytes(const cbessfm_plan_t* p) {
   return sizeof(uint64_t) * (size_t)p->team_capacity * 2 * p->sb.n_sb * 4 * p->Np;
 }
@@ -262,16 +291,16 @@ int cbessfm_plan(cbessfm_plan_t** out, const cbessfm_link* link, const cbessfm_s
   std::vector<float2> tw(Np), poly((size_t)nsb * Np);
   for (int n = 0; n < Np; ++n) {
     const double a = -2.0 * kPi * n / Np;
-    tw[n] = make_float2((float)std::cos(a), (float)std::sin(a));
+    tw[n] = cbessfm::round_pair(std::cos(a), std::sin(a));
   }
   for (int i = 0; i < nsb; ++i)
     for (int k = 0; k < Np; ++k) {
       const double a = -2.0 * kPi * (double)((long long)i * k % N) / N;
-      poly[(size_t)i * Np + k] = make_float2((float)std::cos(a), (float)std::sin(a));
+      poly[(size_t)i * Np + k] = cbessfm::round_pair(std::cos(a), std::sin(a));
     }
   for (int a = 0; a < kMaxSubbands; ++a) {
     const double ang = -2.0 * kPi * a / nsb;
-    p->wsb[a] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    p->wsb[a] = cbessfm::round_pair(std::cos(ang), std::sin(ang));
   }
   std::vector<float> c(crows * p->n_taps);
   if (coeffs->c) {
