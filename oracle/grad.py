@@ -24,17 +24,22 @@ def _demux_index(plan: OraclePlan) -> np.ndarray:
     return np.stack([(-n // 2 + i * nsub + nsub // 2 + delta) % n for i in range(plan.n_sb)])
 
 
-def forward_torch(field_in: torch.Tensor, coeffs: torch.Tensor, rho: torch.Tensor,
-                  plan: OraclePlan) -> torch.Tensor:
-    """Same map as ``oracle.cbessfm.run`` for one instance (2, T), in torch FP64."""
+def forward_torch(field_in: torch.Tensor, coeffs: torch.Tensor, rho, plan: OraclePlan) -> torch.Tensor:
+    """Same map as ``oracle.cbessfm.run`` for one instance (2, T), in torch FP64.
+
+    ``rho`` is a scalar tensor, or a pair (rho of the first GVD, rho of the
+    last GVD) so that the two places where the split ratio enters
+    (Sec. III-C) can be differentiated separately.
+    """
+    rho_first, rho_last = (rho, rho) if not isinstance(rho, (tuple, list)) else rho
     t_len = field_in.shape[-1]
     n, nsub, nsb = plan.n_block, plan.n_sub, plan.n_sb
     L = plan.step_km
     f = torch.from_numpy(bin_frequencies(plan))                       # (N_sb, N')
     ph = 2.0 * np.pi ** 2 * plan.beta2_s2_km * f * f                  # per km
-    h_first = torch.exp(1j * ph * ((1.0 - rho) * L))
+    h_first = torch.exp(1j * ph * ((1.0 - rho_first) * L))
     h_mid = torch.exp(1j * ph * L)
-    h_last = torch.exp(1j * ph * (rho * L))
+    h_last = torch.exp(1j * ph * (rho_last * L))
     qidx = torch.from_numpy(_demux_index(plan))
     ntap = coeffs.shape[-1]
     nc = ntap // 2
@@ -71,11 +76,13 @@ def forward_torch(field_in: torch.Tensor, coeffs: torch.Tensor, rho: torch.Tenso
     return torch.cat(pieces, dim=-1)
 
 
-def vjp(field_in: np.ndarray, plan: OraclePlan, grad_out: np.ndarray):
+def vjp(field_in: np.ndarray, plan: OraclePlan, grad_out: np.ndarray, rho_parts: bool = False):
     """(dL/dfield_in, dL/dC, dL/drho) for L = Re sum conj(G) * out.
 
     field_in / grad_out: (2, T) or (B, 2, T); C and rho gradients are summed
-    over the batch.
+    over the batch.  With ``rho_parts`` the split-ratio derivative is returned
+    as the pair (through the first GVD, through the last GVD), whose sum is
+    dL/drho.
     """
     x = np.asarray(field_in, dtype=np.complex128)
     g = np.asarray(grad_out, dtype=np.complex128)
@@ -83,13 +90,15 @@ def vjp(field_in: np.ndarray, plan: OraclePlan, grad_out: np.ndarray):
     if squeeze:
         x, g = x[None], g[None]
     coeffs = torch.tensor(plan.coeffs, dtype=torch.float64, requires_grad=True)
-    rho = torch.tensor(float(plan.rho), dtype=torch.float64, requires_grad=True)
+    rho_f = torch.tensor(float(plan.rho), dtype=torch.float64, requires_grad=True)
+    rho_l = torch.tensor(float(plan.rho), dtype=torch.float64, requires_grad=True)
     gin = []
     for bi in range(x.shape[0]):
         xi = torch.tensor(x[bi], requires_grad=True)
-        out = forward_torch(xi, coeffs, rho, plan)
+        out = forward_torch(xi, coeffs, (rho_f, rho_l), plan)
         loss = (torch.conj(torch.from_numpy(g[bi])) * out).real.sum()
         loss.backward()
         gin.append(xi.grad.numpy().copy())
     grad_in = np.stack(gin)
-    return (grad_in[0] if squeeze else grad_in), coeffs.grad.numpy().copy(), float(rho.grad)
+    g_rho = (float(rho_f.grad), float(rho_l.grad)) if rho_parts else float(rho_f.grad) + float(rho_l.grad)
+    return (grad_in[0] if squeeze else grad_in), coeffs.grad.numpy().copy(), g_rho

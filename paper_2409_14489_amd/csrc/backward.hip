@@ -1,0 +1,522 @@
+// CB-ESSFM adjoint (reverse-mode) kernel for gfx950 (MI355X).
+//
+// Gives dL/dC (the per-step coupled-filter coefficients), dL/drho and,
+// optionally, dL/dfield_in from dL/dfield_out, by running the forward map of
+// Sec. III-A / III-C backwards.  The paper fits its coefficients offline with
+// finite-difference gradients and names automatic differentiation as future
+// work (Sec. III-B, Sec. V); this is that derivative, hand-written.
+//
+// Per block, with the forward quantities of step s (1-based) written
+//   A = h_s S_{s-1},  v = IDFT(A),  p = |v_x|^2 + |v_y|^2,  theta = C_s (*) p,
+//   w = v exp(-j theta),  S_s = DFT(w)        (unscaled size-N' transforms),
+// and g_X the cotangent of X (PyTorch convention dL/dRe + j dL/dIm):
+//   g_w = IDFT(g_S),  theta_bar = sum_pol Im(conj(g_w) w),
+//   p_bar_l = sum_i C_s[i][l] (x) theta_bar_i   (correlation: taps reversed),
+//   g_v = g_w exp(+j theta) + 2 p_bar v,  g_A = DFT(g_v),  g_{S_{s-1}} = conj(h_s) g_A,
+//   dL/dC_s[i][l][tau] = sum_k theta_bar_i[k] p_l[(k - tau + Nc) mod N'],
+//   dL/drho = L sum_q phi_q [Im(conj(g_A1) A1) - Im(conj(g_B) B)],
+// with phi_q = 2 pi^2 beta2 f_q^2, A1 the first post-GVD spectrum and B the
+// spectrum after the last GVD.  The block's output stage (MUX, inverse size-N
+// DFT) is adjoint to its input stage and vice versa, so both are reused.
+//
+// The forward trajectory of a block is recomputed from spectra stored every
+// `ck_every` steps (segment by segment, Griewank-style with one level).
+// Coefficient and split-ratio partials are written per block and reduced over
+// blocks in FP64 by a second kernel, in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include "fft_lds.hpp"
+#include "internal.hpp"
+#include "stages.hpp"
+#include "team.hpp"
+
+namespace cbessfm {
+
+template <int N>
+__device__ __forceinline__ void store_state(float2* st, const float2 (&x)[FftShape<N>::RR],
+                                            const float2 (&y)[FftShape<N>::RR], int t) {
+  constexpr int RR = FftShape<N>::RR, NT = FftShape<N>::NT;
+#pragma unroll
+  for (int o = 0; o < RR; ++o) {
+    st[t + NT * o] = x[o];
+    st[N + t + NT * o] = y[o];
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void load_state(const float2* st, float2 (&x)[FftShape<N>::RR],
+                                           float2 (&y)[FftShape<N>::RR], int t) {
+  constexpr int RR = FftShape<N>::RR, NT = FftShape<N>::NT;
+#pragma unroll
+  for (int o = 0; o < RR; ++o) {
+    x[o] = st[t + NT * o];
+    y[o] = st[N + t + NT * o];
+  }
+}
+
+// Sum over the 64 lanes of a wave of eight values per lane.  On return the
+// lanes 8 i .. 8 i + 7 hold the total of value i.
+__device__ __forceinline__ float wave_sum8(const float (&v)[8], int lane) {
+  const bool b5 = (lane >> 5) & 1, b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1;
+  float u[4], w[2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float send = b5 ? v[i] : v[i + 4];
+    const float keep = b5 ? v[i + 4] : v[i];
+    u[i] = keep + __shfl_xor(send, 32, 64);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const float send = b4 ? u[i] : u[i + 2];
+    const float keep = b4 ? u[i + 2] : u[i];
+    w[i] = keep + __shfl_xor(send, 16, 64);
+  }
+  float z = (b3 ? w[1] : w[0]) + __shfl_xor(b3 ? w[0] : w[1], 8, 64);
+  z += __shfl_xor(z, 4, 64);
+  z += __shfl_xor(z, 2, 64);
+  z += __shfl_xor(z, 1, 64);
+  return z;
+}
+
+// dL/dC_s[me][l][tau] for this block: sum_k tb[k] p_l[(k - tau + nc) mod N']
+// with tb = theta_bar of member `me` (positions t + NT o).  The p rows of
+// the step are re-read from the exchange (round `tag`, still untouched
+// because this member has not yet published a later round).  Writes
+// n_sb x n_taps floats at `dst`.
+template <int N>
+__device__ __forceinline__ void coeff_grad(const TeamCtx& c, uint64_t* xrow, unsigned tag,
+                                           const float (&p_own)[FftShape<N>::RR], const float (&tb_own)[FftShape<N>::RR],
+                                           int n_taps, float* __restrict__ dst, float* lf) {
+  constexpr int RR = FftShape<N>::RR, NT = FftShape<N>::NT, NW = NT / 64;
+  constexpr int PB = NlprLds<N>::PB;
+  const int t = opaque_tid();
+  const int lane = t & 63, wave = t >> 6;
+  const int nsb = c.nsb, me = c.me, nc = c.nc;
+  const int tap_pad = kTapChunk * c.n_chunks;
+  const int hl = tap_pad - 1 - nc;
+  float* th = lf + 2 * PB;
+  float* red = th + NlprLds<N>::TH;  // [tap_pad][NW]
+
+  __syncthreads();
+#pragma unroll
+  for (int o = 0; o < RR; ++o) th[pad_f(t + NT * o)] = tb_own[o];
+  {
+    float v[RR];
+    if (nsb > 1 && me != 0) {
+      xget<RR>(xrow, t, NT, tag, c.ctl, v);
+      stage_row<N, RR, NT>(lf, v, t, hl, nc);
+    } else {
+      stage_row<N, RR, NT>(lf, p_own, t, hl, nc);
+    }
+  }
+  __syncthreads();
+  float tb[RR];  // block mapping t RR + q
+#pragma unroll
+  for (int q = 0; q < RR; ++q) tb[q] = th[pad_f(t * RR + q)];
+
+  for (int l = 0; l < nsb; ++l) {
+    const float* cur = lf + (l & 1) * PB;
+    const bool fetch = (l + 1 < nsb) && (l + 1 != me);
+    uint64_t w[RR];
+    if (fetch) xissue<RR>(xrow + (size_t)(l + 1) * N, t, NT, w);
+    for (int ch = 0; ch < c.n_chunks; ++ch) {
+      float win[RR + kTapChunk - 1];
+      const int base = t * RR - (kTapChunk - 1) - kTapChunk * ch + nc + hl;
+#pragma unroll
+      for (int i = 0; i < RR + kTapChunk - 1; ++i) win[i] = cur[pad_f(base + i)];
+      float part[kTapChunk];
+#pragma unroll
+      for (int tt = 0; tt < kTapChunk; ++tt) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int q = 0; q < RR; ++q) acc = fmaf(tb[q], win[q - tt + kTapChunk - 1], acc);
+        part[tt] = acc;
+      }
+      const float z = wave_sum8(part, lane);
+      if ((lane & 7) == 0) red[(kTapChunk * ch + (lane >> 3)) * NW + wave] = z;
+    }
+    if (l + 1 < nsb) {
+      if (fetch) {
+        float v[RR];
+        xcomplete<RR>(xrow + (size_t)(l + 1) * N, t, NT, tag, c.ctl, w, v);
+        stage_row<N, RR, NT>(lf + ((l + 1) & 1) * PB, v, t, hl, nc);
+      } else {
+        stage_row<N, RR, NT>(lf + ((l + 1) & 1) * PB, p_own, t, hl, nc);
+      }
+    }
+    __syncthreads();
+    for (int tau = t; tau < n_taps; tau += NT) {
+      float sum = 0.0f;
+      for (int wv = 0; wv < NW; ++wv) sum += red[tau * NW + wv];
+      dst[(size_t)l * n_taps + tau] = sum;
+    }
+    __syncthreads();
+  }
+}
+
+// rho partial: sum over owned bins of phi_q L Im(conj(g) a), both polarisations.
+template <int N>
+__device__ __forceinline__ double rho_term(const double* __restrict__ phase_km, double L, int t,
+                                           const float2 (&gx)[FftShape<N>::RR], const float2 (&gy)[FftShape<N>::RR],
+                                           const float2 (&ax)[FftShape<N>::RR], const float2 (&ay)[FftShape<N>::RR]) {
+  constexpr int RR = FftShape<N>::RR, NT = FftShape<N>::NT;
+  double acc = 0.0;
+#pragma unroll
+  for (int o = 0; o < RR; ++o) {
+    const double ph = phase_km[t + NT * o] * L;
+    const float im = (gx[o].x * ax[o].y - gx[o].y * ax[o].x) + (gy[o].x * ay[o].y - gy[o].y * ay[o].x);
+    acc += ph * (double)im;
+  }
+  return acc;
+}
+
+template <int LOGN>
+__global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void bwd_kernel(BwdArgs a) {
+  constexpr int N = 1 << LOGN;  // N'
+  using S = FftShape<N>;
+  constexpr int RR = S::RR, NT = S::NT, NW = NT / 64;
+  __shared__ __align__(16) float lf[lds_floats<N>()];
+  __shared__ double rho_red[NW];
+  float2* lx = reinterpret_cast<float2*>(lf);
+  float2* ly = lx + S::LDS_C;
+
+  TeamCtx c;
+  c.nsb = a.n_sb;
+  const int r = blockIdx.x / kXcds;
+  c.me = r % c.nsb;
+  c.team = (r / c.nsb) * kXcds + blockIdx.x % kXcds;
+  if (c.team >= a.n_teams) return;
+  c.n_chunks = a.n_chunks;
+  c.nc = a.nc;
+  c.ctl = a.ctl;
+  c.tab = &a.tab;
+  const int nsb = c.nsb, me = c.me;
+  const float2* tw = a.tab.tw;
+  const int T = a.T;
+  const int tap_pad = kTapChunk * a.n_chunks;
+  const int k = a.ck_every;
+  const size_t state_sz = (size_t)2 * N;  // one member's two polarisations
+  float2* team_states = a.states + (size_t)c.team * (a.n_ck + k) * nsb * state_sz;
+  auto st = [&](int slot) { return team_states + ((size_t)slot * nsb + me) * state_sz; };
+  uint64_t* xs_a = a.xspec + ((size_t)c.team * 2 + 0) * nsb * 4 * N;
+  uint64_t* xs_b = a.xspec + ((size_t)c.team * 2 + 1) * nsb * 4 * N;
+  const double* phase_km = a.phase + (size_t)me * N;
+
+  unsigned iter = 0;
+  for (int item = c.team; item < a.n_items; item += a.n_teams, ++iter) {
+    int t = opaque_tid();
+    unsigned rnd = a.tag_base + iter * a.rounds_per_item;
+    unsigned np = 0, nq = 0;  // p- and theta_bar-rounds so far (slot parity)
+    const int inst = item / a.nblk;
+    const int blk = item - inst * a.nblk;
+    float2 x[RR], y[RR], gx[RR], gy[RR];
+    double rho_acc = 0.0;
+
+    // one forward step s (0-based) on x / y, with its intensity exchange round
+    auto forward_step = [&](int s) {
+      t = opaque_tid();
+      apply_diag<N, false>(x, y, (s == 0 ? a.tab.h_first : a.tab.h_mid) + (size_t)me * N, t);
+      fft<N, true>(x, y, lx, ly, tw, t);
+      float p[RR], theta[RR];
+      intensity<N>(x, y, p);
+      uint64_t* xrow = a.xp + ((size_t)c.team * 2 + (np & 1u)) * nsb * N;
+      coupled_fir<N>(c, a.tab.cpad + ((size_t)(s * nsb + me) * nsb) * tap_pad, xrow, rnd, p, theta, lf);
+      ++rnd;
+      ++np;
+      rotate<N, -1>(x, y, theta);
+      fft<N, false>(x, y, lx, ly, tw, t);
+    };
+
+    // ---- A: forward sweep, storing S_s every k steps
+    const float2* in_x = a.in + (size_t)inst * 2 * T;
+    gather_block<N, false>(in_x, in_x + T, blk, a.hop, a.n_ov, T, a.boundary, nsb, me, t, x, y);
+    fft<N, false>(x, y, lx, ly, tw, t);
+    polyphase_to_subband<N>(c, xs_a, rnd++, t, x, y);
+    for (int s = 0; s < a.steps; ++s) {
+      if (s % k == 0) store_state<N>(st(s / k), x, y, opaque_tid());
+      forward_step(s);
+    }
+
+    // ---- B: adjoint of the output stage
+    t = opaque_tid();
+    apply_diag<N, false>(x, y, a.tab.h_last + (size_t)me * N, t);  // B
+    const float2* go_x = a.gout + (size_t)inst * 2 * T;
+    gather_block<N, true>(go_x, go_x + T, blk, a.hop, a.n_ov, T, a.boundary, nsb, me, t, gx, gy);
+    fft<N, false>(gx, gy, lx, ly, tw, t);
+    polyphase_to_subband<N>(c, xs_b, rnd++, t, gx, gy);  // g_B
+    rho_acc -= rho_term<N>(phase_km, a.L, t, gx, gy, x, y);
+    apply_diag<N, true>(gx, gy, a.tab.h_last + (size_t)me * N, t);  // g_{S_Nst}
+
+    // ---- C: reverse sweep, segment by segment
+    for (int seg = a.n_ck - 1; seg >= 0; --seg) {
+      const int s0 = seg * k;
+      const int s1 = min(s0 + k, a.steps);
+      t = opaque_tid();
+      load_state<N>(st(seg), x, y, t);
+      for (int j = 1; j < s1 - s0; ++j) {  // recompute S_{s0+j}
+        forward_step(s0 + j - 1);
+        store_state<N>(st(a.n_ck + j), x, y, opaque_tid());
+      }
+      for (int s = s1; s > s0; --s) {  // 1-based step s, from S_{s-1}
+        t = opaque_tid();
+        const int j = s - 1 - s0;
+        load_state<N>(j == 0 ? st(seg) : st(a.n_ck + j), x, y, t);
+        const float2* hs = (s == 1 ? a.tab.h_first : a.tab.h_mid) + (size_t)me * N;
+        // recompute v, p, theta of step s
+        apply_diag<N, false>(x, y, hs, t);
+        fft<N, true>(x, y, lx, ly, tw, t);
+        float p[RR], theta[RR], tbar[RR];
+        intensity<N>(x, y, p);
+        const unsigned tag_p = rnd++;
+        uint64_t* prow = a.xp + ((size_t)c.team * 2 + (np & 1u)) * nsb * N;
+        ++np;
+        coupled_fir<N>(c, a.tab.cpad + ((size_t)((s - 1) * nsb + me) * nsb) * tap_pad, prow, tag_p, p, theta, lf);
+        // g_w, theta_bar
+        fft<N, true>(gx, gy, lx, ly, tw, t);
+#pragma unroll
+        for (int o = 0; o < RR; ++o) {
+          float sn, cs;
+          sincosf(theta[o], &sn, &cs);
+          const float2 rot = make_float2(cs, -sn);
+          const float2 wx = cmul(x[o], rot), wy = cmul(y[o], rot);
+          tbar[o] = (gx[o].x * wx.y - gx[o].y * wx.x) + (gy[o].x * wy.y - gy[o].y * wy.x);
+        }
+        coeff_grad<N>(c, prow, tag_p, p, tbar, a.n_taps,
+                      a.cpart + ((((size_t)item * a.steps + (s - 1)) * nsb + me) * nsb) * a.n_taps, lf);
+        // p_bar: transposed filter over the team's theta_bar rows
+        float pbar[RR];
+        uint64_t* qrow = a.xq + ((size_t)c.team * 2 + (nq & 1u)) * nsb * N;
+        ++nq;
+        coupled_fir<N>(c, a.ctpad + ((size_t)((s - 1) * nsb + me) * nsb) * tap_pad, qrow, rnd++, tbar, pbar, lf);
+        // g_v = g_w exp(+j theta) + 2 p_bar v
+        rotate<N, +1>(gx, gy, theta);
+#pragma unroll
+        for (int o = 0; o < RR; ++o) {
+          gx[o] = make_float2(fmaf(2.0f * pbar[o], x[o].x, gx[o].x), fmaf(2.0f * pbar[o], x[o].y, gx[o].y));
+          gy[o] = make_float2(fmaf(2.0f * pbar[o], y[o].x, gy[o].x), fmaf(2.0f * pbar[o], y[o].y, gy[o].y));
+        }
+        fft<N, false>(gx, gy, lx, ly, tw, t);  // g_A
+        if (s == 1) {                          // first GVD depends on rho
+          load_state<N>(st(0), x, y, t);
+          apply_diag<N, false>(x, y, hs, t);  // A1
+          rho_acc += rho_term<N>(phase_km, a.L, t, gx, gy, x, y);
+        }
+        apply_diag<N, true>(gx, gy, hs, t);  // g_{S_{s-1}}
+      }
+    }
+
+    // ---- D: adjoint of the input stage (optional)
+    if (a.gin_blk != nullptr) {
+      t = opaque_tid();
+      subband_to_polyphase<N>(c, xs_b, rnd++, t, gx, gy);
+      fft<N, true>(gx, gy, lx, ly, tw, t);
+      float2* dst = a.gin_blk + (size_t)item * 2 * nsb * N;
+#pragma unroll
+      for (int o = 0; o < RR; ++o) {
+        const int n = nsb * (t + NT * o) + me;
+        const float sg = (n & 1) ? -1.0f : 1.0f;
+        dst[n] = cscale(gx[o], sg);
+        dst[(size_t)nsb * N + n] = cscale(gy[o], sg);
+      }
+    }
+
+    // ---- split-ratio partial of this member
+    {
+      t = opaque_tid();
+      double v = rho_acc;
+#pragma unroll
+      for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+      __syncthreads();
+      if ((t & 63) == 0) rho_red[t >> 6] = v;
+      __syncthreads();
+      if (t == 0) {
+        double sum = 0.0;
+        for (int wv = 0; wv < NW; ++wv) sum += rho_red[wv];
+        a.rpart[(size_t)item * nsb + me] = sum;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ reductions
+// out[j] = sum over items of part[item][j], in FP64, items in order.
+__global__ void reduce_items_kernel(const float* __restrict__ part, float* __restrict__ out, int n_items, int per_item) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= per_item) return;
+  double acc = 0.0;
+  for (int it = 0; it < n_items; ++it) acc += (double)part[(size_t)it * per_item + j];
+  out[j] = (float)acc;
+}
+
+__global__ void reduce_rho_kernel(const double* __restrict__ part, float* __restrict__ out, int n) {
+  __shared__ double buf[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += part[i];
+  buf[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) buf[threadIdx.x] += buf[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = (float)buf[0];
+}
+
+__device__ __forceinline__ long long floor_div(long long a, long long h) {
+  return a >= 0 ? a / h : -((-a + h - 1) / h);
+}
+__device__ __forceinline__ long long ceil_div(long long a, long long h) { return -floor_div(-a, h); }
+
+// grad_in[inst][pol][pos] = sum over the blocks that read input sample pos of
+// their input cotangents (blocks in order, FP64 accumulation).
+__global__ void gather_gin_kernel(const float2* __restrict__ blk_g, float2* __restrict__ gin, int T, int N, int hop,
+                                  int n_ov, int nblk, int batch, int boundary) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)batch * 2 * T) return;
+  const int pos = (int)(idx % T);
+  const int pol = (int)((idx / T) % 2);
+  const int inst = (int)(idx / (2LL * T));
+  double ax = 0.0, ay = 0.0;
+  auto add = [&](int b, int n) {
+    const float2 v = blk_g[((size_t)(inst * nblk + b) * 2 + pol) * N + n];
+    ax += v.x;
+    ay += v.y;
+  };
+  const int off = n_ov / 2;
+  if (boundary == 1 || T >= N) {
+    const int m_lo = boundary == 1 ? 0 : -1, m_hi = boundary == 1 ? 0 : 2;
+    for (int m = m_lo; m <= m_hi; ++m) {
+      const long long P = (long long)pos + (long long)m * T;  // unwrapped position
+      // blocks b with start b hop - off <= P < start + N
+      long long b_lo = ceil_div(P + off - N + 1, hop);
+      long long b_hi = floor_div(P + off, hop);
+      if (b_lo < 0) b_lo = 0;
+      if (b_hi > nblk - 1) b_hi = nblk - 1;
+      for (long long b = b_lo; b <= b_hi; ++b) {
+        const long long n = P - (b * hop - off);
+        if (n >= 0 && n < N) add((int)b, (int)n);
+      }
+    }
+  } else {  // sequence shorter than a block: a block wraps over it several times
+    for (int b = 0; b < nblk; ++b) {
+      const long long start = (long long)b * hop - off;
+      long long n0 = ((long long)pos - start) % T;
+      if (n0 < 0) n0 += T;
+      for (long long n = n0; n < N; n += T) add(b, (int)n);
+    }
+  }
+  gin[((size_t)inst * 2 + pol) * T + pos] = make_float2((float)ax, (float)ay);
+}
+
+// ------------------------------------------------------------------ launchers
+template <int LOGN>
+static int launch_bwd_t(const BwdArgs& args, int grid, hipStream_t s) {
+  void* kargs[] = {(void*)&args};
+  hipError_t e = hipLaunchCooperativeKernel((const void*)bwd_kernel<LOGN>, dim3(grid),
+                                            dim3(FftShape<(1 << LOGN)>::NT), kargs, 0, s);
+  return e == hipSuccess ? CBESSFM_OK : CBESSFM_EHIP;
+}
+
+template <int LOGN>
+static int bwd_occ_t(int* blocks) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, bwd_kernel<LOGN>, FftShape<(1 << LOGN)>::NT, 0) ==
+                 hipSuccess
+             ? CBESSFM_OK
+             : CBESSFM_EHIP;
+}
+
+int bwd_occupancy_per_cu(int log_np, int* blocks) {
+  switch (log_np) {
+    case 8: return bwd_occ_t<8>(blocks);
+    case 9: return bwd_occ_t<9>(blocks);
+    case 10: return bwd_occ_t<10>(blocks);
+    case 11: return bwd_occ_t<11>(blocks);
+    case 12: return bwd_occ_t<12>(blocks);
+    case 13: return bwd_occ_t<13>(blocks);
+    default: return CBESSFM_EUNSUPPORTED;
+  }
+}
+
+BwdLayout bwd_layout(const cbessfm_plan_t* p, long long T, int batch, int ck_every) {
+  BwdLayout L;
+  L.k = ck_every <= 0 ? 1 : (ck_every > p->steps ? p->steps : ck_every);
+  L.n_ck = (p->steps + L.k - 1) / L.k;
+  L.nblk = (int)((T + p->hop - 1) / p->hop);
+  L.n_items = batch * L.nblk;
+  L.n_teams = L.n_items < p->bwd_team_capacity ? L.n_items : p->bwd_team_capacity;
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t nsb = p->sb.n_sb;
+  L.states_off = 0;
+  L.cpart_off = up(L.states_off + sizeof(float2) * (size_t)L.n_teams * (L.n_ck + L.k) * nsb * 2 * p->Np);
+  L.rpart_off = up(L.cpart_off + sizeof(float) * (size_t)L.n_items * p->steps * nsb * nsb * p->n_taps);
+  L.gin_off = up(L.rpart_off + sizeof(double) * (size_t)L.n_items * nsb);
+  L.bytes = up(L.gin_off + sizeof(float2) * (size_t)L.n_items * 2 * p->N);
+  return L;
+}
+
+int launch_backward(cbessfm_plan_t* p, const void* field_in, const void* grad_out, void* grad_in, float* grad_c,
+                    float* grad_rho, long long T, int batch, int ck_every, void* workspace, size_t ws_bytes,
+                    hipStream_t s) {
+  const BwdLayout L = bwd_layout(p, T, batch, ck_every);
+  if (ws_bytes < L.bytes) return CBESSFM_EWORKSPACE;
+  char* ws = static_cast<char*>(workspace);
+  BwdArgs a;
+  a.in = static_cast<const float2*>(field_in);
+  a.gout = static_cast<const float2*>(grad_out);
+  a.T = (int)T;
+  a.nblk = L.nblk;
+  a.n_items = L.n_items;
+  a.n_sb = p->sb.n_sb;
+  a.steps = p->steps;
+  a.n_chunks = p->n_chunks;
+  a.nc = p->n_taps / 2;
+  a.n_taps = p->n_taps;
+  a.n_ov = p->sb.overlap;
+  a.hop = p->hop;
+  a.boundary = p->sb.boundary;
+  a.n_teams = L.n_teams;
+  a.ck_every = L.k;
+  a.n_ck = L.n_ck;
+  fill_tables(p, a.tab);
+  a.ctpad = p->d_ctpad;
+  a.phase = p->d_phase;
+  a.L = p->step_km;
+  a.xspec = p->d_xspec;
+  a.xp = p->d_xp;
+  a.xq = p->d_xq;
+  a.states = reinterpret_cast<float2*>(ws + L.states_off);
+  a.cpart = reinterpret_cast<float*>(ws + L.cpart_off);
+  a.rpart = reinterpret_cast<double*>(ws + L.rpart_off);
+  a.gin_blk = grad_in ? reinterpret_cast<float2*>(ws + L.gin_off) : nullptr;
+  a.ctl.abort = p->d_abort;
+  a.ctl.err = p->d_err;
+  a.ctl.spin_limit = 1u << 22;
+  a.rounds_per_item = 4u * (unsigned)p->steps + 4u;
+  const unsigned per_team = (unsigned)((a.n_items + a.n_teams - 1) / a.n_teams);
+  a.tag_base = take_tags(p, per_team * a.rounds_per_item, s);
+  if (a.tag_base == 0u) return CBESSFM_EHIP;
+  const int groups = (a.n_teams + kXcds - 1) / kXcds;
+  const int grid = groups * kXcds * a.n_sb;
+  int rc;
+  switch (p->log_np) {
+    case 8: rc = launch_bwd_t<8>(a, grid, s); break;
+    case 9: rc = launch_bwd_t<9>(a, grid, s); break;
+    case 10: rc = launch_bwd_t<10>(a, grid, s); break;
+    case 11: rc = launch_bwd_t<11>(a, grid, s); break;
+    case 12: rc = launch_bwd_t<12>(a, grid, s); break;
+    case 13: rc = launch_bwd_t<13>(a, grid, s); break;
+    default: rc = CBESSFM_EUNSUPPORTED;
+  }
+  if (rc) return rc;
+  const int per_item = p->steps * a.n_sb * a.n_sb * p->n_taps;
+  reduce_items_kernel<<<(per_item + 255) / 256, 256, 0, s>>>(a.cpart, grad_c, a.n_items, per_item);
+  reduce_rho_kernel<<<1, 256, 0, s>>>(a.rpart, grad_rho, a.n_items * a.n_sb);
+  if (grad_in) {
+    const long long total = (long long)batch * 2 * T;
+    gather_gin_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(a.gin_blk, static_cast<float2*>(grad_in),
+                                                                       (int)T, p->N, p->hop, p->sb.overlap, a.nblk,
+                                                                       batch, p->sb.boundary);
+  }
+  return hipGetLastError() == hipSuccess ? CBESSFM_OK : CBESSFM_EHIP;
+}
+
+}  // namespace cbessfm

@@ -14,261 +14,73 @@
 
 #include "fft_lds.hpp"
 #include "internal.hpp"
+#include "stages.hpp"
 #include "team.hpp"
 
 namespace cbessfm {
-
-// Coupled intensity filter of eq. (15) for subband `me`, circular over N':
-//   theta[k] = sum_l sum_tau C[s][me][l][tau] p_l[(k - tau + nc) mod N'].
-// p_own holds this workgroup's intensities at positions t + NT o; on return
-// theta holds the phase at the same positions.  For n_sb > 1 the team's rows
-// come from the tagged exchange row `xrow` ([n_sb][N'], round `tag`).
-template <int N>
-__device__ __forceinline__ void coupled_fir(const FwdArgs& a, const float* __restrict__ crow, int me,
-                                           uint64_t* xrow, unsigned tag, const float (&p_own)[FftShape<N>::RR],
-                                           float (&theta)[FftShape<N>::RR], float* lf) {
-  using S = FftShape<N>;
-  constexpr int RR = S::RR, NT = S::NT;
-  const int t = opaque_tid();
-  const int nsb = a.n_sb;
-  const int nc = a.nc;
-  const int tap_pad = kTapChunk * a.n_chunks;
-  const int hl = tap_pad - 1 - nc;  // left halo of the circular extension
-  constexpr int PB = NlprLds<N>::PB;  // row l lives at lf + (l & 1) * PB
-  float* th = lf + 2 * PB;
-
-  if (nsb > 1) {
-#pragma unroll
-    for (int o = 0; o < RR; ++o) xput(xrow + (size_t)me * N + t + NT * o, p_own[o], tag);
-  }
-  __syncthreads();  // the LDS rows alias the FFT exchange buffers
-  {
-    float v[RR];
-    if (nsb > 1 && me != 0) {
-      xget<RR>(xrow, t, NT, tag, a.ctl, v);
-      stage_row<N, RR, NT>(lf, v, t, hl, nc);
-    } else {
-      stage_row<N, RR, NT>(lf, p_own, t, hl, nc);
-    }
-  }
-  __syncthreads();
-
-  float acc[RR];
-#pragma unroll
-  for (int q = 0; q < RR; ++q) acc[q] = 0.0f;
-  for (int l = 0; l < nsb; ++l) {
-    const float* cur = lf + (l & 1) * PB;
-    const bool fetch = (l + 1 < nsb) && (l + 1 != me);  // next row is remote
-    uint64_t w[RR];
-    if (fetch) xissue<RR>(xrow + (size_t)(l + 1) * N, t, NT, w);  // in flight during the filter
-    const float* cl = crow + (size_t)l * tap_pad;
-    for (int c = 0; c < a.n_chunks; ++c) {
-      // window w in [0, RR + 7): p index t RR + w - 7 - 8 c + nc, stored at + hl
-      float win[RR + kTapChunk - 1];
-      const int base = t * RR - (kTapChunk - 1) - kTapChunk * c + nc + hl;
-#pragma unroll
-      for (int i = 0; i < RR + kTapChunk - 1; ++i) win[i] = cur[pad_f(base + i)];
-#pragma unroll
-      for (int tt = 0; tt < kTapChunk; ++tt) {
-        const float cf = cl[kTapChunk * c + tt];
-#pragma unroll
-        for (int q = 0; q < RR; ++q) acc[q] = fmaf(cf, win[q - tt + kTapChunk - 1], acc[q]);
-      }
-    }
-    if (l + 1 < nsb) {
-      if (fetch) {
-        float v[RR];
-        xcomplete<RR>(xrow + (size_t)(l + 1) * N, t, NT, tag, a.ctl, w, v);
-        stage_row<N, RR, NT>(lf + ((l + 1) & 1) * PB, v, t, hl, nc);
-      } else {
-        stage_row<N, RR, NT>(lf + ((l + 1) & 1) * PB, p_own, t, hl, nc);
-      }
-    }
-    __syncthreads();
-  }
-  // block mapping (t RR + q) -> owned positions (t + NT o)
-#pragma unroll
-  for (int q = 0; q < RR; ++q) th[pad_f(t * RR + q)] = acc[q];
-  __syncthreads();
-#pragma unroll
-  for (int o = 0; o < RR; ++o) theta[o] = th[pad_f(t + NT * o)];
-}
-
-// Publishes this member's four spectrum components (x.re, x.im, y.re, y.im) at
-// positions t + NT o, for round `tag`.
-template <int RR, int NT, int N>
-__device__ __forceinline__ void put_spectrum(uint64_t* dst, const float2 (&x)[RR], const float2 (&y)[RR],
-                                             unsigned tag, int t) {
-#pragma unroll
-  for (int o = 0; o < RR; ++o) {
-    const int k = t + NT * o;
-    xput(dst + 0 * N + k, x[o].x, tag);
-    xput(dst + 1 * N + k, x[o].y, tag);
-    xput(dst + 2 * N + k, y[o].x, tag);
-    xput(dst + 3 * N + k, y[o].y, tag);
-  }
-}
-
-// ax / ay = sum over members n2 of w_n2 * (member n2's spectrum), where
-// w_n2 = wsb[(n2 * me) mod n_sb], conjugated when CONJ.
-template <int RR, int NT, int N, bool CONJ>
-__device__ __forceinline__ void combine_spectra(const uint64_t* src, int nsb, int me, const float2* wsb,
-                                                unsigned tag, const XchgCtl& ctl, int t, float2 (&ax)[RR],
-                                                float2 (&ay)[RR]) {
-#pragma unroll
-  for (int o = 0; o < RR; ++o) ax[o] = ay[o] = make_float2(0.f, 0.f);
-  for (int n2 = 0; n2 < nsb; ++n2) {
-    const float2 w = wsb[(n2 * me) % nsb];
-    const uint64_t* row = src + (size_t)n2 * 4 * N;
-#pragma unroll
-    for (int comp = 0; comp < 2; ++comp) {  // polarisation x, then y
-      float re[RR], im[RR];
-      xget<RR>(row + (2 * comp) * N, t, NT, tag, ctl, re);
-      xget<RR>(row + (2 * comp + 1) * N, t, NT, tag, ctl, im);
-#pragma unroll
-      for (int o = 0; o < RR; ++o) {
-        const float2 v = make_float2(re[o], im[o]);
-        const float2 prod = CONJ ? cmulc(v, w) : cmul(v, w);
-        if (comp == 0) ax[o] = cadd(ax[o], prod);
-        else ay[o] = cadd(ay[o], prod);
-      }
-    }
-  }
-}
 
 template <int LOGN>
 __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void fwd_kernel(FwdArgs a) {
   constexpr int N = 1 << LOGN;  // N'
   using S = FftShape<N>;
-  constexpr int RR = S::RR, NT = S::NT;
+  constexpr int RR = S::RR;
   __shared__ __align__(16) float lf[lds_floats<N>()];
   float2* lx = reinterpret_cast<float2*>(lf);
   float2* ly = lx + S::LDS_C;
 
-  const int nsb = a.n_sb;
+  TeamCtx c;
+  c.nsb = a.n_sb;
   // XCD-aware mapping: the n_sb members of a team share blockIdx mod 8
-  const int xcd = blockIdx.x % kXcds;
   const int r = blockIdx.x / kXcds;
-  const int me = r % nsb;
-  const int team = (r / nsb) * kXcds + xcd;
-  if (team >= a.n_teams) return;
-
+  c.me = r % c.nsb;
+  c.team = (r / c.nsb) * kXcds + blockIdx.x % kXcds;
+  if (c.team >= a.n_teams) return;
+  c.n_chunks = a.n_chunks;
+  c.nc = a.nc;
+  c.ctl = a.ctl;
+  c.tab = &a.tab;
+  const int nsb = c.nsb, me = c.me;
   const float2* tw = a.tab.tw;
-
   const int T = a.T;
   const int tap_pad = kTapChunk * a.n_chunks;
   const unsigned rounds_per_item = (unsigned)a.steps + 2u;
-  uint64_t* xs_in = a.xspec + ((size_t)team * 2 + 0) * nsb * 4 * N;
-  uint64_t* xs_out = a.xspec + ((size_t)team * 2 + 1) * nsb * 4 * N;
+  uint64_t* xs_in = a.xspec + ((size_t)c.team * 2 + 0) * nsb * 4 * N;
+  uint64_t* xs_out = a.xspec + ((size_t)c.team * 2 + 1) * nsb * 4 * N;
   unsigned iter = 0;
-  for (int item = team; item < a.n_items; item += a.n_teams, ++iter) {
+  for (int item = c.team; item < a.n_items; item += a.n_teams, ++iter) {
     int t = opaque_tid();
     const unsigned round0 = a.tag_base + iter * rounds_per_item;
     const int inst = item / a.nblk;
     const int blk = item - inst * a.nblk;
     const float2* in_x = a.in + (size_t)inst * 2 * T;
-    const float2* in_y = in_x + T;
     float2 x[RR], y[RR];
 
-    // ---- gather polyphase component `me` (n = n_sb n1 + me), times (-1)^n
-    {
-      const int first = frame_first(blk, a.hop, a.n_ov, T, a.boundary);
-      const bool short_seq = T < nsb * N;
-#pragma unroll
-      for (int o = 0; o < RR; ++o) {
-        const int n = nsb * (t + NT * o) + me;
-        const int pos = frame_pos(first, n, T, a.boundary, short_seq);
-        float2 vx = make_float2(0.f, 0.f), vy = vx;
-        if (pos >= 0) {
-          vx = in_x[pos];
-          vy = in_y[pos];
-        }
-        const float sg = (n & 1) ? -1.0f : 1.0f;
-        x[o] = cscale(vx, sg);
-        y[o] = cscale(vy, sg);
-      }
-    }
+    // ---- block input: size-N DFT as N_sb polyphase FFTs + N_sb-point DFT
+    gather_block<N, false>(in_x, in_x + T, blk, a.hop, a.n_ov, T, a.boundary, nsb, me, t, x, y);
     fft<N, false>(x, y, lx, ly, tw, t);
-
-    // ---- size-n_sb DFT across the team: subband `me` of the block spectrum
-    if (nsb > 1) {
-#pragma unroll
-      for (int o = 0; o < RR; ++o) {
-        const float2 w = a.tab.poly_tw[(size_t)me * N + t + NT * o];
-        x[o] = cmul(x[o], w);
-        y[o] = cmul(y[o], w);
-      }
-      put_spectrum<RR, NT, N>(xs_in + (size_t)me * 4 * N, x, y, round0, t);
-      combine_spectra<RR, NT, N, false>(xs_in, nsb, me, a.tab.wsb, round0, a.ctl, t, x, y);
-    }
+    polyphase_to_subband<N>(c, xs_in, round0, t, x, y);
 
     // ---- step loop (Fig. "scheme_CB-ESSFM"), spectra in subband order
     for (int s = 0; s < a.steps; ++s) {
       t = opaque_tid();
-      const float2* h = (s == 0 ? a.tab.h_first : a.tab.h_mid) + (size_t)me * N;
-#pragma unroll
-      for (int o = 0; o < RR; ++o) {
-        const float2 hv = h[t + NT * o];
-        x[o] = cmul(x[o], hv);
-        y[o] = cmul(y[o], hv);
-      }
+      apply_diag<N, false>(x, y, (s == 0 ? a.tab.h_first : a.tab.h_mid) + (size_t)me * N, t);
       fft<N, true>(x, y, lx, ly, tw, t);  // lowpass-equivalent subband samples
       float p[RR], theta[RR];
-#pragma unroll
-      for (int o = 0; o < RR; ++o) p[o] = x[o].x * x[o].x + x[o].y * x[o].y + y[o].x * y[o].x + y[o].y * y[o].y;
+      intensity<N>(x, y, p);
       const unsigned round = round0 + 1u + (unsigned)s;
-      uint64_t* xrow = a.xp + ((size_t)team * 2 + (round & 1u)) * nsb * N;
-      const float* crow = a.tab.cpad + ((size_t)(s * nsb + me) * nsb) * tap_pad;
-      coupled_fir<N>(a, crow, me, xrow, round, p, theta, lf);
-#pragma unroll
-      for (int o = 0; o < RR; ++o) {
-        float sn, cs;
-        sincosf(theta[o], &sn, &cs);
-        const float2 rot = make_float2(cs, -sn);  // exp(-j theta)
-        x[o] = cmul(x[o], rot);
-        y[o] = cmul(y[o], rot);
-      }
+      uint64_t* xrow = a.xp + ((size_t)c.team * 2 + (round & 1u)) * nsb * N;
+      coupled_fir<N>(c, a.tab.cpad + ((size_t)(s * nsb + me) * nsb) * tap_pad, xrow, round, p, theta, lf);
+      rotate<N, -1>(x, y, theta);
       fft<N, false>(x, y, lx, ly, tw, t);
     }
 
-    // ---- final GVD, recombination, inverse size-N DFT
+    // ---- final GVD, recombination, inverse size-N DFT, kept samples
     t = opaque_tid();
-    {
-      const float2* h = a.tab.h_last + (size_t)me * N;
-#pragma unroll
-      for (int o = 0; o < RR; ++o) {
-        const float2 hv = h[t + NT * o];
-        x[o] = cmul(x[o], hv);
-        y[o] = cmul(y[o], hv);
-      }
-    }
-    if (nsb > 1) {
-      const unsigned round = round0 + rounds_per_item - 1u;
-      put_spectrum<RR, NT, N>(xs_out + (size_t)me * 4 * N, x, y, round, t);
-      combine_spectra<RR, NT, N, true>(xs_out, nsb, me, a.tab.wsb, round, a.ctl, t, x, y);
-#pragma unroll
-      for (int o = 0; o < RR; ++o) {
-        const float2 w = a.tab.poly_tw[(size_t)me * N + t + NT * o];
-        x[o] = cmulc(x[o], w);
-        y[o] = cmulc(y[o], w);
-      }
-    }
+    apply_diag<N, false>(x, y, a.tab.h_last + (size_t)me * N, t);
+    subband_to_polyphase<N>(c, xs_out, round0 + rounds_per_item - 1u, t, x, y);
     fft<N, true>(x, y, lx, ly, tw, t);
-
-    // ---- keep samples [N_ov/2, N - N_ov/2) of the block
     float2* out_x = a.out + (size_t)inst * 2 * T;
-    float2* out_y = out_x + T;
-    const int keep_lo = a.n_ov / 2, keep_hi = nsb * N - a.n_ov / 2;
-#pragma unroll
-    for (int o = 0; o < RR; ++o) {
-      const int n = nsb * (t + NT * o) + me;
-      const int pos = blk * a.hop + n - keep_lo;
-      if (n >= keep_lo && n < keep_hi && pos < T) {
-        const float sg = (n & 1) ? -1.0f : 1.0f;
-        out_x[pos] = cscale(x[o], sg);
-        out_y[pos] = cscale(y[o], sg);
-      }
-    }
+    scatter_block<N>(out_x, out_x + T, blk, a.hop, a.n_ov, T, nsb, me, t, x, y);
   }
 }
 
@@ -308,12 +120,17 @@ __global__ void tables_kernel(const double* __restrict__ phase, const double* __
   h[2 * n + q] = round_pair_dev(c * inv_np, s * inv_np);
 }
 
-__global__ void pad_coeffs_kernel(const float* __restrict__ src, float* __restrict__ dst, int rows, int n_taps,
-                                  int tap_pad) {
+// dst[s][i][l][tau] = C[s][i][l][tau] (zero for tau >= n_taps);
+// dstt[s][l][i][tau] = C[s][i][l][n_taps - 1 - tau] (the adjoint's correlation).
+__global__ void pad_coeffs_kernel(const float* __restrict__ src, float* __restrict__ dst, float* __restrict__ dstt,
+                                  int steps, int nsb, int n_taps, int tap_pad) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int rows = steps * nsb * nsb;
   if (i >= rows * tap_pad) return;
   const int row = i / tap_pad, tau = i % tap_pad;
   dst[i] = tau < n_taps ? src[(size_t)row * n_taps + tau] : 0.0f;
+  const int s = row / (nsb * nsb), l = (row / nsb) % nsb, ii = row % nsb;  // row of dstt = (s, l, ii)
+  dstt[i] = tau < n_taps ? src[(((size_t)s * nsb + ii) * nsb + l) * n_taps + (n_taps - 1 - tau)] : 0.0f;
 }
 
 __global__ void copy_rho_kernel(const float* __restrict__ src, double* __restrict__ dst) { *dst = (double)*src; }
@@ -416,7 +233,8 @@ int launch_tables(cbessfm_plan_t* p, hipStream_t s) {
 int launch_pad_coeffs(cbessfm_plan_t* p, const float* src, hipStream_t s) {
   const int rows = p->steps * p->sb.n_sb * p->sb.n_sb;
   const int total = rows * p->tap_pad;
-  pad_coeffs_kernel<<<(total + 255) / 256, 256, 0, s>>>(src, p->d_cpad, rows, p->n_taps, p->tap_pad);
+  pad_coeffs_kernel<<<(total + 255) / 256, 256, 0, s>>>(src, p->d_cpad, p->d_ctpad, p->steps, p->sb.n_sb,
+                                                       p->n_taps, p->tap_pad);
   return hipGetLastError() == hipSuccess ? CBESSFM_OK : CBESSFM_EHIP;
 }
 

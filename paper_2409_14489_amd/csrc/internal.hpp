@@ -47,6 +47,35 @@ struct FwdArgs {
   XchgCtl ctl;
 };
 
+// Everything an adjoint launch needs.
+struct BwdArgs {
+  const float2* in;    // [batch][2][T] forward input
+  const float2* gout;  // [batch][2][T] cotangent of the forward output
+  int T, n_items, nblk;
+  int n_sb, steps, n_chunks, nc, n_taps, n_ov, hop, boundary;
+  int n_teams;
+  int ck_every, n_ck;  // states stored every ck_every steps, n_ck of them
+  unsigned tag_base, rounds_per_item;
+  Tables tab;
+  const float* ctpad;   // [steps][n_sb][n_sb][tap_pad]: ctpad[s][l][i][t] = C[s][i][l][n_taps - 1 - t]
+  const double* phase;  // [N] 2 pi^2 beta2 f^2 per km, subband order
+  double L;             // step length, km
+  uint64_t* xspec;
+  uint64_t* xp;         // tagged intensity rows
+  uint64_t* xq;         // tagged theta_bar rows, [team_capacity][2][n_sb][N']
+  float2* states;       // [n_teams][n_ck + ck_every][n_sb][2][N']
+  float* cpart;         // [n_items][steps][n_sb][n_sb][n_taps]
+  double* rpart;        // [n_items][n_sb]
+  float2* gin_blk;      // [n_items][2][N] or null
+  XchgCtl ctl;
+};
+
+// Workspace layout of one adjoint call.
+struct BwdLayout {
+  int k, n_ck, nblk, n_items, n_teams;
+  size_t states_off, cpart_off, rpart_off, gin_off, bytes;
+};
+
 }  // namespace cbessfm
 
 struct cbessfm_plan {
@@ -59,7 +88,9 @@ struct cbessfm_plan {
   int device;
   int cu_count;
   int threads;
-  int team_capacity;  // teams whose workgroups can all be resident at once
+  int team_capacity;      // forward teams whose workgroups can all be resident at once
+  int bwd_team_capacity;  // the same for the adjoint kernel
+  int xchg_teams;         // teams the exchange buffers are sized for
   // device memory
   double* d_phase;    // [N] 2 pi^2 beta2 f^2 per km, subband order (FP64)
   float2* d_h;        // [3][N]
@@ -67,9 +98,11 @@ struct cbessfm_plan {
   float2* d_poly;     // [n_sb][N']
   float* d_c;         // [steps][n_sb][n_sb][n_taps] as given
   float* d_cpad;      // padded copy used by the kernels
+  float* d_ctpad;     // transposed, tap-reversed padded copy (adjoint)
   double* d_rho;      // current split ratio
   uint64_t* d_xspec;  // tagged exchange words
   uint64_t* d_xp;
+  uint64_t* d_xq;
   unsigned* d_abort;  // sticky exchange-timeout word
   int* d_err;
   unsigned next_tag;  // next unused exchange-round tag (host copy)
@@ -84,5 +117,11 @@ int launch_tables(cbessfm_plan_t* p, hipStream_t s);
 int launch_pad_coeffs(cbessfm_plan_t* p, const float* src, hipStream_t s);
 int launch_copy_rho(cbessfm_plan_t* p, const float* src, hipStream_t s);
 int occupancy_per_cu(int log_np, int* blocks);
+int bwd_occupancy_per_cu(int log_np, int* blocks);
+void fill_tables(const cbessfm_plan_t* p, Tables& tb);
+BwdLayout bwd_layout(const cbessfm_plan_t* p, long long T, int batch, int ck_every);
+int launch_backward(cbessfm_plan_t* p, const void* field_in, const void* grad_out, void* grad_in, float* grad_c,
+                    float* grad_rho, long long T, int batch, int ck_every, void* workspace, size_t ws_bytes,
+                    hipStream_t s);
 int threads_for(int log_np);
 }  // namespace cbessfm

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -113,10 +114,10 @@ float2 round_pair(double c, double s) {
 namespace {
 
 size_t xspec_bytes(const cbessfm_plan_t* p) {
-  return sizeof(uint64_t) * (size_t)p->team_capacity * 2 * p->sb.n_sb * 4 * p->Np;
+  return sizeof(uint64_t) * (size_t)p->xchg_teams * 2 * p->sb.n_sb * 4 * p->Np;
 }
 size_t xp_bytes(const cbessfm_plan_t* p) {
-  return sizeof(uint64_t) * (size_t)p->team_capacity * 2 * p->sb.n_sb * p->Np;
+  return sizeof(uint64_t) * (size_t)p->xchg_teams * 2 * p->sb.n_sb * p->Np;
 }
 
 }  // namespace
@@ -129,7 +130,8 @@ unsigned take_tags(cbessfm_plan_t* p, unsigned rounds, hipStream_t s) {
   if (rounds == 0) rounds = 1;
   if ((unsigned long long)p->next_tag + rounds >= 0xFFFFFF00ull) {
     if (hipMemsetAsync(p->d_xspec, 0, xspec_bytes(p), s) != hipSuccess ||
-        hipMemsetAsync(p->d_xp, 0, xp_bytes(p), s) != hipSuccess)
+        hipMemsetAsync(p->d_xp, 0, xp_bytes(p), s) != hipSuccess ||
+        hipMemsetAsync(p->d_xq, 0, xp_bytes(p), s) != hipSuccess)
       return 0u;
     p->next_tag = 1;
   }
@@ -225,8 +227,8 @@ void cbessfm_destroy(cbessfm_plan_t* p) {
   int prev = 0;
   hipGetDevice(&prev);
   hipSetDevice(p->device);
-  void* bufs[] = {p->d_phase, p->d_h, p->d_tw, p->d_poly, p->d_c, p->d_cpad, p->d_rho,
-                  p->d_xspec, p->d_xp, p->d_abort, p->d_err};
+  void* bufs[] = {p->d_phase, p->d_h, p->d_tw, p->d_poly, p->d_c, p->d_cpad, p->d_ctpad, p->d_rho,
+                  p->d_xspec, p->d_xp, p->d_xq, p->d_abort, p->d_err};
   for (void* b : bufs)
     if (b) hipFree(b);
   hipSetDevice(prev);
@@ -272,12 +274,18 @@ int cbessfm_plan(cbessfm_plan_t** out, const cbessfm_link* link, const cbessfm_s
   }
   // teams are placed as groups of n_sb workgroups per XCD; keep the whole
   // (padded) grid resident
-  const int capacity = per_cu * p->cu_count;
-  p->team_capacity = (capacity / (cbessfm::kXcds * sb->n_sb)) * cbessfm::kXcds;
-  if (p->team_capacity < 1) {
+  int bwd_per_cu = 0;
+  if (cbessfm::bwd_occupancy_per_cu(p->log_np, &bwd_per_cu) != CBESSFM_OK || bwd_per_cu < 1) {
+    delete p;
+    return CBESSFM_EHIP;
+  }
+  p->team_capacity = (per_cu * p->cu_count / (cbessfm::kXcds * sb->n_sb)) * cbessfm::kXcds;
+  p->bwd_team_capacity = (bwd_per_cu * p->cu_count / (cbessfm::kXcds * sb->n_sb)) * cbessfm::kXcds;
+  if (p->team_capacity < 1 || p->bwd_team_capacity < 1) {
     delete p;
     return CBESSFM_EUNSUPPORTED;
   }
+  p->xchg_teams = std::max(p->team_capacity, p->bwd_team_capacity);
 
   const int N = p->N, Np = p->Np, nsb = sb->n_sb;
   const size_t crows = (size_t)steps * nsb * nsb;
@@ -316,7 +324,6 @@ int cbessfm_plan(cbessfm_plan_t** out, const cbessfm_link* link, const cbessfm_s
   }
 
   // ---- device memory
-  const size_t teams = (size_t)p->team_capacity;
   bool ok = true;
   auto alloc = [&](void** ptr, size_t bytes) {
     if (ok && hipMalloc(ptr, bytes) != hipSuccess) ok = false;
@@ -327,9 +334,11 @@ int cbessfm_plan(cbessfm_plan_t** out, const cbessfm_link* link, const cbessfm_s
   alloc((void**)&p->d_poly, sizeof(float2) * nsb * Np);
   alloc((void**)&p->d_c, sizeof(float) * crows * p->n_taps);
   alloc((void**)&p->d_cpad, sizeof(float) * crows * p->tap_pad);
+  alloc((void**)&p->d_ctpad, sizeof(float) * crows * p->tap_pad);
   alloc((void**)&p->d_rho, sizeof(double));
   alloc((void**)&p->d_xspec, xspec_bytes(p));
   alloc((void**)&p->d_xp, xp_bytes(p));
+  alloc((void**)&p->d_xq, xp_bytes(p));
   alloc((void**)&p->d_abort, sizeof(unsigned));
   alloc((void**)&p->d_err, sizeof(int));
   if (!ok) {
@@ -344,7 +353,8 @@ int cbessfm_plan(cbessfm_plan_t** out, const cbessfm_link* link, const cbessfm_s
                 hipMemset(p->d_err, 0, sizeof(int)) == hipSuccess &&
                 hipMemset(p->d_abort, 0, sizeof(unsigned)) == hipSuccess &&
                 hipMemset(p->d_xspec, 0, xspec_bytes(p)) == hipSuccess &&
-                hipMemset(p->d_xp, 0, xp_bytes(p)) == hipSuccess;
+                hipMemset(p->d_xp, 0, xp_bytes(p)) == hipSuccess &&
+                hipMemset(p->d_xq, 0, xp_bytes(p)) == hipSuccess;
   p->next_tag = 1;
   if (!hip_ok || cbessfm::launch_tables(p, nullptr) || cbessfm::launch_pad_coeffs(p, p->d_c, nullptr) ||
       hipDeviceSynchronize() != hipSuccess) {
@@ -388,7 +398,7 @@ int cbessfm_set_split_ratio(cbessfm_plan_t* p, double split_ratio, void* stream)
 
 int cbessfm_run(cbessfm_plan_t* p, const void* field_in, void* field_out, int64_t T, int32_t batch,
                 void* stream) {
-  if (!p || !field_in || !field_out || T < 1 || batch < 1) return CBESSFM_EINVAL;
+  if (!p || !field_in || !field_out || T < 1 || batch < 1 || T >= (1LL << 31)) return CBESSFM_EINVAL;
   const char* a = static_cast<const char*>(field_in);
   const char* b = static_cast<const char*>(field_out);
   const long long bytes = (long long)batch * 2 * T * 8;
@@ -427,18 +437,19 @@ int cbessfm_status(cbessfm_plan_t* p) {
 
 int cbessfm_backward_workspace(const cbessfm_plan_t* p, int64_t T, int32_t batch, int32_t checkpoint_every,
                                size_t* bytes) {
-  (void)checkpoint_every;
-  if (!p || !bytes || T < 1 || batch < 1) return CBESSFM_EINVAL;
-  *bytes = 0;
-  return CBESSFM_EUNSUPPORTED;
+  if (!p || !bytes || T < 1 || batch < 1 || T >= (1LL << 31)) return CBESSFM_EINVAL;
+  *bytes = cbessfm::bwd_layout(p, T, batch, checkpoint_every).bytes;
+  return CBESSFM_OK;
 }
 
 int cbessfm_backward(cbessfm_plan_t* p, const void* field_in, const void* grad_out, void* grad_in, float* grad_c,
                      float* grad_rho, int64_t T, int32_t batch, int32_t checkpoint_every, void* workspace,
                      size_t workspace_bytes, void* stream) {
-  (void)p, (void)field_in, (void)grad_out, (void)grad_in, (void)grad_c, (void)grad_rho, (void)T, (void)batch;
-  (void)checkpoint_every, (void)workspace, (void)workspace_bytes, (void)stream;
-  return CBESSFM_EUNSUPPORTED;
+  if (!p || !field_in || !grad_out || !grad_c || !grad_rho || !workspace || T < 1 || batch < 1 ||
+      T >= (1LL << 31))
+    return CBESSFM_EINVAL;
+  return cbessfm::launch_backward(p, field_in, grad_out, grad_in, grad_c, grad_rho, T, batch, checkpoint_every,
+                                  workspace, workspace_bytes, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -1,0 +1,261 @@
+// Block stages shared by the forward and adjoint kernels.
+//
+// Conventions (see fft_lds.hpp for the register layout): a workgroup is
+// member `me` of a team of n_sb workgroups processing one overlap-and-save
+// block; x / y hold the member's two polarisations at positions t + NT o.
+// In the frequency domain the member holds subband `me` in subband order
+// (bin j of subband i is the block bin i N' + j - N/2); at the block's input
+// and output it holds the polyphase component n = n_sb n1 + me.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fft_lds.hpp"
+#include "internal.hpp"
+#include "team.hpp"
+
+namespace cbessfm {
+
+// What a member needs to know about its team and block.
+struct TeamCtx {
+  int nsb, me, team;
+  int n_chunks, nc;
+  XchgCtl ctl;
+  const Tables* tab;
+};
+
+template <int N>
+struct Regs {
+  static constexpr int RR = FftShape<N>::RR, NT = FftShape<N>::NT;
+};
+
+// x / y *= h[t + NT o] (h already offset to the member's subband).
+template <int N, bool CONJ>
+__device__ __forceinline__ void apply_diag(float2 (&x)[FftShape<N>::RR], float2 (&y)[FftShape<N>::RR],
+                                           const float2* __restrict__ h, int t) {
+  constexpr int RR = FftShape<N>::RR, NT = FftShape<N>::NT;
+#pragma unroll
+  for (int o = 0; o < RR; ++o) {
+    const float2 hv = h[t + NT * o];
+    x[o] = CONJ ? cmulc(x[o], hv) : cmul(x[o], hv);
+    y[o] = CONJ ? cmulc(y[o], hv) : cmul(y[o], hv);
+  }
+}
+
+// Gathers the polyphase component `me` of a block of a sequence (both
+// polarisations), times (-1)^n.  Forward use: every sample of the block
+// (framing of Sec. III-A).  KEEP_ONLY: only samples in [n_ov/2, N - n_ov/2)
+// that fall inside [0, T) after the hop offset (the adjoint of the output
+// write); all others read as zero.
+template <int N, bool KEEP_ONLY>
+__device__ __forceinline__ void gather_block(const float2* __restrict__ sx, const float2* __restrict__ sy,
+                                             int blk, int hop, int n_ov, int T, int boundary, int nsb, int me,
+                                             int t, float2 (&x)[FftShape<N>::RR], float2 (&y)[FftShape<N>::RR]) {
+  constexpr int RR = FftShape<N>::RR, NT = FftShape<N>::NT;
+  const int first = KEEP_ONLY ? 0 : frame_first(blk, hop, n_ov, T, boundary);
+  const bool short_seq = T < nsb * N;
+  const int keep_lo = n_ov / 2, keep_hi = nsb * N - n_ov / 2;
+#pragma unroll
+  for (int o = 0; o < RR; ++o) {
+    const int n = nsb * (t + NT * o) + me;
+    int pos;
+    if (KEEP_ONLY) {
+      pos = blk * hop + n - keep_lo;
+      if (n < keep_lo || n >= keep_hi || pos >= T) pos = -1;
+    } else {
+      pos = frame_pos(first, n, T, boundary, short_seq);
+    }
+    float2 vx = make_float2(0.f, 0.f), vy = vx;
+    if (pos >= 0) {
+      vx = sx[pos];
+      vy = sy[pos];
+    }
+    const float sg = (n & 1) ? -1.0f : 1.0f;
+    x[o] = cscale(vx, sg);
+    y[o] = cscale(vy, sg);
+  }
+}
+
+// Writes the kept samples [n_ov/2, N - n_ov/2) of the block's polyphase
+// component `me` (times (-1)^n) to the output sequence.
+template <int N>
+__device__ __forceinline__ void scatter_block(float2* __restrict__ dx, float2* __restrict__ dy, int blk, int hop,
+                                              int n_ov, int T, int nsb, int me, int t,
+                                              const float2 (&x)[FftShape<N>::RR], const float2 (&y)[FftShape<N>::RR]) {
+  constexpr int RR = FftShape<N>::RR, NT = FftShape<N>::NT;
+  const int keep_lo = n_ov / 2, keep_hi = nsb * N - n_ov / 2;
+#pragma unroll
+  for (int o = 0; o < RR; ++o) {
+    const int n = nsb * (t + NT * o) + me;
+    const int pos = blk * hop + n - keep_lo;
+    if (n >= keep_lo && n < keep_hi && pos < T) {
+      const float sg = (n & 1) ? -1.0f : 1.0f;
+      dx[pos] = cscale(x[o], sg);
+      dy[pos] = cscale(y[o], sg);
+    }
+  }
+}
+
+// Publishes this member's four spectrum components (x.re, x.im, y.re, y.im).
+template <int N>
+__device__ __forceinline__ void put_spectrum(uint64_t* dst, const float2 (&x)[FftShape<N>::RR],
+                                             const float2 (&y)[FftShape<N>::RR], unsigned tag, int t) {
+  constexpr int RR = FftShape<N>::RR, NT = FftShape<N>::NT;
+#pragma unroll
+  for (int o = 0; o < RR; ++o) {
+    const int k = t + NT * o;
+    xput(dst + 0 * N + k, x[o].x, tag);
+    xput(dst + 1 * N + k, x[o].y, tag);
+    xput(dst + 2 * N + k, y[o].x, tag);
+    xput(dst + 3 * N + k, y[o].y, tag);
+  }
+}
+
+// x / y = sum over members n2 of w_n2 * (member n2's spectrum),
+// w_n2 = wsb[(n2 me) mod n_sb], conjugated when CONJ.
+template <int N, bool CONJ>
+__device__ __forceinline__ void combine_spectra(const uint64_t* src, const TeamCtx& c, unsigned tag, int t,
+                                                float2 (&x)[FftShape<N>::RR], float2 (&y)[FftShape<N>::RR]) {
+  constexpr int RR = FftShape<N>::RR, NT = FftShape<N>::NT;
+#pragma unroll
+  for (int o = 0; o < RR; ++o) x[o] = y[o] = make_float2(0.f, 0.f);
+  for (int n2 = 0; n2 < c.nsb; ++n2) {
+    const float2 w = c.tab->wsb[(n2 * c.me) % c.nsb];
+    const uint64_t* row = src + (size_t)n2 * 4 * N;
+#pragma unroll
+    for (int comp = 0; comp < 2; ++comp) {  // polarisation x, then y
+      float re[RR], im[RR];
+      xget<RR>(row + (2 * comp) * N, t, NT, tag, c.ctl, re);
+      xget<RR>(row + (2 * comp + 1) * N, t, NT, tag, c.ctl, im);
+#pragma unroll
+      for (int o = 0; o < RR; ++o) {
+        const float2 v = make_float2(re[o], im[o]);
+        const float2 prod = CONJ ? cmulc(v, w) : cmul(v, w);
+        if (comp == 0) x[o] = cadd(x[o], prod);
+        else y[o] = cadd(y[o], prod);
+      }
+    }
+  }
+}
+
+// Polyphase spectra -> subband spectrum: multiply by exp(-j 2 pi me k / N),
+// exchange, n_sb-point DFT across the team (the input DEMUX of
+// Fig. "scheme_CB-ESSFM").  No-op for one subband.
+template <int N>
+__device__ __forceinline__ void polyphase_to_subband(const TeamCtx& c, uint64_t* xs, unsigned tag, int t,
+                                                     float2 (&x)[FftShape<N>::RR], float2 (&y)[FftShape<N>::RR]) {
+  if (c.nsb == 1) return;
+  apply_diag<N, false>(x, y, c.tab->poly_tw + (size_t)c.me * N, t);
+  put_spectrum<N>(xs + (size_t)c.me * 4 * N, x, y, tag, t);
+  combine_spectra<N, false>(xs, c, tag, t, x, y);
+}
+
+// Subband spectra -> polyphase spectra: the inverse direction (the MUX),
+// conjugate weights and twiddles.  No-op for one subband.
+template <int N>
+__device__ __forceinline__ void subband_to_polyphase(const TeamCtx& c, uint64_t* xs, unsigned tag, int t,
+                                                     float2 (&x)[FftShape<N>::RR], float2 (&y)[FftShape<N>::RR]) {
+  if (c.nsb == 1) return;
+  put_spectrum<N>(xs + (size_t)c.me * 4 * N, x, y, tag, t);
+  combine_spectra<N, true>(xs, c, tag, t, x, y);
+  apply_diag<N, true>(x, y, c.tab->poly_tw + (size_t)c.me * N, t);
+}
+
+// Coupled intensity filter of eq. (15) for member `me`, circular over N':
+//   out[k] = sum_l sum_tau crow[l][tau] in_l[(k - tau + nc) mod N'],
+// crow = the member's coefficient rows ([n_sb][8 n_chunks], zero padded).
+// own: this member's row at positions t + NT o; the other rows come from the
+// tagged exchange `xrow` ([n_sb][N'], round `tag`).  Result at t + NT o.
+template <int N>
+__device__ __forceinline__ void coupled_fir(const TeamCtx& c, const float* __restrict__ crow, uint64_t* xrow,
+                                           unsigned tag, const float (&own)[FftShape<N>::RR],
+                                           float (&out)[FftShape<N>::RR], float* lf) {
+  constexpr int RR = FftShape<N>::RR, NT = FftShape<N>::NT;
+  constexpr int PB = NlprLds<N>::PB;  // row l lives at lf + (l & 1) * PB
+  const int t = opaque_tid();
+  const int nsb = c.nsb, me = c.me, nc = c.nc;
+  const int tap_pad = kTapChunk * c.n_chunks;
+  const int hl = tap_pad - 1 - nc;  // left halo of the circular extension
+  float* th = lf + 2 * PB;
+
+  if (nsb > 1) {
+#pragma unroll
+    for (int o = 0; o < RR; ++o) xput(xrow + (size_t)me * N + t + NT * o, own[o], tag);
+  }
+  __syncthreads();  // the LDS rows alias the FFT exchange buffers
+  {
+    float v[RR];
+    if (nsb > 1 && me != 0) {
+      xget<RR>(xrow, t, NT, tag, c.ctl, v);
+      stage_row<N, RR, NT>(lf, v, t, hl, nc);
+    } else {
+      stage_row<N, RR, NT>(lf, own, t, hl, nc);
+    }
+  }
+  __syncthreads();
+
+  float acc[RR];
+#pragma unroll
+  for (int q = 0; q < RR; ++q) acc[q] = 0.0f;
+  for (int l = 0; l < nsb; ++l) {
+    const float* cur = lf + (l & 1) * PB;
+    const bool fetch = (l + 1 < nsb) && (l + 1 != me);  // next row is remote
+    uint64_t w[RR];
+    if (fetch) xissue<RR>(xrow + (size_t)(l + 1) * N, t, NT, w);  // in flight during the filter
+    const float* cl = crow + (size_t)l * tap_pad;
+    for (int ch = 0; ch < c.n_chunks; ++ch) {
+      // window i in [0, RR + 7): row index t RR + i - 7 - 8 ch + nc, stored at + hl
+      float win[RR + kTapChunk - 1];
+      const int base = t * RR - (kTapChunk - 1) - kTapChunk * ch + nc + hl;
+#pragma unroll
+      for (int i = 0; i < RR + kTapChunk - 1; ++i) win[i] = cur[pad_f(base + i)];
+#pragma unroll
+      for (int tt = 0; tt < kTapChunk; ++tt) {
+        const float cf = cl[kTapChunk * ch + tt];
+#pragma unroll
+        for (int q = 0; q < RR; ++q) acc[q] = fmaf(cf, win[q - tt + kTapChunk - 1], acc[q]);
+      }
+    }
+    if (l + 1 < nsb) {
+      if (fetch) {
+        float v[RR];
+        xcomplete<RR>(xrow + (size_t)(l + 1) * N, t, NT, tag, c.ctl, w, v);
+        stage_row<N, RR, NT>(lf + ((l + 1) & 1) * PB, v, t, hl, nc);
+      } else {
+        stage_row<N, RR, NT>(lf + ((l + 1) & 1) * PB, own, t, hl, nc);
+      }
+    }
+    __syncthreads();
+  }
+  // block mapping (t RR + q) -> owned positions (t + NT o)
+#pragma unroll
+  for (int q = 0; q < RR; ++q) th[pad_f(t * RR + q)] = acc[q];
+  __syncthreads();
+#pragma unroll
+  for (int o = 0; o < RR; ++o) out[o] = th[pad_f(t + NT * o)];
+}
+
+// x / y *= exp(-+ j theta): '-' (SIGN = -1) is the rotation of eq. (3).
+template <int N, int SIGN>
+__device__ __forceinline__ void rotate(float2 (&x)[FftShape<N>::RR], float2 (&y)[FftShape<N>::RR],
+                                       const float (&theta)[FftShape<N>::RR]) {
+  constexpr int RR = FftShape<N>::RR;
+#pragma unroll
+  for (int o = 0; o < RR; ++o) {
+    float sn, cs;
+    sincosf(theta[o], &sn, &cs);
+    const float2 r = make_float2(cs, SIGN < 0 ? -sn : sn);
+    x[o] = cmul(x[o], r);
+    y[o] = cmul(y[o], r);
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void intensity(const float2 (&x)[FftShape<N>::RR], const float2 (&y)[FftShape<N>::RR],
+                                          float (&p)[FftShape<N>::RR]) {
+#pragma unroll
+  for (int o = 0; o < FftShape<N>::RR; ++o)
+    p[o] = x[o].x * x[o].x + x[o].y * x[o].y + y[o].x * y[o].x + y[o].y * y[o].y;
+}
+
+}  // namespace cbessfm

@@ -113,12 +113,14 @@ __device__ __forceinline__ int frame_first(int blk, int hop, int n_ov, int T, in
 }
 
 // LDS of the nonlinear stage (aliases the FFT exchange buffers): two rows of
-// circularly extended intensities and one row of phases, in floats.
+// circularly extended intensities, one row of phases and the per-wave tap
+// sums of the coefficient gradient, in floats.
 template <int N>
 struct NlprLds {
   static constexpr int PB = pad_f_size(N + kMaxTaps + 2 * kTapChunk);
   static constexpr int TH = pad_f_size(N);
-  static constexpr int FLOATS = 2 * PB + TH;
+  static constexpr int RED = (kMaxTaps + 1) * (FftShape<N>::NT / 64);  // per-wave tap sums (adjoint)
+  static constexpr int FLOATS = 2 * PB + TH + RED;
 };
 template <int N>
 constexpr int lds_floats() {

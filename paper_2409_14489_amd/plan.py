@@ -163,6 +163,41 @@ class Plan:
     def set_split_ratio(self, rho: float, stream=None):
         check(lib.cbessfm_set_split_ratio(self._h, float(rho), _stream_ptr(stream)), "cbessfm_set_split_ratio")
 
+    def backward_workspace(self, t_len: int, batch: int = 1, checkpoint_every: int = 1) -> int:
+        """Device workspace bytes of :meth:`backward` (``cbessfm_backward_workspace``)."""
+        out = ctypes.c_size_t()
+        check(lib.cbessfm_backward_workspace(self._h, int(t_len), int(batch), int(checkpoint_every),
+                                             ctypes.byref(out)), "cbessfm_backward_workspace")
+        return out.value
+
+    def backward(self, field_in: torch.Tensor, grad_out: torch.Tensor, need_grad_in: bool = True,
+                 checkpoint_every: int = 1, workspace: torch.Tensor | None = None, stream=None):
+        """(grad_in or None, grad_c [steps][n_sb][n_sb][n_taps], grad_rho [1]) for the current
+        coefficients and split ratio, given grad_out = dL/dRe(out) + j dL/dIm(out)."""
+        x = self._field(field_in)
+        g = self._field(grad_out)
+        if g.shape != x.shape:
+            raise ValueError("grad_out must be shaped like field_in")
+        bsz = 1 if x.dim() == 2 else x.shape[0]
+        t_len = x.shape[-1]
+        need = self.backward_workspace(t_len, bsz, checkpoint_every)
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device=x.device)
+        elif workspace.numel() * workspace.element_size() < need or not workspace.is_cuda:
+            raise ValueError(f"workspace must be a CUDA tensor of at least {need} bytes")
+        grad_in = torch.empty_like(x) if need_grad_in else None
+        grad_c = torch.empty((self.steps, self.n_sb, self.n_sb, self.n_taps), dtype=torch.float32,
+                             device=x.device)
+        grad_rho = torch.empty(1, dtype=torch.float32, device=x.device)
+        gi_ptr = ctypes.c_void_p(grad_in.data_ptr()) if grad_in is not None else ctypes.c_void_p(0)
+        check(lib.cbessfm_backward(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(g.data_ptr()), gi_ptr,
+                                   ctypes.c_void_p(grad_c.data_ptr()), ctypes.c_void_p(grad_rho.data_ptr()),
+                                   int(t_len), int(bsz), int(checkpoint_every),
+                                   ctypes.c_void_p(workspace.data_ptr()),
+                                   ctypes.c_size_t(workspace.numel() * workspace.element_size()),
+                                   _stream_ptr(stream)), "cbessfm_backward")
+        return grad_in, grad_c, grad_rho
+
     def status(self) -> int:
         return lib.cbessfm_status(self._h)
 
