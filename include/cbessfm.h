@@ -36,6 +36,9 @@
  *     and backward are asynchronous on that stream and allocate nothing.
  *   - A plan may be used by one stream at a time; calls that overlap on one
  *     plan race on its exchange buffers.
+ *   - run and backward keep no host-side state between calls (the exchange
+ *     round counters live in device memory), so they may be recorded in a HIP
+ *     graph and replayed.
  */
 #ifndef CBESSFM_H
 #define CBESSFM_H
@@ -53,7 +56,7 @@ enum {
   CBESSFM_EUNSUPPORTED = -2,/* a size this build does not implement */
   CBESSFM_ENOMEM = -3,      /* device or host allocation failed */
   CBESSFM_EHIP = -4,        /* a HIP runtime call failed */
-  CBESSFM_ESYNC = -5,       /* a device-side team barrier gave up waiting */
+  CBESSFM_ESYNC = -5,       /* a device-side exchange wait gave up */
   CBESSFM_EWORKSPACE = -6   /* caller workspace too small */
 };
 
@@ -160,7 +163,8 @@ int cbessfm_analytic_coeffs(const cbessfm_link* link, const cbessfm_subbands* sb
 int cbessfm_plan_info(const cbessfm_plan_t* plan, cbessfm_info* out);
 
 /* Synchronises the plan's device, returns and clears the sticky device error
- * flag (CBESSFM_ESYNC if a team barrier gave up since the last call). */
+ * flag (CBESSFM_ESYNC if an exchange wait gave up since the last call; the
+ * plan's exchange state is then reset as well). */
 int cbessfm_status(cbessfm_plan_t* plan);
 
 /* Releases the plan and all its device memory (NULL is a no-op). */
@@ -168,6 +172,114 @@ void cbessfm_destroy(cbessfm_plan_t* plan);
 
 /* Static description of an error code. */
 const char* cbessfm_strerror(int code);
+
+/* ------------------------------------------------------------------ batches
+ * Many instances in one persistent launch per distinct N' (one launch when
+ * all instances share N').  An instance is a plan -- its own link, subband
+ * count, steps, split ratio and coefficients -- with its own fields, length
+ * and batch count; the batch computes for every instance exactly what
+ * cbessfm_run would (Sec. III-A / III-C).  Workgroups form static teams of the
+ * width (n_sb) of the instances they run; every team is placed on one XCD,
+ * the number of teams of each width balances the predicted work, and blocks
+ * are dealt to teams longest first (cbessfm_schedule).  A run allocates
+ * nothing and keeps no host-side state between launches, so it may be
+ * recorded in a HIP graph and replayed.
+ */
+typedef struct {
+  cbessfm_plan_t* plan;    /* the instance's plan, on the current device; must outlive the batch */
+  const void* field_in;    /* device complex float32 [batch][2][T] */
+  void* field_out;         /* device, same shape; may not overlap any field of the batch */
+  int64_t T;               /* samples per polarisation, 1 <= T < 2^31 */
+  int32_t batch;           /* >= 1 */
+} cbessfm_instance;
+
+typedef struct cbessfm_batch cbessfm_batch_t;
+
+typedef struct {
+  int32_t launches;        /* persistent launches per run (distinct N') */
+  int32_t teams;           /* teams over all launches */
+  int32_t workgroups;      /* summed grid sizes */
+  int64_t items;           /* overlap-and-save blocks over all instances */
+  double makespan_s;       /* predicted run time: summed over launches, max over teams */
+  double lower_bound_s;    /* a lower bound of makespan_s for the same item costs */
+} cbessfm_batch_info;
+
+/* Builds the schedule and the device tables of a batch on the current
+ * device (synchronous).  Field pointers are bound now: every run reads and
+ * writes the same buffers.  Item costs come from the autotuner's device
+ * timings when cbessfm_autotune(..., CBESSFM_TUNE_MEASURE, ...) has run for
+ * the shape, else from an operation-count model.  Errors: CBESSFM_EINVAL for
+ * null or out-of-range arguments, a plan of another device or overlapping
+ * fields; CBESSFM_ENOMEM; CBESSFM_EHIP.  *out is NULL on failure. */
+int cbessfm_batch_create(cbessfm_batch_t** out, const cbessfm_instance* inst, int32_t n);
+
+/* Runs every instance of the batch: asynchronous on stream, no allocation,
+ * graph-capturable (inside a capture the launches are recorded as ordinary
+ * kernel nodes of resident-sized grids).  Runs of one batch that overlap in
+ * time race on its exchange buffers. */
+int cbessfm_batch_run(cbessfm_batch_t* b, void* stream);
+
+/* Schedule summary of a batch. */
+int cbessfm_batch_describe(const cbessfm_batch_t* b, cbessfm_batch_info* out);
+
+/* As cbessfm_status, for the batch's own exchange state. */
+int cbessfm_batch_status(cbessfm_batch_t* b);
+
+/* Releases the batch (not its plans or fields; NULL is a no-op). */
+void cbessfm_batch_destroy(cbessfm_batch_t* b);
+
+/* The batch scheduler on its own (host only, no device).  Job j has n_items
+ * blocks of predicted cost `cost` each, run by teams of `width` workgroups.
+ * slots_per_xcd: resident workgroups per XCD.  Outputs (caller-allocated):
+ * wg_team / wg_member [max_wg] give each workgroup's team and member index
+ * (-1: idle) for workgroups 0 .. grid - 1, workgroup w running on XCD w mod 8;
+ * item_team / item_rank [sum of n_items] give each block's team and its
+ * position in that team's sequence (blocks numbered job by job).  Either pair
+ * may be NULL.  Errors: CBESSFM_EINVAL (bad job, no blocks, grid > max_wg),
+ * CBESSFM_EUNSUPPORTED (a width that does not fit one XCD). */
+typedef struct {
+  int32_t width;
+  int64_t n_items;
+  double cost;
+} cbessfm_sched_job;
+
+typedef struct {
+  int32_t grid;            /* workgroups to launch */
+  int32_t n_teams;
+  double makespan;         /* max over teams of the summed cost of its blocks */
+  double lower_bound;      /* max(largest block cost, total cost x width / workgroup slots) */
+} cbessfm_sched_stats;
+
+int cbessfm_schedule(const cbessfm_sched_job* jobs, int32_t n_jobs, int32_t slots_per_xcd, int32_t max_wg,
+                     int32_t* wg_team, int32_t* wg_member, int32_t* item_team, int32_t* item_rank,
+                     cbessfm_sched_stats* stats);
+
+/* ------------------------------------------------------------------ autotuner
+ * Picks N' and N_ov for one instance.  The overlap must cover the memory of
+ * the accumulated dispersion of the backpropagated link, taken as
+ * 2 pi |beta2| L R^2 full-field samples (the group-delay spread of a band R
+ * over L; Sec. III-A), rounded up to even.  Among the N' in [256, 8192] whose
+ * block N = n_sb N' exceeds it, the one with the least predicted time for the
+ * instance (blocks / resident teams, rounded up, times the time of one block)
+ * wins.  If no N' covers the memory, N' = 8192 with N_ov = min(memory, N / 2)
+ * is returned with covered = 0.  flags: CBESSFM_TUNE_MEASURE times each
+ * candidate block shape on the current device (probe launches of one block
+ * per resident team at 1 and 4 steps, linear in the step count; cached per
+ * device and shape for the process); 0 uses an operation-count model and
+ * touches no device.  Errors: CBESSFM_EINVAL, CBESSFM_EHIP. */
+enum { CBESSFM_TUNE_MEASURE = 1 };
+
+typedef struct {
+  int32_t block_sb;        /* chosen N' */
+  int32_t overlap;         /* chosen N_ov, full-field samples, even */
+  int32_t memory;          /* dispersion memory, full-field samples */
+  int32_t covered;         /* 1 if overlap >= memory */
+  int32_t measured;        /* 1 if the prediction uses device timings */
+  double predicted_s;      /* predicted time of one cbessfm_run of the instance */
+} cbessfm_tuning;
+
+int cbessfm_autotune(const cbessfm_link* link, int32_t n_sb, int32_t steps, int32_t n_taps, int64_t T,
+                     int32_t batch, int32_t flags, cbessfm_tuning* out);
 
 #ifdef __cplusplus
 }

@@ -11,6 +11,7 @@ _PUBLIC = {
     "LinkSpec": "plan", "Plan": "plan", "analytic_coeffs": "plan", "plan_check": "plan",
     "CbessfmError": "_lib", "EXPORTED": "_lib", "LIB_PATH": "_lib",
     "CBESSFMFunction": "autograd", "cbessfm": "autograd",
+    "Batch": "batch", "schedule": "batch", "autotune": "batch",
 }
 
 __all__ = sorted(_PUBLIC)

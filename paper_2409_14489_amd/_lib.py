@@ -18,7 +18,11 @@ EXPORTED = (
     "cbessfm_plan_check", "cbessfm_plan", "cbessfm_set_coeffs", "cbessfm_set_split_ratio",
     "cbessfm_run", "cbessfm_backward_workspace", "cbessfm_backward", "cbessfm_analytic_coeffs",
     "cbessfm_plan_info", "cbessfm_status", "cbessfm_destroy", "cbessfm_strerror",
+    "cbessfm_batch_create", "cbessfm_batch_run", "cbessfm_batch_describe", "cbessfm_batch_status",
+    "cbessfm_batch_destroy", "cbessfm_schedule", "cbessfm_autotune",
 )
+
+TUNE_MEASURE = 1
 
 
 class Link(ctypes.Structure):
@@ -44,6 +48,30 @@ class Info(ctypes.Structure):
                 ("n_taps", ctypes.c_int32), ("threads_per_group", ctypes.c_int32),
                 ("team_capacity", ctypes.c_int32), ("step_km", ctypes.c_double),
                 ("split_ratio", ctypes.c_double)]
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("field_in", ctypes.c_void_p), ("field_out", ctypes.c_void_p),
+                ("T", ctypes.c_int64), ("batch", ctypes.c_int32)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int32), ("teams", ctypes.c_int32), ("workgroups", ctypes.c_int32),
+                ("items", ctypes.c_int64), ("makespan_s", ctypes.c_double), ("lower_bound_s", ctypes.c_double)]
+
+
+class SchedJob(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("n_items", ctypes.c_int64), ("cost", ctypes.c_double)]
+
+
+class SchedStats(ctypes.Structure):
+    _fields_ = [("grid", ctypes.c_int32), ("n_teams", ctypes.c_int32), ("makespan", ctypes.c_double),
+                ("lower_bound", ctypes.c_double)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("block_sb", ctypes.c_int32), ("overlap", ctypes.c_int32), ("memory", ctypes.c_int32),
+                ("covered", ctypes.c_int32), ("measured", ctypes.c_int32), ("predicted_s", ctypes.c_double)]
 
 
 class CbessfmError(RuntimeError):
@@ -72,6 +100,14 @@ def _load() -> ctypes.CDLL:
         "cbessfm_status": ([P], ctypes.c_int),
         "cbessfm_destroy": ([P], None),
         "cbessfm_strerror": ([ctypes.c_int], ctypes.c_char_p),
+        "cbessfm_batch_create": ([ctypes.POINTER(P), ctypes.POINTER(Instance), i32], ctypes.c_int),
+        "cbessfm_batch_run": ([P, P], ctypes.c_int),
+        "cbessfm_batch_describe": ([P, ctypes.POINTER(BatchInfo)], ctypes.c_int),
+        "cbessfm_batch_status": ([P], ctypes.c_int),
+        "cbessfm_batch_destroy": ([P], None),
+        "cbessfm_schedule": ([ctypes.POINTER(SchedJob), i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                              ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(SchedStats)], ctypes.c_int),
+        "cbessfm_autotune": ([LP, i32, i32, i32, i64, i32, i32, ctypes.POINTER(Tuning)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

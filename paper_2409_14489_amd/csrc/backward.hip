@@ -177,6 +177,7 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void bwd_kernel(BwdArgs 
   constexpr int RR = S::RR, NT = S::NT, NW = NT / 64;
   __shared__ __align__(16) float lf[lds_floats<N>()];
   __shared__ double rho_red[NW];
+  __shared__ unsigned epoch_word;
   float2* lx = reinterpret_cast<float2*>(lf);
   float2* ly = lx + S::LDS_C;
 
@@ -201,11 +202,12 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void bwd_kernel(BwdArgs 
   uint64_t* xs_a = a.xspec + ((size_t)c.team * 2 + 0) * nsb * 4 * N;
   uint64_t* xs_b = a.xspec + ((size_t)c.team * 2 + 1) * nsb * 4 * N;
   const double* phase_km = a.phase + (size_t)me * N;
+  const unsigned first = epoch_begin(a.epoch + c.team, &epoch_word);
 
   unsigned iter = 0;
   for (int item = c.team; item < a.n_items; item += a.n_teams, ++iter) {
     int t = opaque_tid();
-    unsigned rnd = a.tag_base + iter * a.rounds_per_item;
+    unsigned rnd = first + iter * a.rounds_per_item;
     unsigned np = 0, nq = 0;  // p- and theta_bar-rounds so far (slot parity)
     const int inst = item / a.nblk;
     const int blk = item - inst * a.nblk;
@@ -336,6 +338,7 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void bwd_kernel(BwdArgs 
       }
     }
   }
+  epoch_end(a.epoch + c.team, first, iter * a.rounds_per_item, me);
 }
 
 // ------------------------------------------------------------------ reductions
@@ -411,8 +414,10 @@ __global__ void gather_gin_kernel(const float2* __restrict__ blk_g, float2* __re
 template <int LOGN>
 static int launch_bwd_t(const BwdArgs& args, int grid, hipStream_t s) {
   void* kargs[] = {(void*)&args};
-  hipError_t e = hipLaunchCooperativeKernel((const void*)bwd_kernel<LOGN>, dim3(grid),
-                                            dim3(FftShape<(1 << LOGN)>::NT), kargs, 0, s);
+  const dim3 threads(FftShape<(1 << LOGN)>::NT);
+  hipError_t e = stream_capturing(s)
+                     ? hipLaunchKernel((const void*)bwd_kernel<LOGN>, dim3(grid), threads, kargs, 0, s)
+                     : hipLaunchCooperativeKernel((const void*)bwd_kernel<LOGN>, dim3(grid), threads, kargs, 0, s);
   return e == hipSuccess ? CBESSFM_OK : CBESSFM_EHIP;
 }
 
@@ -491,9 +496,7 @@ int launch_backward(cbessfm_plan_t* p, const void* field_in, const void* grad_ou
   a.ctl.err = p->d_err;
   a.ctl.spin_limit = 1u << 22;
   a.rounds_per_item = 4u * (unsigned)p->steps + 4u;
-  const unsigned per_team = (unsigned)((a.n_items + a.n_teams - 1) / a.n_teams);
-  a.tag_base = take_tags(p, per_team * a.rounds_per_item, s);
-  if (a.tag_base == 0u) return CBESSFM_EHIP;
+  a.epoch = p->d_epoch;
   const int groups = (a.n_teams + kXcds - 1) / kXcds;
   const int grid = groups * kXcds * a.n_sb;
   int rc;

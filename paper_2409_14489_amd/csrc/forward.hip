@@ -19,69 +19,117 @@
 
 namespace cbessfm {
 
+// One overlap-and-save block of one instance, as member c.me of a team.
+// sub = batch entry * nblk + block; the team's exchange rounds for this block
+// are round0 .. round0 + steps + 1.  xs_in / xs_out: the team's two spectrum
+// slots; xp_team: its two intensity-row slots.
+template <int N>
+__device__ __forceinline__ void fwd_item(TeamCtx& c, const Inst& d, int sub, unsigned round0, uint64_t* xs_in,
+                                         uint64_t* xs_out, uint64_t* xp_team, float* lf) {
+  using S = FftShape<N>;
+  constexpr int RR = S::RR;
+  float2* lx = reinterpret_cast<float2*>(lf);
+  float2* ly = lx + S::LDS_C;
+  const int nsb = c.nsb, me = c.me;
+  const float2* tw = d.tab.tw;
+  const int T = d.T;
+  const int tap_pad = kTapChunk * d.n_chunks;
+  const int inst = sub / d.nblk;
+  const int blk = sub - inst * d.nblk;
+  const float2* in_x = d.in + (size_t)inst * 2 * T;
+  int t = opaque_tid();
+  float2 x[RR], y[RR];
+
+  // ---- block input: size-N DFT as N_sb polyphase FFTs + N_sb-point DFT
+  gather_block<N, false>(in_x, in_x + T, blk, d.hop, d.n_ov, T, d.boundary, nsb, me, t, x, y);
+  fft<N, false>(x, y, lx, ly, tw, t);
+  polyphase_to_subband<N>(c, xs_in, round0, t, x, y);
+
+  // ---- step loop (Fig. "scheme_CB-ESSFM"), spectra in subband order
+  for (int s = 0; s < d.steps; ++s) {
+    t = opaque_tid();
+    apply_diag<N, false>(x, y, (s == 0 ? d.tab.h_first : d.tab.h_mid) + (size_t)me * N, t);
+    fft<N, true>(x, y, lx, ly, tw, t);  // lowpass-equivalent subband samples
+    float p[RR], theta[RR];
+    intensity<N>(x, y, p);
+    const unsigned round = round0 + 1u + (unsigned)s;
+    uint64_t* xrow = xp_team + (size_t)(round & 1u) * nsb * N;
+    coupled_fir<N>(c, d.tab.cpad + ((size_t)(s * nsb + me) * nsb) * tap_pad, xrow, round, p, theta, lf);
+    rotate<N, -1>(x, y, theta);
+    fft<N, false>(x, y, lx, ly, tw, t);
+  }
+
+  // ---- final GVD, recombination, inverse size-N DFT, kept samples
+  t = opaque_tid();
+  apply_diag<N, false>(x, y, d.tab.h_last + (size_t)me * N, t);
+  subband_to_polyphase<N>(c, xs_out, round0 + (unsigned)d.steps + 1u, t, x, y);
+  fft<N, true>(x, y, lx, ly, tw, t);
+  float2* out_x = d.out + (size_t)inst * 2 * T;
+  scatter_block<N>(out_x, out_x + T, blk, d.hop, d.n_ov, T, nsb, me, t, x, y);
+}
+
+// Single plan: team j takes blocks j, j + n_teams, ...  The n_sb members of a
+// team share blockIdx mod 8, i.e. one XCD and its L2 (workgroups are dispatched
+// round-robin over the 8 XCDs).
 template <int LOGN>
 __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void fwd_kernel(FwdArgs a) {
   constexpr int N = 1 << LOGN;  // N'
-  using S = FftShape<N>;
-  constexpr int RR = S::RR;
   __shared__ __align__(16) float lf[lds_floats<N>()];
-  float2* lx = reinterpret_cast<float2*>(lf);
-  float2* ly = lx + S::LDS_C;
+  __shared__ unsigned epoch_word;
 
   TeamCtx c;
-  c.nsb = a.n_sb;
-  // XCD-aware mapping: the n_sb members of a team share blockIdx mod 8
+  c.nsb = a.inst.n_sb;
   const int r = blockIdx.x / kXcds;
   c.me = r % c.nsb;
   c.team = (r / c.nsb) * kXcds + blockIdx.x % kXcds;
   if (c.team >= a.n_teams) return;
-  c.n_chunks = a.n_chunks;
-  c.nc = a.nc;
+  c.n_chunks = a.inst.n_chunks;
+  c.nc = a.inst.nc;
   c.ctl = a.ctl;
-  c.tab = &a.tab;
-  const int nsb = c.nsb, me = c.me;
-  const float2* tw = a.tab.tw;
-  const int T = a.T;
-  const int tap_pad = kTapChunk * a.n_chunks;
-  const unsigned rounds_per_item = (unsigned)a.steps + 2u;
+  c.tab = &a.inst.tab;
+  const int nsb = c.nsb;
+  const unsigned rounds_per_item = (unsigned)a.inst.steps + 2u;
   uint64_t* xs_in = a.xspec + ((size_t)c.team * 2 + 0) * nsb * 4 * N;
   uint64_t* xs_out = a.xspec + ((size_t)c.team * 2 + 1) * nsb * 4 * N;
+  uint64_t* xp_team = a.xp + (size_t)c.team * 2 * nsb * N;
+  const unsigned first = epoch_begin(a.epoch + c.team, &epoch_word);
   unsigned iter = 0;
-  for (int item = c.team; item < a.n_items; item += a.n_teams, ++iter) {
-    int t = opaque_tid();
-    const unsigned round0 = a.tag_base + iter * rounds_per_item;
-    const int inst = item / a.nblk;
-    const int blk = item - inst * a.nblk;
-    const float2* in_x = a.in + (size_t)inst * 2 * T;
-    float2 x[RR], y[RR];
+  for (int item = c.team; item < a.n_items; item += a.n_teams, ++iter)
+    fwd_item<N>(c, a.inst, item, first + iter * rounds_per_item, xs_in, xs_out, xp_team, lf);
+  epoch_end(a.epoch + c.team, first, iter * rounds_per_item, c.me);
+}
 
-    // ---- block input: size-N DFT as N_sb polyphase FFTs + N_sb-point DFT
-    gather_block<N, false>(in_x, in_x + T, blk, a.hop, a.n_ov, T, a.boundary, nsb, me, t, x, y);
-    fft<N, false>(x, y, lx, ly, tw, t);
-    polyphase_to_subband<N>(c, xs_in, round0, t, x, y);
+// Batch: workgroup -> (team, member) and team -> items come from a schedule
+// built on the host; the instances of one team all have the team's n_sb and
+// this kernel's N'.
+template <int LOGN>
+__global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void fwd_batch_kernel(BatchArgs a) {
+  constexpr int N = 1 << LOGN;
+  __shared__ __align__(16) float lf[lds_floats<N>()];
+  __shared__ unsigned epoch_word;
 
-    // ---- step loop (Fig. "scheme_CB-ESSFM"), spectra in subband order
-    for (int s = 0; s < a.steps; ++s) {
-      t = opaque_tid();
-      apply_diag<N, false>(x, y, (s == 0 ? a.tab.h_first : a.tab.h_mid) + (size_t)me * N, t);
-      fft<N, true>(x, y, lx, ly, tw, t);  // lowpass-equivalent subband samples
-      float p[RR], theta[RR];
-      intensity<N>(x, y, p);
-      const unsigned round = round0 + 1u + (unsigned)s;
-      uint64_t* xrow = a.xp + ((size_t)c.team * 2 + (round & 1u)) * nsb * N;
-      coupled_fir<N>(c, a.tab.cpad + ((size_t)(s * nsb + me) * nsb) * tap_pad, xrow, round, p, theta, lf);
-      rotate<N, -1>(x, y, theta);
-      fft<N, false>(x, y, lx, ly, tw, t);
-    }
-
-    // ---- final GVD, recombination, inverse size-N DFT, kept samples
-    t = opaque_tid();
-    apply_diag<N, false>(x, y, a.tab.h_last + (size_t)me * N, t);
-    subband_to_polyphase<N>(c, xs_out, round0 + rounds_per_item - 1u, t, x, y);
-    fft<N, true>(x, y, lx, ly, tw, t);
-    float2* out_x = a.out + (size_t)inst * 2 * T;
-    scatter_block<N>(out_x, out_x + T, blk, a.hop, a.n_ov, T, nsb, me, t, x, y);
+  const int2 wg = a.wg[blockIdx.x];
+  if (wg.x < 0) return;
+  const BatchTeam& tm = a.teams[wg.x];
+  TeamCtx c;
+  c.nsb = tm.width;
+  c.me = wg.y;
+  c.team = wg.x;
+  c.ctl = a.ctl;
+  uint64_t* xs_in = a.xspec + tm.xspec_off;
+  uint64_t* xs_out = xs_in + (size_t)c.nsb * 4 * N;
+  uint64_t* xp_team = a.xp + tm.xp_off;
+  unsigned* epoch = a.epoch + tm.epoch_slot;
+  const unsigned first = epoch_begin(epoch, &epoch_word);
+  for (int k = 0; k < tm.count; ++k) {
+    const BatchItem it = a.items[tm.first + k];
+    const Inst& d = a.insts[it.inst];
+    c.n_chunks = d.n_chunks;
+    c.nc = d.nc;
+    c.tab = &d.tab;
+    fwd_item<N>(c, d, it.sub, first + it.round_off, xs_in, xs_out, xp_team, lf);
   }
+  epoch_end(epoch, first, tm.rounds, c.me);
 }
 
 // ------------------------------------------------------------------ tables
@@ -136,12 +184,49 @@ __global__ void pad_coeffs_kernel(const float* __restrict__ src, float* __restri
 __global__ void copy_rho_kernel(const float* __restrict__ src, double* __restrict__ dst) { *dst = (double)*src; }
 
 // ------------------------------------------------------------------ launchers
+// True when `s` is recording a graph.  Cooperative launches guarantee that
+// the whole grid is resident; inside a capture an ordinary launch of the same
+// (resident-sized) grid is recorded instead.
+bool stream_capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return st != hipStreamCaptureStatusNone;
+}
+
+template <typename K, typename A>
+static int launch_persistent(K kernel, const A& args, int grid, int threads, hipStream_t s) {
+  void* kargs[] = {(void*)&args};
+  hipError_t e;
+  if (stream_capturing(s))
+    e = hipLaunchKernel((const void*)kernel, dim3(grid), dim3(threads), kargs, 0, s);
+  else
+    e = hipLaunchCooperativeKernel((const void*)kernel, dim3(grid), dim3(threads), kargs, 0, s);
+  return e == hipSuccess ? CBESSFM_OK : CBESSFM_EHIP;
+}
+
 template <int LOGN>
 static int launch_fwd_t(const FwdArgs& args, int grid, hipStream_t s) {
-  void* kargs[] = {(void*)&args};
-  hipError_t e = hipLaunchCooperativeKernel((const void*)fwd_kernel<LOGN>, dim3(grid),
-                                            dim3(FftShape<(1 << LOGN)>::NT), kargs, 0, s);
-  return e == hipSuccess ? CBESSFM_OK : CBESSFM_EHIP;
+  return launch_persistent(fwd_kernel<LOGN>, args, grid, FftShape<(1 << LOGN)>::NT, s);
+}
+
+template <int LOGN>
+static int launch_batch_t(const BatchArgs& args, int grid, hipStream_t s) {
+  return launch_persistent(fwd_batch_kernel<LOGN>, args, grid, FftShape<(1 << LOGN)>::NT, s);
+}
+
+int launch_batch(int log_np, const BatchArgs& a, int grid, hipStream_t s) {
+  switch (log_np) {
+    case 8: return launch_batch_t<8>(a, grid, s);
+    case 9: return launch_batch_t<9>(a, grid, s);
+    case 10: return launch_batch_t<10>(a, grid, s);
+    case 11: return launch_batch_t<11>(a, grid, s);
+    case 12: return launch_batch_t<12>(a, grid, s);
+    case 13: return launch_batch_t<13>(a, grid, s);
+    default: return CBESSFM_EUNSUPPORTED;
+  }
 }
 
 int threads_for(int log_np) {
@@ -162,6 +247,26 @@ static int occ_t(int* blocks) {
                  hipSuccess
              ? CBESSFM_OK
              : CBESSFM_EHIP;
+}
+
+template <int LOGN>
+static int bocc_t(int* blocks) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fwd_batch_kernel<LOGN>, FftShape<(1 << LOGN)>::NT,
+                                                      0) == hipSuccess
+             ? CBESSFM_OK
+             : CBESSFM_EHIP;
+}
+
+int batch_occupancy_per_cu(int log_np, int* blocks) {
+  switch (log_np) {
+    case 8: return bocc_t<8>(blocks);
+    case 9: return bocc_t<9>(blocks);
+    case 10: return bocc_t<10>(blocks);
+    case 11: return bocc_t<11>(blocks);
+    case 12: return bocc_t<12>(blocks);
+    case 13: return bocc_t<13>(blocks);
+    default: return CBESSFM_EUNSUPPORTED;
+  }
 }
 
 int occupancy_per_cu(int log_np, int* blocks) {
@@ -186,32 +291,35 @@ void fill_tables(const cbessfm_plan_t* p, Tables& tb) {
   for (int i = 0; i < kMaxSubbands; ++i) tb.wsb[i] = p->wsb[i];
 }
 
+void fill_inst(const cbessfm_plan_t* p, const void* in, void* out, long long T, int batch, Inst& d) {
+  (void)batch;
+  d.in = static_cast<const float2*>(in);
+  d.out = static_cast<float2*>(out);
+  d.T = (int)T;
+  d.nblk = (int)((T + p->hop - 1) / p->hop);
+  d.n_sb = p->sb.n_sb;
+  d.steps = p->steps;
+  d.n_chunks = p->n_chunks;
+  d.nc = p->n_taps / 2;
+  d.n_ov = p->sb.overlap;
+  d.hop = p->hop;
+  d.boundary = p->sb.boundary;
+  fill_tables(p, d.tab);
+}
+
 int launch_forward(cbessfm_plan_t* p, const void* in, void* out, long long T, int batch, hipStream_t s) {
   FwdArgs a;
-  a.in = static_cast<const float2*>(in);
-  a.out = static_cast<float2*>(out);
-  a.T = (int)T;
-  a.nblk = (int)((T + p->hop - 1) / p->hop);
-  a.n_items = batch * a.nblk;
-  a.n_sb = p->sb.n_sb;
-  a.steps = p->steps;
-  a.n_chunks = p->n_chunks;
-  a.nc = p->n_taps / 2;
-  a.n_ov = p->sb.overlap;
-  a.hop = p->hop;
-  a.boundary = p->sb.boundary;
+  fill_inst(p, in, out, T, batch, a.inst);
+  a.n_items = batch * a.inst.nblk;
   a.n_teams = a.n_items < p->team_capacity ? a.n_items : p->team_capacity;
-  fill_tables(p, a.tab);
+  a.epoch = p->d_epoch;
   a.xspec = p->d_xspec;
   a.xp = p->d_xp;
   a.ctl.abort = p->d_abort;
   a.ctl.err = p->d_err;
   a.ctl.spin_limit = 1u << 22;
-  const unsigned per_team = (unsigned)((a.n_items + a.n_teams - 1) / a.n_teams);
-  a.tag_base = take_tags(p, per_team * (unsigned)(a.steps + 2), s);
-  if (a.tag_base == 0u) return CBESSFM_EHIP;
   const int groups = (a.n_teams + kXcds - 1) / kXcds;
-  const int grid = groups * kXcds * a.n_sb;
+  const int grid = groups * kXcds * a.inst.n_sb;
   switch (p->log_np) {
     case 8: return launch_fwd_t<8>(a, grid, s);
     case 9: return launch_fwd_t<9>(a, grid, s);

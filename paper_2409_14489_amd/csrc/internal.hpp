@@ -31,19 +31,49 @@ struct XchgCtl {
   unsigned spin_limit;  // polls before a wait gives up
 };
 
-// Everything a forward launch needs.
-struct FwdArgs {
+// One forward instance: a plan's tables and geometry and the fields it runs on.
+struct Inst {
   const float2* in;   // [batch][2][T]
   float2* out;        // [batch][2][T]
   int T;
-  int n_items;        // batch * blocks per instance
-  int nblk;           // overlap-and-save blocks per instance
+  int nblk;           // overlap-and-save blocks per batch entry
   int n_sb, steps, n_chunks, nc, n_ov, hop, boundary;
-  int n_teams;        // persistent teams of n_sb workgroups
-  unsigned tag_base;  // first exchange-round tag of this launch
   Tables tab;
+};
+
+// Everything a single-plan forward launch needs.
+struct FwdArgs {
+  Inst inst;
+  int n_items;        // batch * blocks per batch entry
+  int n_teams;        // persistent teams of n_sb workgroups
+  unsigned* epoch;    // [teams] exchange rounds completed so far by each team (device)
   uint64_t* xspec;    // [team_capacity][2 slots][n_sb][4 comps][N']  tagged spectra
   uint64_t* xp;       // [team_capacity][2 slots][n_sb][N']           tagged intensities
+  XchgCtl ctl;
+};
+
+// Batched forward: a static schedule of teams of varying width.
+struct BatchItem {
+  int inst;            // index into the instance table
+  int sub;             // batch entry * nblk + block
+  unsigned round_off;  // exchange rounds of the team's earlier items in this launch
+};
+struct BatchTeam {
+  int width;           // n_sb of every instance the team runs
+  int first, count;    // its items: items[first, first + count)
+  unsigned rounds;     // exchange rounds of all its items
+  int epoch_slot;      // index into the epoch array
+  long long xspec_off; // word offsets of its exchange buffers
+  long long xp_off;
+};
+struct BatchArgs {
+  const Inst* insts;
+  const int2* wg;            // per workgroup: (team, member), team < 0 = idle
+  const BatchTeam* teams;
+  const BatchItem* items;
+  unsigned* epoch;
+  uint64_t* xspec;
+  uint64_t* xp;
   XchgCtl ctl;
 };
 
@@ -55,7 +85,8 @@ struct BwdArgs {
   int n_sb, steps, n_chunks, nc, n_taps, n_ov, hop, boundary;
   int n_teams;
   int ck_every, n_ck;  // states stored every ck_every steps, n_ck of them
-  unsigned tag_base, rounds_per_item;
+  unsigned rounds_per_item;
+  unsigned* epoch;     // [teams] exchange rounds completed so far by each team (device)
   Tables tab;
   const float* ctpad;   // [steps][n_sb][n_sb][tap_pad]: ctpad[s][l][i][t] = C[s][i][l][n_taps - 1 - t]
   const double* phase;  // [N] 2 pi^2 beta2 f^2 per km, subband order
@@ -103,15 +134,14 @@ struct cbessfm_plan {
   uint64_t* d_xspec;  // tagged exchange words
   uint64_t* d_xp;
   uint64_t* d_xq;
+  unsigned* d_epoch;  // [xchg_teams] exchange rounds completed per team
   unsigned* d_abort;  // sticky exchange-timeout word
   int* d_err;
-  unsigned next_tag;  // next unused exchange-round tag (host copy)
   float2 wsb[cbessfm::kMaxSubbands];
 };
 
 namespace cbessfm {
-// kernels.hip
-unsigned take_tags(cbessfm_plan_t* p, unsigned rounds, hipStream_t s);
+// forward.hip
 int launch_forward(cbessfm_plan_t* p, const void* in, void* out, long long T, int batch, hipStream_t s);
 int launch_tables(cbessfm_plan_t* p, hipStream_t s);
 int launch_pad_coeffs(cbessfm_plan_t* p, const float* src, hipStream_t s);
@@ -124,4 +154,8 @@ int launch_backward(cbessfm_plan_t* p, const void* field_in, const void* grad_ou
                     float* grad_rho, long long T, int batch, int ck_every, void* workspace, size_t ws_bytes,
                     hipStream_t s);
 int threads_for(int log_np);
+bool stream_capturing(hipStream_t s);
+int batch_occupancy_per_cu(int log_np, int* blocks);
+int launch_batch(int log_np, const BatchArgs& a, int grid, hipStream_t s);
+void fill_inst(const cbessfm_plan_t* p, const void* in, void* out, long long T, int batch, Inst& d);
 }  // namespace cbessfm

@@ -122,25 +122,6 @@ size_t xp_bytes(const cbessfm_plan_t* p) {
 
 }  // namespace
 
-namespace cbessfm {
-// Reserves `rounds` consecutive exchange tags for one launch.  Tags only grow,
-// so no word left by an earlier launch can match; when the 32-bit range runs
-// out every exchange word is cleared (stream-ordered) and numbering restarts.
-unsigned take_tags(cbessfm_plan_t* p, unsigned rounds, hipStream_t s) {
-  if (rounds == 0) rounds = 1;
-  if ((unsigned long long)p->next_tag + rounds >= 0xFFFFFF00ull) {
-    if (hipMemsetAsync(p->d_xspec, 0, xspec_bytes(p), s) != hipSuccess ||
-        hipMemsetAsync(p->d_xp, 0, xp_bytes(p), s) != hipSuccess ||
-        hipMemsetAsync(p->d_xq, 0, xp_bytes(p), s) != hipSuccess)
-      return 0u;
-    p->next_tag = 1;
-  }
-  const unsigned base = p->next_tag;
-  p->next_tag += rounds;
-  return base;
-}
-}  // namespace cbessfm
-
 extern "C" {
 
 const char* cbessfm_strerror(int code) {
@@ -227,8 +208,8 @@ void cbessfm_destroy(cbessfm_plan_t* p) {
   int prev = 0;
   hipGetDevice(&prev);
   hipSetDevice(p->device);
-  void* bufs[] = {p->d_phase, p->d_h, p->d_tw, p->d_poly, p->d_c, p->d_cpad, p->d_ctpad, p->d_rho,
-                  p->d_xspec, p->d_xp, p->d_xq, p->d_abort, p->d_err};
+  void* bufs[] = {p->d_phase, p->d_h,  p->d_tw,    p->d_poly,  p->d_c,     p->d_cpad, p->d_ctpad,
+                  p->d_rho,   p->d_xspec, p->d_xp, p->d_xq, p->d_epoch, p->d_abort, p->d_err};
   for (void* b : bufs)
     if (b) hipFree(b);
   hipSetDevice(prev);
@@ -339,6 +320,7 @@ int cbessfm_plan(cbessfm_plan_t** out, const cbessfm_link* link, const cbessfm_s
   alloc((void**)&p->d_xspec, xspec_bytes(p));
   alloc((void**)&p->d_xp, xp_bytes(p));
   alloc((void**)&p->d_xq, xp_bytes(p));
+  alloc((void**)&p->d_epoch, sizeof(unsigned) * p->xchg_teams);
   alloc((void**)&p->d_abort, sizeof(unsigned));
   alloc((void**)&p->d_err, sizeof(int));
   if (!ok) {
@@ -354,8 +336,8 @@ int cbessfm_plan(cbessfm_plan_t** out, const cbessfm_link* link, const cbessfm_s
                 hipMemset(p->d_abort, 0, sizeof(unsigned)) == hipSuccess &&
                 hipMemset(p->d_xspec, 0, xspec_bytes(p)) == hipSuccess &&
                 hipMemset(p->d_xp, 0, xp_bytes(p)) == hipSuccess &&
-                hipMemset(p->d_xq, 0, xp_bytes(p)) == hipSuccess;
-  p->next_tag = 1;
+                hipMemset(p->d_xq, 0, xp_bytes(p)) == hipSuccess &&
+                hipMemset(p->d_epoch, 0, sizeof(unsigned) * p->xchg_teams) == hipSuccess;
   if (!hip_ok || cbessfm::launch_tables(p, nullptr) || cbessfm::launch_pad_coeffs(p, p->d_c, nullptr) ||
       hipDeviceSynchronize() != hipSuccess) {
     cbessfm_destroy(p);
@@ -427,9 +409,16 @@ int cbessfm_status(cbessfm_plan_t* p) {
   if (hipSetDevice(p->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return CBESSFM_EHIP;
   int err = 0;
   if (hipMemcpy(&err, p->d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return CBESSFM_EHIP;
-  if (err) {  // an exchange wait gave up: clear the sticky words
+  if (err) {
+    // An exchange wait gave up.  Workgroups of that launch may have written
+    // words with tags a later launch would reuse, so the exchange state is
+    // reset along with the sticky words.
     if (hipMemset(p->d_err, 0, sizeof(int)) != hipSuccess ||
-        hipMemset(p->d_abort, 0, sizeof(unsigned)) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+        hipMemset(p->d_abort, 0, sizeof(unsigned)) != hipSuccess ||
+        hipMemset(p->d_xspec, 0, xspec_bytes(p)) != hipSuccess || hipMemset(p->d_xp, 0, xp_bytes(p)) != hipSuccess ||
+        hipMemset(p->d_xq, 0, xp_bytes(p)) != hipSuccess ||
+        hipMemset(p->d_epoch, 0, sizeof(unsigned) * p->xchg_teams) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess)
       return CBESSFM_EHIP;
   }
   return err;

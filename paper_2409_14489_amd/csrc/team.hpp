@@ -6,12 +6,24 @@
 // device-scope atomics (single-copy atomic, coherent across the XCDs' L2s).
 // A reader polls a word until it carries the tag of the round it needs, so it
 // can never consume stale data, and no cache write-back / invalidate fences
-// are needed.  Tags grow monotonically across rounds and launches.
+// are needed.
+//
+// Tags come from a per-team round counter kept in device memory (the team's
+// "epoch"): a launch reads it once at the start, numbers its rounds after it,
+// and member 0 stores the advanced value at the end.  Nothing on the host has
+// to number rounds, so a launch recorded in a HIP graph stays correct on every
+// replay.  Member 0 finishes only after consuming a round from every member,
+// and each member reads the counter before its first write, so the update can
+// never be seen by a member of the same launch.
 //
 // Reuse of a buffer slot is safe when two uses of the same slot are separated
 // by at least one other all-to-all round: a member writes round r + 1 only
 // after it has consumed round r, so a member that has consumed round r + 1 from
-// everybody knows that everybody is done reading round r.
+// everybody knows that everybody is done reading round r.  A word therefore
+// holds either the tag a reader expects or the tag of an earlier use of that
+// slot a few rounds back; tags are compared modulo 2^32, so the counter may
+// wrap.  Buffers start zeroed and the first tag of a team is 1, and every slot
+// has been written before its team's tags can come back around to 0.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -38,6 +50,20 @@ __device__ __forceinline__ void xput(uint64_t* dst, float v, unsigned tag) {
 
 __device__ __forceinline__ uint64_t xload(const uint64_t* src) {
   return __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Reads the team's round counter into LDS (one load per workgroup) and
+// returns the first tag of this launch.
+__device__ __forceinline__ unsigned epoch_begin(const unsigned* epoch, unsigned* lds_word) {
+  if (threadIdx.x == 0) *lds_word = __hip_atomic_load(epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  return *lds_word + 1u;
+}
+
+// Member 0 stores the counter advanced by the rounds of this launch.
+__device__ __forceinline__ void epoch_end(unsigned* epoch, unsigned first_tag, unsigned rounds, int me) {
+  if (me == 0 && threadIdx.x == 0)
+    __hip_atomic_store(epoch, first_tag - 1u + rounds, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Issues the CNT loads row[t + stride * o].

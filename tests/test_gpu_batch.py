@@ -1,0 +1,222 @@
+"""Batched execution, graph replay and the measured autotuner on the GPU.
+
+Every instance of a batch must give what the FP64 oracle gives for it alone
+(relative L2 <= 1e-5), and what cbessfm_run gives for it; launches recorded in
+a HIP graph must give the eager result on every replay, with eager work and
+changed inputs between replays.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synth import random_field
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+BETA2_PS2 = -21.7
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def rand_coeffs(steps, n_sb, taps, phase_rad, power_w, seed):
+    rng = np.random.default_rng(seed)
+    c = rng.standard_normal((steps, n_sb, n_sb, taps))
+    c *= phase_rad / (power_w * np.abs(c).sum(axis=(2, 3), keepdims=True))
+    return c.astype(np.float32)
+
+
+# (n_sb, N', overlap, steps, rho, taps, T, batch, boundary, spans)
+SHAPES = [
+    (1, 1024, 128, 3, 0.5, 11, 9000, 1, "circular", 1),
+    (2, 1024, 256, 2, 0.3, 7, 20000, 2, "circular", 2),
+    (3, 1024, 384, 4, 0.2, 9, 7000, 1, "zero", 3),
+    (5, 1024, 640, 1, 0.5, 21, 30000, 1, "circular", 5),
+    (2, 1024, 256, 5, 0.7, 5, 1500, 1, "circular", 1),     # T < N: a block wraps
+    (2, 512, 128, 3, 0.4, 5, 6000, 1, "circular", 2),      # second N' class
+    (1, 512, 64, 2, 0.5, 3, 4000, 3, "zero", 1),
+]
+
+
+def make_instances(shapes, seed0=0):
+    from paper_2409_14489_amd import LinkSpec, Plan
+    power = 4e-3
+    out = []
+    for k, (nsb, np_, ov, steps, rho, taps, t_len, batch, bnd, spans) in enumerate(shapes):
+        rate = nsb * 64e9
+        c = rand_coeffs(steps, nsb, taps, 0.5, power, seed0 + k)
+        link = LinkSpec(beta2_ps2_km=BETA2_PS2, n_spans=spans, sample_rate_hz=rate)
+        plan = Plan(link, nsb, np_, ov, steps, rho, coeffs=c, boundary=bnd)
+        o = oracle.OraclePlan(BETA2_PS2 * 1e-24, rate, 80.0 * spans / steps, steps, rho, nsb, nsb * np_, ov,
+                              c.astype(np.float64), boundary=bnd)
+        shape = (batch, 2, t_len) if batch > 1 else (2, t_len)
+        x = random_field(shape, 500 + seed0 + k, power_w=power)
+        xt = torch.from_numpy(x.astype(np.complex64)).cuda()
+        out.append(dict(plan=plan, oracle=o, x=x, xt=xt, yt=torch.empty_like(xt)))
+    return out
+
+
+def test_batch_matches_oracle_and_single_runs():
+    from paper_2409_14489_amd import Batch
+    insts = make_instances(SHAPES)
+    b = Batch([(d["plan"], d["xt"], d["yt"]) for d in insts])
+    info = b.info()
+    print(info)
+    assert info["launches"] == 2 and info["items"] > 0
+    b.run()
+    torch.cuda.synchronize()
+    assert b.status() == 0
+    for k, d in enumerate(insts):
+        got = d["yt"].cpu().numpy().astype(np.complex128)
+        ref = oracle.run(d["x"], d["oracle"])
+        single = d["plan"].run(d["xt"])
+        torch.cuda.synchronize()
+        e_or = rel_l2(got, ref)
+        e_single = rel_l2(got, single.cpu().numpy().astype(np.complex128))
+        print(k, SHAPES[k][:4], "vs oracle", e_or, "vs single run", e_single)
+        assert e_or < TOL
+        assert e_single < 1e-6
+    # a second run of the same batch (device-side round counters) gives the same bytes
+    first = [d["yt"].clone() for d in insts]
+    b.run()
+    torch.cuda.synchronize()
+    assert b.status() == 0
+    for f, d in zip(first, insts):
+        assert torch.equal(f, d["yt"])
+    b.close()
+    for d in insts:
+        d["plan"].close()
+
+
+def test_batch_of_many_uneven_instances():
+    """Forty instances of 1-5 subbands, 1-12 steps and log-uniform lengths in one launch."""
+    from paper_2409_14489_amd import Batch
+    rng = np.random.default_rng(77)
+    shapes = []
+    for _ in range(40):
+        nsb = int(rng.integers(1, 6))
+        steps = int(rng.integers(1, 13))
+        t_len = int(2 ** rng.uniform(11, 15)) * nsb
+        taps = int(rng.choice([3, 9, 17]))
+        shapes.append((nsb, 1024, 128 * nsb, steps, float(rng.uniform(0.1, 0.9)), taps, t_len, 1, "circular",
+                       int(rng.integers(1, 6))))
+    insts = make_instances(shapes, seed0=1000)
+    b = Batch([(d["plan"], d["xt"], d["yt"]) for d in insts])
+    info = b.info()
+    print(info)
+    assert info["launches"] == 1
+    b.run()
+    torch.cuda.synchronize()
+    assert b.status() == 0
+    worst = 0.0
+    for d in insts:
+        got = d["yt"].cpu().numpy().astype(np.complex128)
+        worst = max(worst, rel_l2(got, oracle.run(d["x"], d["oracle"])))
+    print("worst rel L2", worst)
+    assert worst < TOL
+    b.close()
+
+
+def test_batch_graph_replays_match_eager():
+    from paper_2409_14489_amd import Batch
+    insts = make_instances(SHAPES[:4], seed0=50)
+    b = Batch([(d["plan"], d["xt"], d["yt"]) for d in insts])
+    b.run()  # eager warm-up
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.run()
+    for rep in range(3):
+        # new inputs in place, eager work in between, then a replay
+        for k, d in enumerate(insts):
+            new = random_field(tuple(d["xt"].shape), 900 + 10 * rep + k, power_w=4e-3)
+            d["xt"].copy_(torch.from_numpy(new.astype(np.complex64)))
+            d["x"] = new
+        eager = [d["plan"].run(d["xt"]) for d in insts]
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert b.status() == 0
+        for d, e in zip(insts, eager):
+            err = rel_l2(d["yt"].cpu().numpy().astype(np.complex128), e.cpu().numpy().astype(np.complex128))
+            assert err < 1e-6, (rep, err)
+        ref = oracle.run(insts[0]["x"], insts[0]["oracle"])
+        assert rel_l2(insts[0]["yt"].cpu().numpy().astype(np.complex128), ref) < TOL
+    del g
+    b.close()
+
+
+def test_single_plan_graph_replays_forward_and_adjoint():
+    from paper_2409_14489_amd import LinkSpec, Plan
+    power = 4e-3
+    c = rand_coeffs(3, 2, 7, 0.5, power, 5)
+    plan = Plan(LinkSpec(beta2_ps2_km=BETA2_PS2, n_spans=2, sample_rate_hz=128e9), 2, 1024, 256, 3, 0.3,
+                coeffs=c)
+    x = torch.from_numpy(random_field((2, 12000), 61, power_w=power).astype(np.complex64)).cuda()
+    gout = torch.from_numpy(random_field((2, 12000), 62, power_w=1.0).astype(np.complex64)).cuda()
+    y = torch.empty_like(x)
+    ws = torch.empty(plan.backward_workspace(12000, 1, 2), dtype=torch.uint8, device="cuda")
+    plan.run(x, out=y)
+    plan.backward(x, gout, checkpoint_every=2, workspace=ws)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.run(x, out=y)
+        gi, gc, gr = plan.backward(x, gout, checkpoint_every=2, workspace=ws)
+    for rep in range(3):
+        x.copy_(torch.from_numpy(random_field((2, 12000), 70 + rep, power_w=power).astype(np.complex64)))
+        y_e = plan.run(x)
+        gi_e, gc_e, gr_e = plan.backward(x, gout, checkpoint_every=2)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert plan.status() == 0
+        assert rel_l2(y.cpu().numpy(), y_e.cpu().numpy()) < 1e-6
+        assert rel_l2(gi.cpu().numpy(), gi_e.cpu().numpy()) < 1e-6
+        assert rel_l2(gc.cpu().numpy(), gc_e.cpu().numpy()) < 1e-6
+        assert abs(float(gr) - float(gr_e)) <= 1e-6 * max(1.0, abs(float(gr_e)))
+    del g
+    plan.close()
+
+
+def test_many_launches_keep_exchange_consistent():
+    """200 launches of one plan: the per-team round counters advance on the
+    device and the last result equals the first, byte for byte."""
+    from paper_2409_14489_amd import LinkSpec, Plan
+    power = 4e-3
+    c = rand_coeffs(2, 3, 5, 0.5, power, 8)
+    plan = Plan(LinkSpec(beta2_ps2_km=BETA2_PS2, n_spans=1, sample_rate_hz=192e9), 3, 512, 192, 2, 0.5, coeffs=c)
+    x = torch.from_numpy(random_field((2, 40000), 63, power_w=power).astype(np.complex64)).cuda()
+    first = plan.run(x)
+    y = torch.empty_like(x)
+    for _ in range(200):
+        plan.run(x, out=y)
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    assert torch.equal(first, y)
+    plan.close()
+
+
+def test_measured_autotune_gives_a_working_plan():
+    from paper_2409_14489_amd import LinkSpec, Plan, autotune
+    link = LinkSpec(beta2_ps2_km=BETA2_PS2, n_spans=3, sample_rate_hz=128e9)
+    t_len = 50000
+    tun = autotune(link, 2, 4, 9, t_len, measure=True)
+    print(tun)
+    assert tun["measured"] == 1 and tun["covered"] == 1
+    assert tun["overlap"] >= tun["memory"] and tun["overlap"] % 2 == 0
+    assert 2 * tun["block_sb"] > tun["overlap"] and tun["predicted_s"] > 0
+    power = 4e-3
+    c = rand_coeffs(4, 2, 9, 0.5, power, 9)
+    plan = Plan(link, 2, tun["block_sb"], tun["overlap"], 4, 0.5, coeffs=c)
+    x = random_field((2, t_len), 64, power_w=power)
+    y = plan.run(torch.from_numpy(x.astype(np.complex64)).cuda())
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    o = oracle.OraclePlan(BETA2_PS2 * 1e-24, 128e9, 240.0 / 4, 4, 0.5, 2, 2 * tun["block_sb"], tun["overlap"],
+                          c.astype(np.float64))
+    assert rel_l2(y.cpu().numpy().astype(np.complex128), oracle.run(x, o)) < TOL
+    plan.close()
