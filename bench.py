@@ -1,21 +1,35 @@
-"""Throughput of the CB-ESSFM forward on one MI355X.
+"""Throughput of CB-ESSFM digital backpropagation on one MI355X.
 
-Workload: 5 WDM channels x 64 GBd DP-64QAM on a 100 GHz grid, 2^16 symbols per
-channel sampled at 640 GS/s (T = 655360 per polarisation), 15 x 80 km SMF;
-backpropagation with 5 subbands, N' = 4096, N_ov = 2560, 15 asymmetric steps
-(rho = 0.3) and 21 analytic taps, one persistent launch per step.
+Primary workload (the JSON line's value): 5 WDM channels x 64 GBd DP-64QAM on a
+100 GHz grid, 2^16 symbols per channel sampled at 640 GS/s (T = 655360 per
+polarisation), 15 x 80 km SMF; backpropagation with 5 subbands, N' = 4096,
+N_ov = 2560, 15 asymmetric steps (rho = 0.3) and 21 analytic taps, one
+persistent launch per pass.  A "step" of this benchmark is one pass of the
+hot path over that field.
 
-A "step" of this benchmark is one full pass of the hot path over the field.
-Prints one JSON line.  Options:
+Two more legs are reported in the same line:
+  grad     1 ch 32 GBd DP-16QAM, 2^14 symbols, 1 x 80 km, 16 realisations,
+           15 steps x 11 taps: forward + adjoint + Adam iterations per second
+           (checkpointing on and off), peak device memory, 200 Adam iterations
+           of the matched-filter MSE, and the adjoint's error against the FP64
+           oracle on one realisation;
+  batched  64 uneven instances (1-5 channels, 5-40 spans, 1-40 steps, 2^12 -
+           2^18 symbols per channel), N' / N_ov from the measured autotuner,
+           one graph-replayed batch against 64 separate launches.
+
+Options:
   --gpus N      only 1 is supported (one GPU per process and per box)
-  --steps K     timed passes (default 200)
+  --steps K     timed passes of the primary workload (default 200)
   --warmup W    untimed passes (default 20)
-  --no-cpu      skip the oracle timing
-  --copy-mib M  after timing, run one plain device copy of M MiB (counter calibration)
+  --legs L      comma list of fwd,grad,batched (default all)
+  --no-cpu      skip the oracle timing (and the full-size parity check)
+  --copy-mib M  after timing, one plain device copy of M MiB (counter calibration)
 """
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import math
 import os
@@ -26,10 +40,44 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOAD = "5ch-64GBd-64QAM-2^16sym-15x80km"
+GRAD_WORKLOAD = "1ch-32GBd-16QAM-2^14sym-1x80km-15steps"
 METRIC = "DBP 2D-symbols/s (all channels) + % HBM roofline; coeff-gradient steps/s at ≤1e-5 rel err"
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 vector (published)
-GEN_STEPS_PER_SPAN = 4         # forward-link simulator steps per span for the synthetic field
+GEN_STEPS_PER_SPAN = 4         # forward-link simulator steps per span, 5-channel field
+GRAD_GEN_STEPS_PER_SPAN = 50   # the same for the single-channel gradient fields
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fwd_kernel_5ch_64GBd_2p16sym_15x80km_traffic.md")
+KERNEL_SOURCES = ["paper_2409_14489_amd/csrc/*.hip", "paper_2409_14489_amd/csrc/*.hpp",
+                  "paper_2409_14489_amd/csrc/*.cpp", "include/cbessfm.h",
+                  "paper_2409_14489_amd/build.py"]
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for pat in KERNEL_SOURCES:
+        for f in sorted(glob.glob(os.path.join(ROOT, pat))):
+            h.update(os.path.relpath(f, ROOT).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the kernel sources as they are now; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    try:
+        return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def algorithmic_flops_per_block(n_sb, n_sub, steps, n_taps):
@@ -48,41 +96,42 @@ def algorithmic_flops_per_block(n_sb, n_sub, steps, n_taps):
     return 4 * dft_n + steps * per_step + 2 * 6 * n
 
 
-def cpu_baseline(x, coeffs, d, link_rate, step_km):
-    """The FP64 oracle, as it stands, on the whole workload (one pass)."""
+def link_of(ch, rate):
+    from paper_2409_14489_amd import LinkSpec
+    return LinkSpec(alpha_db_km=ch.alpha_db_km, beta2_ps2_km=ch.beta2_ps2_km, gamma_w_km=ch.gamma_w_km,
+                    span_km=ch.span_km, n_spans=ch.n_spans, sample_rate_hz=rate)
+
+
+def oracle_plan(d, rate, step_km, coeffs, beta2_ps2_km):
     import numpy as np
     import oracle
-    plan = oracle.OraclePlan(-21.7e-24, link_rate, step_km, d["n_steps"], d["rho"], d["n_sb"],
+    return oracle.OraclePlan(beta2_ps2_km * 1e-24, rate, step_km, d["n_steps"], d["rho"], d["n_sb"],
                              d["n_sb"] * d["n_sub"], d["n_overlap"], np.asarray(coeffs, np.float64))
-    t0 = time.perf_counter()
-    oracle.run(x, plan)
-    return time.perf_counter() - t0
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--copy-mib", type=int, default=0)
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
-              "(the multi-GPU sharding is described in DESIGN.md)", file=sys.stderr)
-        sys.exit(2)
+def timed_events(stream, fn, reps):
+    """Average seconds per call of fn() on `stream`, HIP events around the loop."""
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps
 
+
+# ------------------------------------------------------------------ primary: 5-channel forward
+def leg_forward(args):
     import numpy as np
     import torch
-
-    from paper_2409_14489_amd import LinkSpec, Plan, analytic_coeffs
+    from paper_2409_14489_amd import Plan, analytic_coeffs
     from synth import workload
 
-    torch.cuda.set_device(0)
     x, _, w = workload(WORKLOAD, 2001, steps_per_span=GEN_STEPS_PER_SPAN)
     d, wdm, ch = w["dbp"], w["wdm"], w["ch"]
-    link = LinkSpec(alpha_db_km=ch.alpha_db_km, beta2_ps2_km=ch.beta2_ps2_km, gamma_w_km=ch.gamma_w_km,
-                    span_km=ch.span_km, n_spans=ch.n_spans, sample_rate_hz=wdm.sample_rate)
+    link = link_of(ch, wdm.sample_rate)
     coeffs = analytic_coeffs(link, d["n_sb"], d["n_steps"], d["rho"], d["n_taps"]).astype(np.float32)
     plan = Plan(link, d["n_sb"], d["n_sub"], d["n_overlap"], d["n_steps"], d["rho"], coeffs=coeffs)
     t_len = x.shape[-1]
@@ -107,25 +156,24 @@ def main():
     wall = time.perf_counter() - t0
     if plan.status() != 0:
         raise RuntimeError("device error flag set during the timed region")
-    kernel_s = ev0.elapsed_time(ev1) / 1e3 / args.steps   # one launch per step
+    kernel_s = ev0.elapsed_time(ev1) / 1e3 / args.steps   # one launch per pass
 
     n2d = wdm.n_channels * 2 * wdm.n_symbols                # 2D symbols per pass
-    ms_per_step = wall / args.steps * 1e3
-    value = n2d / (wall / args.steps)
     nblk = plan.n_blocks(t_len)
     flops = algorithmic_flops_per_block(d["n_sb"], d["n_sub"], d["n_steps"], d["n_taps"]) * nblk
     achieved = flops / kernel_s / 1e12
     alg_bytes = 2 * (2 * t_len * 8)                          # read + write complex64, both pols
     hbm_gbs = alg_bytes / kernel_s / 1e9
+    traffic = measured_traffic()
 
     result = {
         "metric": METRIC,
-        "value": value,
+        "value": n2d / (wall / args.steps),
         "unit": "2D-symbols/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": wall / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -137,16 +185,28 @@ def main():
                    "n_taps": d["n_taps"], "blocks": nblk, "kernel": "cbessfm::fwd_kernel<12>",
                    "threads_per_group": plan.info().threads_per_group},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "flops_per_launch": flops, "kernel_ms": kernel_s * 1e3},
         "hbm_roofline": {"achieved": hbm_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                          "frac": hbm_gbs / PEAK_HBM_GBS, "bytes_per_launch": alg_bytes},
     }
     if not args.no_cpu:
-        secs = cpu_baseline(x, coeffs, d, wdm.sample_rate, ch.span_km * ch.n_spans / d["n_steps"])
-        result["cpu_baseline"] = {"value": n2d / secs, "unit": "2D-symbols/s", "cores": 1, "kind": "oracle",
-                                  "sample": f"whole workload, one pass ({nblk} blocks), numpy FP64, "
-                                            f"{secs:.2f} s"}
+        import oracle
+        oplan = oracle_plan(d, wdm.sample_rate, ch.span_km * ch.n_spans / d["n_steps"], coeffs, ch.beta2_ps2_km)
+        passes, cpu_s, proc_s, ref = 0, 0.0, 0.0, None
+        while passes < 1 or (cpu_s < 10.0 and passes < 12):
+            t0, p0 = time.perf_counter(), time.process_time()
+            out = oracle.run(x, oplan)
+            cpu_s += time.perf_counter() - t0
+            proc_s += time.process_time() - p0
+            ref = out if ref is None else ref
+            passes += 1
+        got = yout.cpu().numpy().astype(np.complex128)
+        result["parity_rel_l2"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        result["cpu_baseline"] = {"value": n2d * passes / cpu_s, "unit": "2D-symbols/s",
+                                  "cores": max(1, round(proc_s / cpu_s)), "kind": "oracle",
+                                  "sample": f"the whole workload ({nblk} blocks), {passes} passes of the FP64 "
+                                            f"numpy oracle, {cpu_s:.1f} s"}
     if args.copy_mib:
         n = args.copy_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -155,6 +215,197 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         result["copy_calibration_bytes"] = 4 * n
+    plan.close()
+    return result
+
+
+# ------------------------------------------------------------------ gradient leg
+def leg_grad(args):
+    import numpy as np
+    import torch
+    from paper_2409_14489_amd import Plan, analytic_coeffs, cbessfm
+    from paper_2409_14489_amd.train import SymbolReceiver, fit, phase_aligned_mse
+    from synth import workload
+
+    n_real, iters = 16, 200
+    fields, syms = [], []
+    for r in range(n_real):
+        x, s, w = workload(GRAD_WORKLOAD, 3000 + r, steps_per_span=GRAD_GEN_STEPS_PER_SPAN)
+        fields.append(x)
+        syms.append(s[0])                              # channel 0: (2, n_symbols)
+    d, wdm, ch = w["dbp"], w["wdm"], w["ch"]
+    link = link_of(ch, wdm.sample_rate)
+    x = torch.from_numpy(np.stack(fields).astype(np.complex64)).cuda()
+    s = torch.from_numpy(np.stack(syms).astype(np.complex64)).cuda()
+    t_len = x.shape[-1]
+    c0 = analytic_coeffs(link, d["n_sb"], d["n_steps"], d["rho"], d["n_taps"]).astype(np.float32)
+    plan = Plan(link, d["n_sb"], d["n_sub"], d["n_overlap"], d["n_steps"], d["rho"], coeffs=c0)
+    p_w = 1e-3 * 10 ** (wdm.power_dbm_per_channel / 10)
+    rx = SymbolReceiver(t_len, wdm.sample_rate, wdm.baud, wdm.rolloff, p_w)
+
+    def mse(coeffs, rho):
+        with torch.no_grad():
+            return float(phase_aligned_mse(rx(cbessfm(x, coeffs, rho, plan)), s))
+
+    c0_t = torch.from_numpy(c0).cuda()
+    rho0 = torch.tensor(d["rho"], dtype=torch.float32, device="cuda")
+    zero = torch.zeros_like(c0_t)
+    mse_edc = mse(zero, rho0)
+    mse_analytic = mse(c0_t, rho0)
+
+    out = {"workload": GRAD_WORKLOAD, "realisations": n_real, "T": t_len, "steps": d["n_steps"],
+           "n_taps": d["n_taps"], "parameters": int(c0.size) + 1, "unit": "steps/s",
+           "step": "forward + matched-filter MSE + adjoint + Adam update, 16 realisations"}
+    stream = torch.cuda.current_stream()
+    for ck in (1, 5):
+        fit(plan, x, s, rx, c0, d["rho"], iters=3, checkpoint_every=ck)   # warm-up
+        torch.cuda.synchronize()
+        torch.cuda.reset_peak_memory_stats()
+        base_mem = torch.cuda.memory_allocated()
+        t0 = time.perf_counter()
+        c_fit, rho_fit, losses = fit(plan, x, s, rx, c0, d["rho"], iters=iters, checkpoint_every=ck)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        if plan.status() != 0:
+            raise RuntimeError("device error flag set in the gradient leg")
+        peak = torch.cuda.max_memory_allocated() - base_mem
+        key = "store_every_step" if ck == 1 else f"checkpoint_every_{ck}"
+        out[key] = {"steps_per_s": iters / wall, "ms_per_step": wall / iters * 1e3,
+                    "peak_extra_mib": peak / 2 ** 20,
+                    "adjoint_workspace_mib": plan.backward_workspace(t_len, n_real, ck) / 2 ** 20}
+        if ck == 1:
+            mse_fit = mse(c_fit, rho_fit)
+            out["adam_iterations"] = iters
+            out["snr_db"] = {"edc": -10 * math.log10(mse_edc), "analytic": -10 * math.log10(mse_analytic),
+                             "fitted": -10 * math.log10(mse_fit)}
+            out["rho_fitted"] = float(rho_fit)
+    # adjoint kernel alone (both sweeps + reductions), timed on its stream
+    g = torch.from_numpy(((np.random.default_rng(5).standard_normal(x.shape)
+                           + 1j * np.random.default_rng(6).standard_normal(x.shape)) * 1e-2)
+                         .astype(np.complex64)).cuda()
+    plan.set_coeffs(c0_t, rho0)
+    ws = torch.empty(plan.backward_workspace(t_len, n_real, 1), dtype=torch.uint8, device="cuda")
+    gi, gc, gr = plan.backward(x, g, need_grad_in=False, workspace=ws)
+    out["adjoint_ms"] = timed_events(stream, lambda: plan.backward(x, g, need_grad_in=False, workspace=ws),
+                                     20) * 1e3
+    out["forward_ms"] = timed_events(stream, lambda: plan.run(x), 20) * 1e3
+    if not args.no_cpu:
+        from oracle.grad import vjp
+        oplan = oracle_plan(d, wdm.sample_rate, ch.span_km * ch.n_spans / d["n_steps"], c0, ch.beta2_ps2_km)
+        gi, gc, gr = plan.backward(x[:1], g[:1])
+        torch.cuda.synchronize()
+        ogi, ogc, ogr = vjp(fields[0].astype(np.complex64).astype(np.complex128), oplan,
+                            g[0].cpu().numpy().astype(np.complex128))
+        out["parity_rel_l2"] = {
+            "grad_c": float(np.linalg.norm(gc.cpu().numpy() - ogc) / np.linalg.norm(ogc)),
+            "grad_in": float(np.linalg.norm(gi[0].cpu().numpy() - ogi) / np.linalg.norm(ogi)),
+            "grad_rho_vs_oracle": float(abs(float(gr) - ogr) / abs(ogr)),
+        }
+    out["value"] = out["store_every_step"]["steps_per_s"]
+    plan.close()
+    return out
+
+
+# ------------------------------------------------------------------ batched leg
+def batch_instances(seed=4000, n=64):
+    """The uneven 64-instance workload: per instance, channels, spans, steps and
+    log-uniform symbol counts drawn from PCG64(seed)."""
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(n):
+        n_ch = int(rng.integers(1, 6))
+        spans = int(rng.integers(5, 41))
+        steps = int(rng.integers(1, 41))
+        n_sym = int(round(2 ** rng.uniform(12, 18)))
+        qam = int(rng.choice([16, 64]))
+        out.append(dict(n_ch=n_ch, spans=spans, steps=steps, n_sym=n_sym, qam=qam, rate=n_ch * 128e9,
+                        T=n_sym * 2 * n_ch, taps=11 if n_ch == 1 else 21))
+    return out
+
+
+def leg_batched(args):
+    import numpy as np
+    import torch
+    from paper_2409_14489_amd import Batch, LinkSpec, Plan, autotune
+    from synth import random_field
+
+    specs = batch_instances()
+    plans, xs, ys, tuned = [], [], [], []
+    t_tune = time.perf_counter()
+    for k, sp in enumerate(specs):
+        link = LinkSpec(n_spans=sp["spans"], sample_rate_hz=sp["rate"])
+        tun = autotune(link, sp["n_ch"], sp["steps"], sp["taps"], sp["T"], measure=True)
+        tuned.append(tun)
+        plans.append(Plan(link, sp["n_ch"], tun["block_sb"], tun["overlap"], sp["steps"], 0.5,
+                          n_taps=sp["taps"]))
+        p_w = sp["n_ch"] * 1e-3 * 10 ** 0.2
+        xs.append(torch.from_numpy(random_field((2, sp["T"]), 4100 + k, power_w=p_w).astype(np.complex64)).cuda())
+        ys.append(torch.empty_like(xs[-1]))
+    t_tune = time.perf_counter() - t_tune
+    n2d = sum(sp["n_ch"] * 2 * sp["n_sym"] for sp in specs)
+    stream = torch.cuda.current_stream()
+
+    b = Batch(list(zip(plans, xs, ys)))
+    info = b.info()
+    b.run()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        b.run()
+    for _ in range(3):
+        graph.replay()
+    reps = 10
+    t_batch = timed_events(stream, graph.replay, reps)
+    if b.status() != 0:
+        raise RuntimeError("device error flag set in the batched leg")
+    batched_out = [y.clone() for y in ys]
+
+    def separate():
+        for p, x, y in zip(plans, xs, ys):
+            p.run(x, out=y)
+    for _ in range(2):
+        separate()
+    t_sep = timed_events(stream, separate, reps)
+    same = max(float((a - y).abs().max() / y.abs().max()) for a, y in zip(batched_out, ys))
+    out = {"workload": "64 uneven instances: 1-5 ch x 64 GBd, 5-40 x 80 km, 1-40 steps, 2^12-2^18 symbols/ch",
+           "unit": "2D-symbols/s", "value": n2d / t_batch, "ms_per_run": t_batch * 1e3,
+           "separate_launches": {"value": n2d / t_sep, "ms_per_run": t_sep * 1e3, "launches": len(specs)},
+           "speedup_vs_separate": t_sep / t_batch, "graph_replayed": True,
+           "launches_per_run": info["launches"], "teams": info["teams"], "workgroups": info["workgroups"],
+           "blocks": info["items"], "predicted_ms": info["makespan_s"] * 1e3,
+           "lower_bound_ms": info["lower_bound_s"] * 1e3,
+           "block_sb_chosen": sorted({t["block_sb"] for t in tuned}),
+           "instances_overlap_covers_memory": sum(t["covered"] for t in tuned),
+           "max_rel_diff_vs_separate": same, "autotune_s": t_tune, "symbols_2d": n2d}
+    b.close()
+    for p in plans:
+        p.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--legs", default="fwd,grad,batched")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
+              "(the multi-GPU sharding is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    legs = set(args.legs.split(","))
+
+    import torch
+    torch.cuda.set_device(0)
+    result = leg_forward(args)
+    if "grad" in legs:
+        result["grad"] = leg_grad(args)
+    if "batched" in legs:
+        result["batched"] = leg_batched(args)
     print(json.dumps(result), flush=True)
 
 

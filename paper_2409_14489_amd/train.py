@@ -1,0 +1,102 @@
+"""On-device fitting of the CB-ESSFM coefficients and split ratio (Sec. III-B).
+
+The paper fits the coefficients by minimising the mean square error between
+the transmitted symbols and the received ones after backpropagation, matched
+filtering and sampling, and picks the split ratio by sweeping it.  Here the
+backpropagation and its adjoint are the library's kernels (through
+``cbessfm``); the receiver -- channel selection, root-raised-cosine matched
+filter, decimation, a common phase estimate -- is a few PyTorch operations on
+the device, differentiated by autograd; Adam updates C and rho on the device.
+"""
+from __future__ import annotations
+
+import math
+
+import torch
+
+from .autograd import cbessfm
+
+
+def rrc_amplitude(f: torch.Tensor, baud: float, rolloff: float) -> torch.Tensor:
+    """Root-raised-cosine amplitude response, unit height in the flat band."""
+    af = f.abs()
+    f1 = (1.0 - rolloff) * baud / 2.0
+    f2 = (1.0 + rolloff) * baud / 2.0
+    out = torch.zeros_like(af)
+    out[af <= f1] = 1.0
+    if rolloff > 0:
+        mid = (af > f1) & (af <= f2)
+        out[mid] = torch.sqrt(0.5 * (1.0 + torch.cos(math.pi / (rolloff * baud) * (af[mid] - f1))))
+    return out
+
+
+class SymbolReceiver:
+    """Matched filter and symbol sampler of one WDM channel.
+
+    The channel sits at ``offset_hz`` (a whole number of DFT bins of the
+    length-T record) and carries symbols at ``baud`` with sample k * sps at
+    symbol k, sps = sample_rate / baud.  A transmitter of unit-energy symbols
+    normalised to ``power_w`` over both polarisations has a pulse amplitude of
+    sps sqrt(power_w / 2); after the matched filter (a raised-cosine overall
+    response, Nyquist at the symbol rate) the sample at symbol k is the
+    symbol times sqrt(power_w / 2), which the output is divided by.
+    """
+
+    def __init__(self, t_len: int, sample_rate: float, baud: float, rolloff: float, power_w: float,
+                 offset_hz: float = 0.0, device="cuda"):
+        sps = sample_rate / baud
+        if abs(sps - round(sps)) > 1e-9:
+            raise ValueError("sample_rate must be a whole multiple of baud")
+        self.sps = int(round(sps))
+        df = sample_rate / t_len
+        shift = offset_hz / df
+        if abs(shift - round(shift)) > 1e-6:
+            raise ValueError("channel offset must fall on a DFT bin")
+        self.shift = int(round(shift))
+        f = torch.fft.fftfreq(t_len, d=1.0 / sample_rate, device=device, dtype=torch.float64)
+        h = rrc_amplitude(f, baud, rolloff) / math.sqrt(power_w / 2.0)
+        self.h = h.to(torch.complex64)
+
+    def __call__(self, y: torch.Tensor) -> torch.Tensor:
+        spec = torch.fft.fft(y, dim=-1)
+        if self.shift:
+            spec = torch.roll(spec, -self.shift, dims=-1)
+        z = torch.fft.ifft(spec * self.h, dim=-1)
+        return z[..., :: self.sps]
+
+
+def phase_aligned_mse(z: torch.Tensor, s: torch.Tensor) -> torch.Tensor:
+    """Mean |z exp(-j phi) - s|^2 with phi = arg sum z conj(s) per realisation
+    (the common phase is estimated, not learned, so it is held constant)."""
+    with torch.no_grad():
+        corr = (z * s.conj()).sum(dim=(-2, -1), keepdim=True)
+        rot = torch.exp(-1j * torch.angle(corr)).to(z.dtype)
+    return (z * rot - s).abs().pow(2).mean()
+
+
+def fit(plan, fields: torch.Tensor, symbols: torch.Tensor, receiver: SymbolReceiver, coeffs0, rho0: float,
+        iters: int = 200, lr: float = 1e-2, checkpoint_every: int = 1, fit_rho: bool = True):
+    """Adam on (C, rho) for ``iters`` iterations; returns (coeffs, rho, losses).
+
+    fields: complex64 (B, 2, T) on the device; symbols: complex64 (B, 2, n)
+    transmitted symbols of the channel the receiver selects.  The update of C
+    is taken in units of the initial coefficients' scale so that one learning
+    rate suits every tap.
+    """
+    c0 = torch.as_tensor(coeffs0, dtype=torch.float32, device=fields.device)
+    scale = c0.abs().max().clamp_min(1e-12)
+    u = (c0 / scale).clone().requires_grad_(True)
+    rho = torch.tensor(float(rho0), dtype=torch.float32, device=fields.device, requires_grad=fit_rho)
+    params = [u, rho] if fit_rho else [u]
+    opt = torch.optim.Adam(params, lr=lr)
+    losses = []
+    for _ in range(iters):
+        opt.zero_grad(set_to_none=True)
+        y = cbessfm(fields, (u * scale).contiguous(), rho, plan, checkpoint_every)
+        loss = phase_aligned_mse(receiver(y), symbols)
+        loss.backward()
+        opt.step()
+        with torch.no_grad():
+            rho.clamp_(0.0, 1.0)
+        losses.append(loss.detach())
+    return (u * scale).detach(), rho.detach(), torch.stack(losses)
