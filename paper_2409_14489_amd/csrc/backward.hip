@@ -99,7 +99,7 @@ __device__ __forceinline__ void coeff_grad(const TeamCtx& c, uint64_t* xrow, uns
 
   __syncthreads();
 #pragma unroll
-  for (int o = 0; o < RR; ++o) th[pad_f(t + NT * o)] = tb_own[o];
+  for (int o = 0; o < RR; ++o) th[pad_r(t + NT * o)] = tb_own[o];
   {
     float v[RR];
     if (nsb > 1 && me != 0) {
@@ -112,18 +112,18 @@ __device__ __forceinline__ void coeff_grad(const TeamCtx& c, uint64_t* xrow, uns
   __syncthreads();
   float tb[RR];  // block mapping t RR + q
 #pragma unroll
-  for (int q = 0; q < RR; ++q) tb[q] = th[pad_f(t * RR + q)];
+  for (int q = 0; q < RR; ++q) tb[q] = th[pad_r(t * RR + q)];
 
   for (int l = 0; l < nsb; ++l) {
     const float* cur = lf + (l & 1) * PB;
     const bool fetch = (l + 1 < nsb) && (l + 1 != me);
     uint64_t w[RR];
     if (fetch) xissue<RR>(xrow + (size_t)(l + 1) * N, t, NT, w);
-    for (int ch = 0; ch < c.n_chunks; ++ch) {
-      float win[RR + kTapChunk - 1];
-      const int base = t * RR - (kTapChunk - 1) - kTapChunk * ch + nc + hl;
-#pragma unroll
-      for (int i = 0; i < RR + kTapChunk - 1; ++i) win[i] = cur[pad_f(base + i)];
+    // window W[i] = cur[t RR + i]; chunk ch of taps reads W[tap_pad - 8 ch - 8 + i]
+    float win[RR + kTapChunk];
+    int start = t * RR;
+    load_row4<RR + kTapChunk, 0>(cur, start, win);
+    for (int ch = c.n_chunks - 1; ch >= 0; --ch) {
       float part[kTapChunk];
 #pragma unroll
       for (int tt = 0; tt < kTapChunk; ++tt) {
@@ -134,6 +134,12 @@ __device__ __forceinline__ void coeff_grad(const TeamCtx& c, uint64_t* xrow, uns
       }
       const float z = wave_sum8(part, lane);
       if ((lane & 7) == 0) red[(kTapChunk * ch + (lane >> 3)) * NW + wave] = z;
+      if (ch > 0) {
+#pragma unroll
+        for (int i = 0; i < RR; ++i) win[i] = win[i + kTapChunk];
+        start += kTapChunk;
+        load_row4<kTapChunk, RR>(cur, start + RR, win);
+      }
     }
     if (l + 1 < nsb) {
       if (fetch) {
@@ -342,13 +348,26 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void bwd_kernel(BwdArgs 
 }
 
 // ------------------------------------------------------------------ reductions
-// out[j] = sum over items of part[item][j], in FP64, items in order.
-__global__ void reduce_items_kernel(const float* __restrict__ part, float* __restrict__ out, int n_items, int per_item) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= per_item) return;
+// out[j] = sum over items of part[item][j] in FP64.  Thread (jj, g) of a
+// 64 x 16 block sums items g, g + 16, ... in order; the 16 partial sums are
+// then added in a fixed tree order, so the result does not depend on timing.
+constexpr int kRedJ = 64, kRedG = 16;
+__global__ __launch_bounds__(kRedJ * kRedG) void reduce_items_kernel(const float* __restrict__ part,
+                                                                     float* __restrict__ out, int n_items,
+                                                                     int per_item) {
+  __shared__ double buf[kRedG][kRedJ];
+  const int jj = threadIdx.x % kRedJ, g = threadIdx.x / kRedJ;
+  const int j = blockIdx.x * kRedJ + jj;
   double acc = 0.0;
-  for (int it = 0; it < n_items; ++it) acc += (double)part[(size_t)it * per_item + j];
-  out[j] = (float)acc;
+  if (j < per_item)
+    for (int it = g; it < n_items; it += kRedG) acc += (double)part[(size_t)it * per_item + j];
+  buf[g][jj] = acc;
+  __syncthreads();
+  for (int w = kRedG / 2; w > 0; w >>= 1) {
+    if (g < w) buf[g][jj] += buf[g + w][jj];
+    __syncthreads();
+  }
+  if (g == 0 && j < per_item) out[j] = (float)buf[0][jj];
 }
 
 __global__ void reduce_rho_kernel(const double* __restrict__ part, float* __restrict__ out, int n) {
@@ -511,7 +530,7 @@ int launch_backward(cbessfm_plan_t* p, const void* field_in, const void* grad_ou
   }
   if (rc) return rc;
   const int per_item = p->steps * a.n_sb * a.n_sb * p->n_taps;
-  reduce_items_kernel<<<(per_item + 255) / 256, 256, 0, s>>>(a.cpart, grad_c, a.n_items, per_item);
+  reduce_items_kernel<<<(per_item + kRedJ - 1) / kRedJ, kRedJ * kRedG, 0, s>>>(a.cpart, grad_c, a.n_items, per_item);
   reduce_rho_kernel<<<1, 256, 0, s>>>(a.rpart, grad_rho, a.n_items * a.n_sb);
   if (grad_in) {
     const long long total = (long long)batch * 2 * T;

@@ -194,6 +194,11 @@ __device__ __forceinline__ void coupled_fir(const TeamCtx& c, const float* __res
   }
   __syncthreads();
 
+  // The row of member l, circularly extended, is W[i] = cur[t RR + i] for this
+  // thread's outputs k = t RR + q:  out[q] += sum_tau c[tau] W[q - tau + tap_pad - 1].
+  // Taps go in chunks of 8 from the last chunk down; chunk ch reads
+  // W[tap_pad - 8 ch - 8 + i], i < RR + 8, so each next chunk's window is the
+  // previous one moved by 8 (RR floats are kept, 8 are read).
   float acc[RR];
 #pragma unroll
   for (int q = 0; q < RR; ++q) acc[q] = 0.0f;
@@ -203,17 +208,21 @@ __device__ __forceinline__ void coupled_fir(const TeamCtx& c, const float* __res
     uint64_t w[RR];
     if (fetch) xissue<RR>(xrow + (size_t)(l + 1) * N, t, NT, w);  // in flight during the filter
     const float* cl = crow + (size_t)l * tap_pad;
-    for (int ch = 0; ch < c.n_chunks; ++ch) {
-      // window i in [0, RR + 7): row index t RR + i - 7 - 8 ch + nc, stored at + hl
-      float win[RR + kTapChunk - 1];
-      const int base = t * RR - (kTapChunk - 1) - kTapChunk * ch + nc + hl;
-#pragma unroll
-      for (int i = 0; i < RR + kTapChunk - 1; ++i) win[i] = cur[pad_f(base + i)];
+    float win[RR + kTapChunk];
+    int start = t * RR;  // = t RR + tap_pad - 8 n_chunks
+    load_row4<RR + kTapChunk, 0>(cur, start, win);
+    for (int ch = c.n_chunks - 1; ch >= 0; --ch) {
 #pragma unroll
       for (int tt = 0; tt < kTapChunk; ++tt) {
         const float cf = cl[kTapChunk * ch + tt];
 #pragma unroll
         for (int q = 0; q < RR; ++q) acc[q] = fmaf(cf, win[q - tt + kTapChunk - 1], acc[q]);
+      }
+      if (ch > 0) {
+#pragma unroll
+        for (int i = 0; i < RR; ++i) win[i] = win[i + kTapChunk];
+        start += kTapChunk;
+        load_row4<kTapChunk, RR>(cur, start + RR, win);
       }
     }
     if (l + 1 < nsb) {
@@ -229,10 +238,11 @@ __device__ __forceinline__ void coupled_fir(const TeamCtx& c, const float* __res
   }
   // block mapping (t RR + q) -> owned positions (t + NT o)
 #pragma unroll
-  for (int q = 0; q < RR; ++q) th[pad_f(t * RR + q)] = acc[q];
+  for (int q = 0; q < RR; q += 4)
+    *reinterpret_cast<float4*>(th + pad_r(t * RR + q)) = make_float4(acc[q], acc[q + 1], acc[q + 2], acc[q + 3]);
   __syncthreads();
 #pragma unroll
-  for (int o = 0; o < RR; ++o) out[o] = th[pad_f(t + NT * o)];
+  for (int o = 0; o < RR; ++o) out[o] = th[pad_r(t + NT * o)];
 }
 
 // x / y *= exp(-+ j theta): '-' (SIGN = -1) is the rotation of eq. (3).

@@ -140,11 +140,17 @@ __device__ __forceinline__ int frame_first(int blk, int hop, int n_ov, int T, in
 
 // LDS of the nonlinear stage (aliases the FFT exchange buffers): two rows of
 // circularly extended intensities, one row of phases and the per-wave tap
-// sums of the coefficient gradient, in floats.
+// sums of the coefficient gradient, in floats.  Rows use the layout pad_r:
+// four floats of padding after every 32, so aligned groups of four stay
+// contiguous (128-bit reads) and lanes reading 4, 8 or 16 floats apart fall
+// on different banks.
+__device__ __forceinline__ int pad_r(int i) { return i + ((i >> 5) << 2); }
+__host__ __device__ constexpr int pad_r_size(int n) { return ((n + ((n >> 5) << 2) + 8) + 3) & ~3; }
+
 template <int N>
 struct NlprLds {
-  static constexpr int PB = pad_f_size(N + kMaxTaps + 2 * kTapChunk);
-  static constexpr int TH = pad_f_size(N);
+  static constexpr int PB = pad_r_size(N + kMaxTaps + 3 * kTapChunk + FftShape<N>::RR);
+  static constexpr int TH = pad_r_size(N);
   static constexpr int RED = (kMaxTaps + 1) * (FftShape<N>::NT / 64);  // per-wave tap sums (adjoint)
   static constexpr int FLOATS = 2 * PB + TH + RED;
 };
@@ -154,16 +160,31 @@ constexpr int lds_floats() {
 }
 
 // Writes values held at positions t + NT o (o < RR) into a circularly extended
-// LDS row: row[pad_f(k + hl)] = v[k], plus the wrapped copies for the left
+// LDS row: row[pad_r(k + hl)] = v[k], plus the wrapped copies for the left
 // halo (hl samples) and the right halo (hr samples).
 template <int N, int RR, int NT>
 __device__ __forceinline__ void stage_row(float* row, const float (&v)[RR], int t, int hl, int hr) {
 #pragma unroll
   for (int o = 0; o < RR; ++o) {
     const int k = t + NT * o;
-    row[pad_f(k + hl)] = v[o];
-    if (k >= N - hl) row[pad_f(k - N + hl)] = v[o];
-    if (k < hr) row[pad_f(k + N + hl)] = v[o];
+    row[pad_r(k + hl)] = v[o];
+    if (k >= N - hl) row[pad_r(k - N + hl)] = v[o];
+    if (k < hr) row[pad_r(k + N + hl)] = v[o];
+  }
+}
+
+// CNT (a multiple of 4) consecutive floats of a pad_r row from index `start`
+// (a multiple of 4) into w[OFF ..), by 128-bit reads.
+template <int CNT, int OFF, int W>
+__device__ __forceinline__ void load_row4(const float* row, int start, float (&w)[W]) {
+  static_assert(CNT % 4 == 0 && OFF + CNT <= W, "window");
+#pragma unroll
+  for (int i = 0; i < CNT; i += 4) {
+    const float4 v = *reinterpret_cast<const float4*>(row + pad_r(start + i));
+    w[OFF + i] = v.x;
+    w[OFF + i + 1] = v.y;
+    w[OFF + i + 2] = v.z;
+    w[OFF + i + 3] = v.w;
   }
 }
 
