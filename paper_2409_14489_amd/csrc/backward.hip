@@ -184,8 +184,7 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void bwd_kernel(BwdArgs 
   __shared__ __align__(16) float lf[lds_floats<N>()];
   __shared__ double rho_red[NW];
   __shared__ unsigned epoch_word;
-  float2* lx = reinterpret_cast<float2*>(lf);
-  float2* ly = lx + S::LDS_C;
+  float4* lxy = reinterpret_cast<float4*>(lf);
 
   TeamCtx c;
   c.nsb = a.n_sb;
@@ -224,7 +223,7 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void bwd_kernel(BwdArgs 
     auto forward_step = [&](int s) {
       t = opaque_tid();
       apply_diag<N, false>(x, y, (s == 0 ? a.tab.h_first : a.tab.h_mid) + (size_t)me * N, t);
-      fft<N, true>(x, y, lx, ly, tw, t);
+      fft<N, true>(x, y, lxy, tw, t);
       float p[RR], theta[RR];
       intensity<N>(x, y, p);
       uint64_t* xrow = a.xp + ((size_t)c.team * 2 + (np & 1u)) * nsb * N;
@@ -232,13 +231,13 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void bwd_kernel(BwdArgs 
       ++rnd;
       ++np;
       rotate<N, -1>(x, y, theta);
-      fft<N, false>(x, y, lx, ly, tw, t);
+      fft<N, false>(x, y, lxy, tw, t);
     };
 
     // ---- A: forward sweep, storing S_s every k steps
     const float2* in_x = a.in + (size_t)inst * 2 * T;
     gather_block<N, false>(in_x, in_x + T, blk, a.hop, a.n_ov, T, a.boundary, nsb, me, t, x, y);
-    fft<N, false>(x, y, lx, ly, tw, t);
+    fft<N, false>(x, y, lxy, tw, t);
     polyphase_to_subband<N>(c, xs_a, rnd++, t, x, y);
     for (int s = 0; s < a.steps; ++s) {
       if (s % k == 0) store_state<N>(st(s / k), x, y, opaque_tid());
@@ -250,7 +249,7 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void bwd_kernel(BwdArgs 
     apply_diag<N, false>(x, y, a.tab.h_last + (size_t)me * N, t);  // B
     const float2* go_x = a.gout + (size_t)inst * 2 * T;
     gather_block<N, true>(go_x, go_x + T, blk, a.hop, a.n_ov, T, a.boundary, nsb, me, t, gx, gy);
-    fft<N, false>(gx, gy, lx, ly, tw, t);
+    fft<N, false>(gx, gy, lxy, tw, t);
     polyphase_to_subband<N>(c, xs_b, rnd++, t, gx, gy);  // g_B
     rho_acc -= rho_term<N>(phase_km, a.L, t, gx, gy, x, y);
     apply_diag<N, true>(gx, gy, a.tab.h_last + (size_t)me * N, t);  // g_{S_Nst}
@@ -272,7 +271,7 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void bwd_kernel(BwdArgs 
         const float2* hs = (s == 1 ? a.tab.h_first : a.tab.h_mid) + (size_t)me * N;
         // recompute v, p, theta of step s
         apply_diag<N, false>(x, y, hs, t);
-        fft<N, true>(x, y, lx, ly, tw, t);
+        fft<N, true>(x, y, lxy, tw, t);
         float p[RR], theta[RR], tbar[RR];
         intensity<N>(x, y, p);
         const unsigned tag_p = rnd++;
@@ -280,7 +279,7 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void bwd_kernel(BwdArgs 
         ++np;
         coupled_fir<N>(c, a.tab.cpad + ((size_t)((s - 1) * nsb + me) * nsb) * tap_pad, prow, tag_p, p, theta, lf);
         // g_w, theta_bar
-        fft<N, true>(gx, gy, lx, ly, tw, t);
+        fft<N, true>(gx, gy, lxy, tw, t);
 #pragma unroll
         for (int o = 0; o < RR; ++o) {
           float sn, cs;
@@ -303,7 +302,7 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void bwd_kernel(BwdArgs 
           gx[o] = make_float2(fmaf(2.0f * pbar[o], x[o].x, gx[o].x), fmaf(2.0f * pbar[o], x[o].y, gx[o].y));
           gy[o] = make_float2(fmaf(2.0f * pbar[o], y[o].x, gy[o].x), fmaf(2.0f * pbar[o], y[o].y, gy[o].y));
         }
-        fft<N, false>(gx, gy, lx, ly, tw, t);  // g_A
+        fft<N, false>(gx, gy, lxy, tw, t);  // g_A
         if (s == 1) {                          // first GVD depends on rho
           load_state<N>(st(0), x, y, t);
           apply_diag<N, false>(x, y, hs, t);  // A1
@@ -317,7 +316,7 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void bwd_kernel(BwdArgs 
     if (a.gin_blk != nullptr) {
       t = opaque_tid();
       subband_to_polyphase<N>(c, xs_b, rnd++, t, gx, gy);
-      fft<N, true>(gx, gy, lx, ly, tw, t);
+      fft<N, true>(gx, gy, lxy, tw, t);
       float2* dst = a.gin_blk + (size_t)item * 2 * nsb * N;
 #pragma unroll
       for (int o = 0; o < RR; ++o) {

@@ -191,24 +191,47 @@ struct FftShape {
     }
     return p;
   }
-  // twiddle registers of pass p (>= 1): (RR / R_p) butterflies x (R_p - 1)
-  static constexpr int tw_offset(int p) {
-    int off = 0;
-    for (int q = 1; q < p; ++q) off += (RR / radix(q)) * (radix(q) - 1);
-    return off;
-  }
-  static constexpr int TWC = tw_offset(passes());
-  static constexpr int LDS_C = pad_c_size(N);  // float2 entries per exchange buffer
+  static constexpr int LDS_C = pad_c_size(N);  // float2 entries per polarisation (float4 entries in all)
 };
 
-// One Stockham pass p of radix R over both polarisations.
+// Twiddle registers of pass P: NB butterflies x (R - 1) factors (one dummy
+// for passes without twiddles).
+template <int N, int P>
+struct PassTw {
+  static constexpr int R = FftShape<N>::radix(P);
+  static constexpr int NB = FftShape<N>::RR / R;
+  static constexpr int C = (P == 0 || P >= FftShape<N>::passes() || R < 2) ? 1 : NB * (R - 1);
+};
+template <int N, int P>
+using PassTwRegs = float2[PassTw<N, P>::C];
+
+// Loads the twiddles W_{L R}^{k m} = table[k m N / (L R)], k = j mod L, of
+// pass P.  They depend only on the thread, so they are issued one pass ahead.
+template <int N, int P>
+__device__ __forceinline__ void load_pass_tw(PassTwRegs<N, P>& w, const float2* __restrict__ twt, int t) {
+  using S = FftShape<N>;
+  if constexpr (P > 0 && P < S::passes()) {
+    constexpr int R = S::radix(P);
+    constexpr int L = S::stride(P);
+    constexpr int NB = S::RR / R;
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      const int k = (t + S::NT * a) % L;
+#pragma unroll
+      for (int m = 1; m < R; ++m) w[a * (R - 1) + m - 1] = twt[(k * m * (N / (L * R))) % N];
+    }
+  }
+}
+
+// One Stockham pass p of radix R over both polarisations.  The exchange
+// buffer holds (x.re, x.im, y.re, y.im) per position, so each value moves
+// through LDS with one 128-bit access.
 //   FIRST: inputs come from the owned registers (positions t + NT o)
 //   LAST : outputs go to the owned registers
 // Otherwise inputs are read from / outputs written to LDS.
 template <int N, int P, bool INV>
 __device__ __forceinline__ void fft_pass(float2 (&x)[FftShape<N>::RR], float2 (&y)[FftShape<N>::RR],
-                                         float2* __restrict__ lx, float2* __restrict__ ly,
-                                         const float2* __restrict__ twt, int t) {
+                                         float4* __restrict__ lxy, const PassTwRegs<N, P>& w, int t) {
   using S = FftShape<N>;
   constexpr int R = S::radix(P);
   constexpr int L = S::stride(P);
@@ -216,16 +239,6 @@ __device__ __forceinline__ void fft_pass(float2 (&x)[FftShape<N>::RR], float2 (&
   constexpr bool FIRST = (P == 0);
   constexpr bool LAST = (P == S::passes() - 1);
   constexpr int NR = N / R;
-  // twiddles W_{L R}^{k m} = table[k m N / (L R)], k = j mod L, issued first
-  float2 w[NB][R > 1 ? R - 1 : 1];
-  if constexpr (!FIRST) {
-#pragma unroll
-    for (int a = 0; a < NB; ++a) {
-      const int k = (t + S::NT * a) % L;
-#pragma unroll
-      for (int m = 1; m < R; ++m) w[a][m - 1] = twt[(k * m * (N / (L * R))) % N];
-    }
-  }
   // gather inputs: vx[a][m] = x[j + m N/R], j = t + NT a
   float2 vx[NB][R], vy[NB][R];
 #pragma unroll
@@ -236,9 +249,9 @@ __device__ __forceinline__ void fft_pass(float2 (&x)[FftShape<N>::RR], float2 (&
         vx[a][m] = x[a + m * NB];
         vy[a][m] = y[a + m * NB];
       } else {
-        const int idx = pad_c(t + S::NT * a + m * NR);
-        vx[a][m] = lx[idx];
-        vy[a][m] = ly[idx];
+        const float4 v = lxy[pad_c(t + S::NT * a + m * NR)];
+        vx[a][m] = make_float2(v.x, v.y);
+        vy[a][m] = make_float2(v.z, v.w);
       }
     }
   if constexpr (!FIRST && !LAST) __syncthreads();  // everyone has read before anyone writes
@@ -247,8 +260,8 @@ __device__ __forceinline__ void fft_pass(float2 (&x)[FftShape<N>::RR], float2 (&
     if constexpr (!FIRST) {
 #pragma unroll
       for (int m = 1; m < R; ++m) {
-        vx[a][m] = twmul<INV>(vx[a][m], w[a][m - 1]);
-        vy[a][m] = twmul<INV>(vy[a][m], w[a][m - 1]);
+        vx[a][m] = twmul<INV>(vx[a][m], w[a * (R - 1) + m - 1]);
+        vy[a][m] = twmul<INV>(vy[a][m], w[a * (R - 1) + m - 1]);
       }
     }
     dft<R, INV>(vx[a]);
@@ -264,9 +277,7 @@ __device__ __forceinline__ void fft_pass(float2 (&x)[FftShape<N>::RR], float2 (&
         x[a + m * NB] = vx[a][m];
         y[a + m * NB] = vy[a][m];
       } else {
-        const int idx = pad_c((j - k) * R + k + m * L);
-        lx[idx] = vx[a][m];
-        ly[idx] = vy[a][m];
+        lxy[pad_c((j - k) * R + k + m * L)] = make_float4(vx[a][m].x, vx[a][m].y, vy[a][m].x, vy[a][m].y);
       }
     }
   }
@@ -275,22 +286,27 @@ __device__ __forceinline__ void fft_pass(float2 (&x)[FftShape<N>::RR], float2 (&
 
 template <int N, int P, bool INV>
 __device__ __forceinline__ void fft_passes(float2 (&x)[FftShape<N>::RR], float2 (&y)[FftShape<N>::RR],
-                                           float2* lx, float2* ly, const float2* twt, int t) {
+                                           float4* lxy, const float2* twt, const PassTwRegs<N, P>& w,
+                                           int t) {
   if constexpr (P < FftShape<N>::passes()) {
-    fft_pass<N, P, INV>(x, y, lx, ly, twt, t);
-    fft_passes<N, P + 1, INV>(x, y, lx, ly, twt, t);
+    PassTwRegs<N, P + 1> w_next;
+    load_pass_tw<N, P + 1>(w_next, twt, t);  // in flight during this pass
+    fft_pass<N, P, INV>(x, y, lxy, w, t);
+    fft_passes<N, P + 1, INV>(x, y, lxy, twt, w_next, t);
   }
 }
 
 // Unnormalised size-N DFT (INV = false: exp(-j...), INV = true: exp(+j...))
 // of the two owned register sets; twt[n] = exp(-j 2 pi n / N) (FP64 values
-// rounded once, read through the L1/L2 caches at the start of each pass).  Starts with a barrier so that earlier LDS
-// readers are done before the first pass overwrites the exchange buffers.
+// rounded once, read through the caches one pass ahead of their use).
+// Starts with a barrier so that earlier LDS readers are done before the first
+// pass overwrites the exchange buffer (N + N/16 + N/256 + 1 float4 entries).
 template <int N, bool INV>
-__device__ __forceinline__ void fft(float2 (&x)[FftShape<N>::RR], float2 (&y)[FftShape<N>::RR],
-                                    float2* lx, float2* ly, const float2* twt, int t) {
+__device__ __forceinline__ void fft(float2 (&x)[FftShape<N>::RR], float2 (&y)[FftShape<N>::RR], float4* lxy,
+                                    const float2* twt, int t) {
+  PassTwRegs<N, 0> w0;
   __syncthreads();
-  fft_passes<N, 0, INV>(x, y, lx, ly, twt, t);
+  fft_passes<N, 0, INV>(x, y, lxy, twt, w0, t);
 }
 
 }  // namespace cbessfm

@@ -28,8 +28,7 @@ __device__ __forceinline__ void fwd_item(TeamCtx& c, const Inst& d, int sub, uns
                                          uint64_t* xs_out, uint64_t* xp_team, float* lf) {
   using S = FftShape<N>;
   constexpr int RR = S::RR;
-  float2* lx = reinterpret_cast<float2*>(lf);
-  float2* ly = lx + S::LDS_C;
+  float4* lxy = reinterpret_cast<float4*>(lf);
   const int nsb = c.nsb, me = c.me;
   const float2* tw = d.tab.tw;
   const int T = d.T;
@@ -42,28 +41,28 @@ __device__ __forceinline__ void fwd_item(TeamCtx& c, const Inst& d, int sub, uns
 
   // ---- block input: size-N DFT as N_sb polyphase FFTs + N_sb-point DFT
   gather_block<N, false>(in_x, in_x + T, blk, d.hop, d.n_ov, T, d.boundary, nsb, me, t, x, y);
-  fft<N, false>(x, y, lx, ly, tw, t);
+  fft<N, false>(x, y, lxy, tw, t);
   polyphase_to_subband<N>(c, xs_in, round0, t, x, y);
 
   // ---- step loop (Fig. "scheme_CB-ESSFM"), spectra in subband order
   for (int s = 0; s < d.steps; ++s) {
     t = opaque_tid();
     apply_diag<N, false>(x, y, (s == 0 ? d.tab.h_first : d.tab.h_mid) + (size_t)me * N, t);
-    fft<N, true>(x, y, lx, ly, tw, t);  // lowpass-equivalent subband samples
+    fft<N, true>(x, y, lxy, tw, t);  // lowpass-equivalent subband samples
     float p[RR], theta[RR];
     intensity<N>(x, y, p);
     const unsigned round = round0 + 1u + (unsigned)s;
     uint64_t* xrow = xp_team + (size_t)(round & 1u) * nsb * N;
     coupled_fir<N>(c, d.tab.cpad + ((size_t)(s * nsb + me) * nsb) * tap_pad, xrow, round, p, theta, lf);
     rotate<N, -1>(x, y, theta);
-    fft<N, false>(x, y, lx, ly, tw, t);
+    fft<N, false>(x, y, lxy, tw, t);
   }
 
   // ---- final GVD, recombination, inverse size-N DFT, kept samples
   t = opaque_tid();
   apply_diag<N, false>(x, y, d.tab.h_last + (size_t)me * N, t);
   subband_to_polyphase<N>(c, xs_out, round0 + (unsigned)d.steps + 1u, t, x, y);
-  fft<N, true>(x, y, lx, ly, tw, t);
+  fft<N, true>(x, y, lxy, tw, t);
   float2* out_x = d.out + (size_t)inst * 2 * T;
   scatter_block<N>(out_x, out_x + T, blk, d.hop, d.n_ov, T, nsb, me, t, x, y);
 }
