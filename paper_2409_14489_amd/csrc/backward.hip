@@ -283,7 +283,7 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void bwd_kernel(BwdArgs 
 #pragma unroll
         for (int o = 0; o < RR; ++o) {
           float sn, cs;
-          sincosf(theta[o], &sn, &cs);
+          phase_sincos(theta[o], sn, cs);
           const float2 rot = make_float2(cs, -sn);
           const float2 wx = cmul(x[o], rot), wy = cmul(y[o], rot);
           tbar[o] = (gx[o].x * wx.y - gx[o].y * wx.x) + (gy[o].x * wy.y - gy[o].y * wy.x);

@@ -12,6 +12,7 @@
 
 #include "fft_lds.hpp"
 #include "internal.hpp"
+#include "sincos.hpp"
 #include "team.hpp"
 
 namespace cbessfm {
@@ -253,7 +254,7 @@ __device__ __forceinline__ void rotate(float2 (&x)[FftShape<N>::RR], float2 (&y)
 #pragma unroll
   for (int o = 0; o < RR; ++o) {
     float sn, cs;
-    sincosf(theta[o], &sn, &cs);
+    phase_sincos(theta[o], sn, cs);
     const float2 r = make_float2(cs, SIGN < 0 ? -sn : sn);
     x[o] = cmul(x[o], r);
     y[o] = cmul(y[o], r);
