@@ -183,7 +183,8 @@ def leg_forward(args):
         "config": {"workload": WORKLOAD, "T": t_len, "batch": 1, "n_sb": d["n_sb"], "block_sb": d["n_sub"],
                    "overlap": d["n_overlap"], "steps": d["n_steps"], "split_ratio": d["rho"],
                    "n_taps": d["n_taps"], "blocks": nblk, "kernel": "cbessfm::fwd_kernel<12>",
-                   "threads_per_group": plan.info().threads_per_group},
+                   "threads_per_group": plan.info().threads_per_group,
+                   "kernel_source_sha256": kernel_source_digest()},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "flops_per_launch": flops, "kernel_ms": kernel_s * 1e3},
