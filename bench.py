@@ -5,7 +5,8 @@ Primary workload (the JSON line's value): 5 WDM channels x 64 GBd DP-64QAM on a
 polarisation), 15 x 80 km SMF; backpropagation with 5 subbands, N' = 4096,
 N_ov = 2560, 15 asymmetric steps (rho = 0.3) and 21 analytic taps, one
 persistent launch per pass.  A "step" of this benchmark is one pass of the
-hot path over that field.
+hot path over that field; the timed passes are replayed from a HIP graph
+(the eager, cooperative-launch time per pass is reported beside it).
 
 Two more legs are reported in the same line:
   grad     1 ch 32 GBd DP-16QAM, 2^14 symbols, 1 x 80 km, 16 realisations,
@@ -144,19 +145,32 @@ def leg_forward(args):
     torch.cuda.synchronize()
     if plan.status() != 0:
         raise RuntimeError("device error flag set during warm-up")
+    # eager launches (cooperative), for reference
+    eager_s = timed_events(stream, lambda: plan.run(xin, out=yout), max(1, args.steps // 4))
 
+    # timed passes: the launches are replayed from a HIP graph (ordinary
+    # kernel nodes of the resident-sized persistent grid), `per_graph` per replay
+    per_graph = 10 if args.steps % 10 == 0 else 1
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for _ in range(per_graph):
+            plan.run(xin, out=yout)
+    graph.replay()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(stream)
-    for _ in range(args.steps):
-        plan.run(xin, out=yout)
+    for _ in range(args.steps // per_graph):
+        graph.replay()
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     if plan.status() != 0:
         raise RuntimeError("device error flag set during the timed region")
     kernel_s = ev0.elapsed_time(ev1) / 1e3 / args.steps   # one launch per pass
+    del graph
 
     n2d = wdm.n_channels * 2 * wdm.n_symbols                # 2D symbols per pass
     nblk = plan.n_blocks(t_len)
@@ -188,6 +202,8 @@ def leg_forward(args):
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "flops_per_launch": flops, "kernel_ms": kernel_s * 1e3},
+        "launch": {"timed": f"HIP graph replays, {per_graph} launch(es) per replay",
+                   "eager_cooperative_ms_per_step": eager_s * 1e3},
         "hbm_roofline": {"achieved": hbm_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                          "frac": hbm_gbs / PEAK_HBM_GBS, "bytes_per_launch": alg_bytes},
     }

@@ -113,28 +113,53 @@ __device__ __forceinline__ void put_spectrum(uint64_t* dst, const float2 (&x)[Ff
 }
 
 // x / y = sum over members n2 of w_n2 * (member n2's spectrum),
-// w_n2 = wsb[(n2 me) mod n_sb], conjugated when CONJ.
+// w_n2 = wsb[(n2 me) mod n_sb], conjugated when CONJ.  On entry x / y hold
+// this member's own spectrum (already published), which is used from the
+// registers; the other members' spectra come from the exchange.
 template <int N, bool CONJ>
 __device__ __forceinline__ void combine_spectra(const uint64_t* src, const TeamCtx& c, unsigned tag, int t,
                                                 float2 (&x)[FftShape<N>::RR], float2 (&y)[FftShape<N>::RR]) {
   constexpr int RR = FftShape<N>::RR, NT = FftShape<N>::NT;
+  {
+    const float2 w = c.tab->wsb[(c.me * c.me) % c.nsb];
 #pragma unroll
-  for (int o = 0; o < RR; ++o) x[o] = y[o] = make_float2(0.f, 0.f);
+    for (int o = 0; o < RR; ++o) {
+      x[o] = CONJ ? cmulc(x[o], w) : cmul(x[o], w);
+      y[o] = CONJ ? cmulc(y[o], w) : cmul(y[o], w);
+    }
+  }
   for (int n2 = 0; n2 < c.nsb; ++n2) {
+    if (n2 == c.me) continue;
     const float2 w = c.tab->wsb[(n2 * c.me) % c.nsb];
     const uint64_t* row = src + (size_t)n2 * 4 * N;
+    // all four components of the member in flight at once (two at a time
+    // when the register file cannot hold them)
+    constexpr bool ALL4 = RR <= 8;
+    uint64_t wxr[RR], wxi[RR], wyr[RR], wyi[RR];
+    xissue<RR>(row, t, NT, wxr);
+    xissue<RR>(row + N, t, NT, wxi);
+    if constexpr (ALL4) {
+      xissue<RR>(row + 2 * N, t, NT, wyr);
+      xissue<RR>(row + 3 * N, t, NT, wyi);
+    }
+    float re[RR], im[RR];
+    xcomplete<RR>(row, t, NT, tag, c.ctl, wxr, re);
+    xcomplete<RR>(row + N, t, NT, tag, c.ctl, wxi, im);
 #pragma unroll
-    for (int comp = 0; comp < 2; ++comp) {  // polarisation x, then y
-      float re[RR], im[RR];
-      xget<RR>(row + (2 * comp) * N, t, NT, tag, c.ctl, re);
-      xget<RR>(row + (2 * comp + 1) * N, t, NT, tag, c.ctl, im);
+    for (int o = 0; o < RR; ++o) {
+      const float2 v = make_float2(re[o], im[o]);
+      x[o] = cadd(x[o], CONJ ? cmulc(v, w) : cmul(v, w));
+    }
+    if constexpr (!ALL4) {
+      xissue<RR>(row + 2 * N, t, NT, wyr);
+      xissue<RR>(row + 3 * N, t, NT, wyi);
+    }
+    xcomplete<RR>(row + 2 * N, t, NT, tag, c.ctl, wyr, re);
+    xcomplete<RR>(row + 3 * N, t, NT, tag, c.ctl, wyi, im);
 #pragma unroll
-      for (int o = 0; o < RR; ++o) {
-        const float2 v = make_float2(re[o], im[o]);
-        const float2 prod = CONJ ? cmulc(v, w) : cmul(v, w);
-        if (comp == 0) x[o] = cadd(x[o], prod);
-        else y[o] = cadd(y[o], prod);
-      }
+    for (int o = 0; o < RR; ++o) {
+      const float2 v = make_float2(re[o], im[o]);
+      y[o] = cadd(y[o], CONJ ? cmulc(v, w) : cmul(v, w));
     }
   }
 }
@@ -183,11 +208,14 @@ __device__ __forceinline__ void coupled_fir(const TeamCtx& c, const float* __res
 #pragma unroll
     for (int o = 0; o < RR; ++o) xput(xrow + (size_t)me * N + t + NT * o, own[o], tag);
   }
-  __syncthreads();  // the LDS rows alias the FFT exchange buffers
   {
-    float v[RR];
-    if (nsb > 1 && me != 0) {
-      xget<RR>(xrow, t, NT, tag, c.ctl, v);
+    const bool remote0 = nsb > 1 && me != 0;
+    uint64_t w0[RR];
+    if (remote0) xissue<RR>(xrow, t, NT, w0);  // in flight across the barrier
+    __syncthreads();  // the LDS rows alias the FFT exchange buffers
+    if (remote0) {
+      float v[RR];
+      xcomplete<RR>(xrow, t, NT, tag, c.ctl, w0, v);
       stage_row<N, RR, NT>(lf, v, t, hl, nc);
     } else {
       stage_row<N, RR, NT>(lf, own, t, hl, nc);
