@@ -177,7 +177,7 @@ __device__ __forceinline__ double rho_term(const double* __restrict__ phase_km, 
 }
 
 template <int LOGN>
-__global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void bwd_kernel(BwdArgs a) {
+__global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdArgs a) {
   constexpr int N = 1 << LOGN;  // N'
   using S = FftShape<N>;
   constexpr int RR = S::RR, NT = S::NT, NW = NT / 64;
