@@ -274,23 +274,25 @@ def leg_grad(args):
            "n_taps": d["n_taps"], "parameters": int(c0.size) + 1, "unit": "steps/s",
            "step": "forward + matched-filter MSE + adjoint + Adam update, 16 realisations"}
     stream = torch.cuda.current_stream()
-    for ck in (1, 5):
+    for ck, graph in ((1, True), (5, True), (1, False)):
         fit(plan, x, s, rx, c0, d["rho"], iters=3, checkpoint_every=ck)   # warm-up
         torch.cuda.synchronize()
         torch.cuda.reset_peak_memory_stats()
         base_mem = torch.cuda.memory_allocated()
         t0 = time.perf_counter()
-        c_fit, rho_fit, losses = fit(plan, x, s, rx, c0, d["rho"], iters=iters, checkpoint_every=ck)
+        c_fit, rho_fit, losses = fit(plan, x, s, rx, c0, d["rho"], iters=iters, checkpoint_every=ck, graph=graph)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         if plan.status() != 0:
             raise RuntimeError("device error flag set in the gradient leg")
         peak = torch.cuda.max_memory_allocated() - base_mem
-        key = "store_every_step" if ck == 1 else f"checkpoint_every_{ck}"
+        key = ("store_every_step" if ck == 1 else f"checkpoint_every_{ck}") + ("" if graph else "_eager")
         out[key] = {"steps_per_s": iters / wall, "ms_per_step": wall / iters * 1e3,
                     "peak_extra_mib": peak / 2 ** 20,
-                    "adjoint_workspace_mib": plan.backward_workspace(t_len, n_real, ck) / 2 ** 20}
-        if ck == 1:
+                    "adjoint_workspace_mib": plan.backward_workspace(t_len, n_real, ck) / 2 ** 20,
+                    "launch": "HIP graph of the whole iteration (3 eager warm-up iterations included)"
+                              if graph else "eager"}
+        if ck == 1 and graph:
             mse_fit = mse(c_fit, rho_fit)
             out["adam_iterations"] = iters
             out["snr_db"] = {"edc": -10 * math.log10(mse_edc), "analytic": -10 * math.log10(mse_analytic),

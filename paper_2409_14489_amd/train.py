@@ -75,28 +75,52 @@ def phase_aligned_mse(z: torch.Tensor, s: torch.Tensor) -> torch.Tensor:
 
 
 def fit(plan, fields: torch.Tensor, symbols: torch.Tensor, receiver: SymbolReceiver, coeffs0, rho0: float,
-        iters: int = 200, lr: float = 1e-2, checkpoint_every: int = 1, fit_rho: bool = True):
+        iters: int = 200, lr: float = 1e-2, checkpoint_every: int = 1, fit_rho: bool = True,
+        graph: bool = False, warmup: int = 3):
     """Adam on (C, rho) for ``iters`` iterations; returns (coeffs, rho, losses).
 
     fields: complex64 (B, 2, T) on the device; symbols: complex64 (B, 2, n)
     transmitted symbols of the channel the receiver selects.  The update of C
     is taken in units of the initial coefficients' scale so that one learning
-    rate suits every tap.
+    rate suits every tap.  With ``graph`` the whole iteration (forward,
+    loss, adjoint, Adam update) is recorded once in a HIP graph after
+    ``warmup`` eager iterations and replayed for the rest; ``iters`` counts
+    all of them.
     """
     c0 = torch.as_tensor(coeffs0, dtype=torch.float32, device=fields.device)
     scale = c0.abs().max().clamp_min(1e-12)
     u = (c0 / scale).clone().requires_grad_(True)
     rho = torch.tensor(float(rho0), dtype=torch.float32, device=fields.device, requires_grad=fit_rho)
     params = [u, rho] if fit_rho else [u]
-    opt = torch.optim.Adam(params, lr=lr)
-    losses = []
-    for _ in range(iters):
-        opt.zero_grad(set_to_none=True)
+    opt = torch.optim.Adam(params, lr=lr, capturable=graph)
+
+    def step():
+        opt.zero_grad(set_to_none=not graph)
         y = cbessfm(fields, (u * scale).contiguous(), rho, plan, checkpoint_every)
         loss = phase_aligned_mse(receiver(y), symbols)
         loss.backward()
         opt.step()
         with torch.no_grad():
             rho.clamp_(0.0, 1.0)
-        losses.append(loss.detach())
+        return loss.detach()
+
+    losses = []
+    if not graph:
+        for _ in range(iters):
+            losses.append(step())
+        return (u * scale).detach(), rho.detach(), torch.stack(losses)
+    side = torch.cuda.Stream(device=fields.device)
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(min(warmup, iters)):
+            losses.append(step())
+    torch.cuda.current_stream().wait_stream(side)
+    if iters > warmup:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            static_loss = step()
+        for _ in range(iters - warmup):
+            g.replay()
+            losses.append(static_loss.clone())
+        del g
     return (u * scale).detach(), rho.detach(), torch.stack(losses)
