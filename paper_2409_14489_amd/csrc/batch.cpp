@@ -231,9 +231,10 @@ int probe_time(const cbessfm_link* link, int log_np, int nsb, int n_taps, int st
     }
     if (!rc) rc = cbessfm_status(p);
   }
-  if (e0) hipEventDestroy(e0);
-  if (e1) hipEventDestroy(e1);
-  if (buf) hipFree(buf);
+  // release: failures here cannot change the measurement
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (buf) (void)hipFree(buf);
   cbessfm_destroy(p);
   if (!rc) *out_s = best;
   return rc;
@@ -405,11 +406,12 @@ int cbessfm_autotune(const cbessfm_link* link, int32_t n_sb, int32_t steps, int3
 
 void cbessfm_batch_destroy(cbessfm_batch_t* b) {
   if (!b) return;
+  // a void release path: HIP errors are not reportable here
   int prev = 0;
-  hipGetDevice(&prev);
-  hipSetDevice(b->device);
-  for (void* p : b->allocs) hipFree(p);
-  hipSetDevice(prev);
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(b->device);
+  for (void* p : b->allocs) (void)hipFree(p);
+  (void)hipSetDevice(prev);
   delete b;
 }
 

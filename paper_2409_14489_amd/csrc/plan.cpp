@@ -205,14 +205,15 @@ int cbessfm_analytic_coeffs(const cbessfm_link* link, const cbessfm_subbands* sb
 
 void cbessfm_destroy(cbessfm_plan_t* p) {
   if (!p) return;
+  // a void release path: HIP errors are not reportable here
   int prev = 0;
-  hipGetDevice(&prev);
-  hipSetDevice(p->device);
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(p->device);
   void* bufs[] = {p->d_phase, p->d_h,  p->d_tw,    p->d_poly,  p->d_c,     p->d_cpad, p->d_ctpad,
                   p->d_rho,   p->d_xspec, p->d_xp, p->d_xq, p->d_epoch, p->d_abort, p->d_err};
   for (void* b : bufs)
-    if (b) hipFree(b);
-  hipSetDevice(prev);
+    if (b) (void)hipFree(b);
+  (void)hipSetDevice(prev);
   delete p;
 }
 

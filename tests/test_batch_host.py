@@ -134,3 +134,16 @@ def test_model_autotune_rejects_bad_arguments():
     for args in [(0, 1, 11, 1000), (9, 1, 11, 1000), (1, 0, 11, 1000), (1, 1, 10, 1000), (1, 1, 11, 0)]:
         with pytest.raises(CbessfmError):
             autotune(link, *args, measure=False)
+
+
+def test_model_autotune_memory_matches_the_overlap_the_paper_uses():
+    """Sec. IV-A uses N_ov of about 1800 samples for its 15 x 80 km link
+    (D = 17 ps/nm/km, i.e. beta2 = -21.68 ps^2/km at 1550 nm) sampled at
+    1.125 samples per symbol of 93 GBd; the autotuner's group-delay spread of
+    that link must land there."""
+    d_ps_nm_km, lam, c = 17.0, 1550e-9, 299792458.0
+    beta2_ps2_km = -d_ps_nm_km * 1e-6 * lam ** 2 / (2 * math.pi * c) * 1e27
+    assert abs(beta2_ps2_km + 21.68) < 0.01
+    link = LinkSpec(beta2_ps2_km=beta2_ps2_km, n_spans=15, sample_rate_hz=93e9 * 1.125)
+    t = autotune(link, 1, 15, 11, 1 << 16, measure=False)
+    assert abs(t["memory"] - 1800) <= 0.02 * 1800
