@@ -38,6 +38,8 @@ SHAPES = [
     (2, 1024, 256, 5, 0.7, 5, 1500, 1, "circular", 1),     # T < N: a block wraps
     (2, 512, 128, 3, 0.4, 5, 6000, 1, "circular", 2),      # second N' class
     (1, 512, 64, 2, 0.5, 3, 4000, 3, "zero", 1),
+    (2, 8192, 2048, 3, 0.3, 9, 70000, 1, "circular", 3),   # third class: one workgroup per polarisation
+    (1, 8192, 1024, 2, 0.5, 5, 20000, 2, "zero", 2),
 ]
 
 
@@ -65,7 +67,7 @@ def test_batch_matches_oracle_and_single_runs():
     b = Batch([(d["plan"], d["xt"], d["yt"]) for d in insts])
     info = b.info()
     print(info)
-    assert info["launches"] == 2 and info["items"] > 0
+    assert info["launches"] == 3 and info["items"] > 0
     b.run()
     torch.cuda.synchronize()
     assert b.status() == 0
