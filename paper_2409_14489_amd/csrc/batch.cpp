@@ -192,7 +192,7 @@ int team_capacity(int log_np, int nsb, int* teams, int* slots_per_xcd) {
   if (cbessfm::batch_occupancy_per_cu(log_np, &per_cu) != CBESSFM_OK || per_cu < 1) return CBESSFM_EHIP;
   const int spx = per_cu * prop.multiProcessorCount / kXcds;
   if (slots_per_xcd) *slots_per_xcd = spx;
-  if (teams) *teams = (spx / (nsb * (cbessfm::pol_split_for(log_np) ? 2 : 1))) * kXcds;
+  if (teams) *teams = (spx / nsb) * kXcds;
   return CBESSFM_OK;
 }
 
@@ -278,9 +278,6 @@ int item_cost(const cbessfm_link* link, int log_np, int nsb, int n_taps, int ste
   return CBESSFM_OK;
 }
 
-// Subbands of a team of `width` workgroups in a launch of N' = 2^log_np.
-size_t team_subbands(int log_np, int width) { return (size_t)(cbessfm::pol_split_for(log_np) ? width / 2 : width); }
-
 long long dispersion_memory(const cbessfm_link* link) {
   const double beta2 = std::fabs(link->beta2_ps2_km) * 1e-24;  // s^2/km
   const double L = link->span_km * link->n_spans;
@@ -307,9 +304,8 @@ struct cbessfm_batch {
   int* d_err = nullptr;
   uint64_t* d_xspec = nullptr;
   uint64_t* d_xp = nullptr;
-  uint64_t* d_xpar = nullptr;
   unsigned* d_epoch = nullptr;
-  size_t xspec_words = 0, xp_words = 0, xpar_words = 0, n_epoch = 0;
+  size_t xspec_words = 0, xp_words = 0, n_epoch = 0;
 };
 
 namespace {
@@ -324,7 +320,6 @@ int reset_exchange(cbessfm_batch_t* b) {
   if (hipMemset(b->d_err, 0, sizeof(int)) != hipSuccess || hipMemset(b->d_abort, 0, sizeof(unsigned)) != hipSuccess ||
       hipMemset(b->d_xspec, 0, b->xspec_words * sizeof(uint64_t)) != hipSuccess ||
       hipMemset(b->d_xp, 0, b->xp_words * sizeof(uint64_t)) != hipSuccess ||
-      hipMemset(b->d_xpar, 0, b->xpar_words * sizeof(uint64_t)) != hipSuccess ||
       hipMemset(b->d_epoch, 0, b->n_epoch * sizeof(unsigned)) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
     return CBESSFM_EHIP;
   return CBESSFM_OK;
@@ -391,7 +386,7 @@ int cbessfm_autotune(const cbessfm_link* link, int32_t n_sb, int32_t steps, int3
       int rc = team_capacity(log_np, n_sb, &teams, nullptr);
       if (rc) return rc;
     } else {
-      teams = (256 / (kXcds * n_sb * (cbessfm::pol_split_for(log_np) ? 2 : 1))) * kXcds;
+      teams = (256 * (log_np <= 12 ? 2 : 1) / (kXcds * n_sb)) * kXcds;
     }
     if (teams < 1) continue;
     double t_item = 0.0;
@@ -455,7 +450,7 @@ int cbessfm_batch_create(cbessfm_batch_t** out, const cbessfm_instance* inst, in
     std::vector<Inst> insts;
   };
   std::vector<Built> built;
-  size_t xspec_words = 0, xp_words = 0, xpar_words = 0, n_epoch = 0;
+  size_t xspec_words = 0, xp_words = 0, n_epoch = 0;
   int rc = CBESSFM_OK;
   for (auto& kv : by_np) {
     Built bt;
@@ -474,19 +469,15 @@ int cbessfm_batch_create(cbessfm_batch_t** out, const cbessfm_instance* inst, in
       double cost = 0.0;
       rc = item_cost(&p->link, p->log_np, p->sb.n_sb, p->n_taps, p->steps, kCachedOrModel, &cost);
       if (rc) break;
-      // polarisation-split launches give each subband two workgroups
-      const int width = p->sb.n_sb * (cbessfm::pol_split_for(bt.log_np) ? 2 : 1);
-      jobs.push_back(Job{width, (long long)a.batch * d.nblk, cost});
+      jobs.push_back(Job{p->sb.n_sb, (long long)a.batch * d.nblk, cost});
     }
     if (rc) break;
     rc = build_schedule(jobs, spx, bt.s);
     if (rc) break;
     const int np = 1 << bt.log_np;
     for (size_t tm = 0; tm < bt.s.team_width.size(); ++tm) {
-      const size_t nsb = team_subbands(bt.log_np, bt.s.team_width[tm]);
-      xspec_words += 8 * nsb * np;
-      xp_words += 2 * nsb * np;
-      if (cbessfm::pol_split_for(bt.log_np)) xpar_words += 4 * nsb * np;
+      xspec_words += (size_t)2 * bt.s.team_width[tm] * 4 * np;
+      xp_words += (size_t)2 * bt.s.team_width[tm] * np;
       ++n_epoch;
     }
     built.push_back(std::move(bt));
@@ -512,8 +503,6 @@ int cbessfm_batch_create(cbessfm_batch_t** out, const cbessfm_instance* inst, in
   b->n_epoch = n_epoch;
   b->d_xspec = static_cast<uint64_t*>(alloc(xspec_words * sizeof(uint64_t)));
   b->d_xp = static_cast<uint64_t*>(alloc(xp_words * sizeof(uint64_t)));
-  b->xpar_words = xpar_words;
-  b->d_xpar = static_cast<uint64_t*>(alloc((xpar_words ? xpar_words : 1) * sizeof(uint64_t)));
   b->d_epoch = static_cast<unsigned*>(alloc(n_epoch * sizeof(unsigned)));
   b->d_abort = static_cast<unsigned*>(alloc(sizeof(unsigned)));
   b->d_err = static_cast<int*>(alloc(sizeof(int)));
@@ -521,7 +510,7 @@ int cbessfm_batch_create(cbessfm_batch_t** out, const cbessfm_instance* inst, in
     cbessfm_batch_destroy(b);
     return ok ? CBESSFM_EHIP : CBESSFM_ENOMEM;
   }
-  size_t xs_off = 0, xp_off = 0, xpar_off = 0, ep_off = 0;
+  size_t xs_off = 0, xp_off = 0, ep_off = 0;
   long long total_items = 0;
   int total_teams = 0, total_wg = 0;
   double makespan = 0.0, bound = 0.0;
@@ -545,23 +534,16 @@ int cbessfm_batch_create(cbessfm_batch_t** out, const cbessfm_instance* inst, in
       t.epoch_slot = (int)(ep_off + tm);
       t.xspec_off = (long long)xs_off;
       t.xp_off = (long long)xp_off;
-      t.xpar_off = (long long)xpar_off;
-      const size_t nsb = team_subbands(bt.log_np, t.width);
-      const bool split = cbessfm::pol_split_for(bt.log_np);
-      xs_off += 8 * nsb * np;
-      xp_off += 2 * nsb * np;
-      if (split) xpar_off += 4 * nsb * np;
-      unsigned rounds = 0, steps = 0;
+      xs_off += (size_t)2 * t.width * 4 * np;
+      xp_off += (size_t)2 * t.width * np;
+      unsigned rounds = 0;
       for (long long id : s.team_items[tm]) {
         const size_t j = std::upper_bound(first_item.begin(), first_item.end(), id) - first_item.begin() - 1;
         BatchItem it;
         it.inst = (int)j;
         it.sub = (int)(id - first_item[j]);
         it.round_off = rounds;
-        it.step_off = steps;
-        const unsigned st = (unsigned)bt.insts[j].steps;
-        rounds += split ? 2u * st + 2u : st + 2u;
-        steps += st;
+        rounds += (unsigned)bt.insts[j].steps + 2u;
         items.push_back(it);
       }
       t.rounds = rounds;
@@ -588,7 +570,6 @@ int cbessfm_batch_create(cbessfm_batch_t** out, const cbessfm_instance* inst, in
     L.args.epoch = b->d_epoch;
     L.args.xspec = b->d_xspec;
     L.args.xp = b->d_xp;
-    L.args.xpar = b->d_xpar;
     L.args.ctl.abort = b->d_abort;
     L.args.ctl.err = b->d_err;
     L.args.ctl.spin_limit = 1u << 22;

@@ -223,16 +223,15 @@ __device__ __forceinline__ void load_pass_tw(PassTwRegs<N, P>& w, const float2* 
   }
 }
 
-// One Stockham pass p of radix R over the owned sequences: both
-// polarisations (PAIR) or one.  For a pair the exchange buffer holds
-// (x.re, x.im, y.re, y.im) per position, so each value moves through LDS with
-// one 128-bit access; a single sequence uses (re, im) per position.
+// One Stockham pass p of radix R over both polarisations.  The exchange
+// buffer holds (x.re, x.im, y.re, y.im) per position, so each value moves
+// through LDS with one 128-bit access.
 //   FIRST: inputs come from the owned registers (positions t + NT o)
 //   LAST : outputs go to the owned registers
 // Otherwise inputs are read from / outputs written to LDS.
-template <int N, int P, bool INV, bool PAIR>
+template <int N, int P, bool INV>
 __device__ __forceinline__ void fft_pass(float2 (&x)[FftShape<N>::RR], float2 (&y)[FftShape<N>::RR],
-                                         void* __restrict__ lds, const PassTwRegs<N, P>& w, int t) {
+                                         float4* __restrict__ lxy, const PassTwRegs<N, P>& w, int t) {
   using S = FftShape<N>;
   constexpr int R = S::radix(P);
   constexpr int L = S::stride(P);
@@ -240,23 +239,19 @@ __device__ __forceinline__ void fft_pass(float2 (&x)[FftShape<N>::RR], float2 (&
   constexpr bool FIRST = (P == 0);
   constexpr bool LAST = (P == S::passes() - 1);
   constexpr int NR = N / R;
-  float4* lxy = static_cast<float4*>(lds);
-  float2* l1 = static_cast<float2*>(lds);
   // gather inputs: vx[a][m] = x[j + m N/R], j = t + NT a
-  float2 vx[NB][R], vy[NB][PAIR ? R : 1];
+  float2 vx[NB][R], vy[NB][R];
 #pragma unroll
   for (int a = 0; a < NB; ++a)
 #pragma unroll
     for (int m = 0; m < R; ++m) {
       if constexpr (FIRST) {
         vx[a][m] = x[a + m * NB];
-        if constexpr (PAIR) vy[a][m] = y[a + m * NB];
-      } else if constexpr (PAIR) {
+        vy[a][m] = y[a + m * NB];
+      } else {
         const float4 v = lxy[pad_c(t + S::NT * a + m * NR)];
         vx[a][m] = make_float2(v.x, v.y);
         vy[a][m] = make_float2(v.z, v.w);
-      } else {
-        vx[a][m] = l1[pad_c(t + S::NT * a + m * NR)];
       }
     }
   if constexpr (!FIRST && !LAST) __syncthreads();  // everyone has read before anyone writes
@@ -266,11 +261,11 @@ __device__ __forceinline__ void fft_pass(float2 (&x)[FftShape<N>::RR], float2 (&
 #pragma unroll
       for (int m = 1; m < R; ++m) {
         vx[a][m] = twmul<INV>(vx[a][m], w[a * (R - 1) + m - 1]);
-        if constexpr (PAIR) vy[a][m] = twmul<INV>(vy[a][m], w[a * (R - 1) + m - 1]);
+        vy[a][m] = twmul<INV>(vy[a][m], w[a * (R - 1) + m - 1]);
       }
     }
     dft<R, INV>(vx[a]);
-    if constexpr (PAIR) dft<R, INV>(vy[a]);
+    dft<R, INV>(vy[a]);
   }
 #pragma unroll
   for (int a = 0; a < NB; ++a) {
@@ -280,25 +275,24 @@ __device__ __forceinline__ void fft_pass(float2 (&x)[FftShape<N>::RR], float2 (&
     for (int m = 0; m < R; ++m) {
       if constexpr (LAST) {  // j < L here, so the output position is j + m L
         x[a + m * NB] = vx[a][m];
-        if constexpr (PAIR) y[a + m * NB] = vy[a][m];
-      } else if constexpr (PAIR) {
-        lxy[pad_c((j - k) * R + k + m * L)] = make_float4(vx[a][m].x, vx[a][m].y, vy[a][m].x, vy[a][m].y);
+        y[a + m * NB] = vy[a][m];
       } else {
-        l1[pad_c((j - k) * R + k + m * L)] = vx[a][m];
+        lxy[pad_c((j - k) * R + k + m * L)] = make_float4(vx[a][m].x, vx[a][m].y, vy[a][m].x, vy[a][m].y);
       }
     }
   }
   if constexpr (!LAST) __syncthreads();
 }
 
-template <int N, int P, bool INV, bool PAIR>
-__device__ __forceinline__ void fft_passes(float2 (&x)[FftShape<N>::RR], float2 (&y)[FftShape<N>::RR], void* lds,
-                                           const float2* twt, const PassTwRegs<N, P>& w, int t) {
+template <int N, int P, bool INV>
+__device__ __forceinline__ void fft_passes(float2 (&x)[FftShape<N>::RR], float2 (&y)[FftShape<N>::RR],
+                                           float4* lxy, const float2* twt, const PassTwRegs<N, P>& w,
+                                           int t) {
   if constexpr (P < FftShape<N>::passes()) {
     PassTwRegs<N, P + 1> w_next;
     load_pass_tw<N, P + 1>(w_next, twt, t);  // in flight during this pass
-    fft_pass<N, P, INV, PAIR>(x, y, lds, w, t);
-    fft_passes<N, P + 1, INV, PAIR>(x, y, lds, twt, w_next, t);
+    fft_pass<N, P, INV>(x, y, lxy, w, t);
+    fft_passes<N, P + 1, INV>(x, y, lxy, twt, w_next, t);
   }
 }
 
@@ -312,16 +306,7 @@ __device__ __forceinline__ void fft(float2 (&x)[FftShape<N>::RR], float2 (&y)[Ff
                                     const float2* twt, int t) {
   PassTwRegs<N, 0> w0;
   __syncthreads();
-  fft_passes<N, 0, INV, true>(x, y, lxy, twt, w0, t);
-}
-
-// The same for one owned sequence (exchange buffer of float2 entries).
-template <int N, bool INV>
-__device__ __forceinline__ void fft1(float2 (&x)[FftShape<N>::RR], float2* lx, const float2* twt, int t) {
-  PassTwRegs<N, 0> w0;
-  float2 unused[FftShape<N>::RR];
-  __syncthreads();
-  fft_passes<N, 0, INV, false>(x, unused, lx, twt, w0, t);
+  fft_passes<N, 0, INV>(x, y, lxy, twt, w0, t);
 }
 
 }  // namespace cbessfm

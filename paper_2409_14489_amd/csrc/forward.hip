@@ -131,147 +131,6 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void fwd_batch_kernel(Ba
   epoch_end(epoch, first, tm.rounds, c.me);
 }
 
-// ------------------------------------------------------------------ polarisation-split teams
-// For the largest N' a team gives each subband two workgroups, one per
-// polarisation, so a thread holds one polarisation's RR samples.  Once per
-// step the pair swaps |x|^2 and |y|^2 rows to form p = |x|^2 + |y|^2; the
-// x-workgroup publishes p for the coupled filter, which both compute.  The
-// team DFT of the block's input and output runs among the workgroups of one
-// polarisation.
-//
-// Exchange slots: the pair's |.|^2 rows and the filter rows alternate on the
-// team's running step count g, the block spectra have an input and an output
-// slot.  A member writes a slot again two steps later, after consuming
-// (directly or through its partner) rows that every reader of the slot wrote
-// after it had read the old contents, so two slots suffice.
-template <int N>
-constexpr int lds_floats_pol() {
-  return 2 * FftShape<N>::LDS_C > NlprLds<N>::FLOATS ? 2 * FftShape<N>::LDS_C : NlprLds<N>::FLOATS;
-}
-
-// One block; rounds round0 (input DFT), round0 + 1 + 2 s (pair swap of step
-// s), round0 + 2 + 2 s (filter rows), round0 + 2 steps + 1 (output DFT).
-// g0: the team's steps before this block.  xs_in / xs_out: [2 pols][n_sb][2][N'];
-// xpar_team: [2 slots][2 pols][n_sb][N']; xp_team: [2 slots][n_sb][N'].
-template <int N>
-__device__ __forceinline__ void fwd_pol_item(TeamCtx& c, int pol, const Inst& d, int sub, unsigned round0, unsigned g0,
-                                             uint64_t* xs_in, uint64_t* xs_out, uint64_t* xp_team,
-                                             uint64_t* xpar_team, float* lf) {
-  using S = FftShape<N>;
-  constexpr int RR = S::RR, NT = S::NT;
-  float2* l1 = reinterpret_cast<float2*>(lf);
-  const int nsb = c.nsb, me = c.me;
-  const float2* tw = d.tab.tw;
-  const int T = d.T;
-  const int tap_pad = kTapChunk * d.n_chunks;
-  const int inst = sub / d.nblk;
-  const int blk = sub - inst * d.nblk;
-  const size_t pol_words = (size_t)nsb * 2 * N;
-  int t = opaque_tid();
-  float2 x[RR];
-
-  gather_block1<N>(d.in + ((size_t)inst * 2 + pol) * T, blk, d.hop, d.n_ov, T, d.boundary, nsb, me, t, x);
-  fft1<N, false>(x, l1, tw, t);
-  polyphase_to_subband1<N>(c, xs_in + pol * pol_words, round0, t, x);
-
-  for (int s = 0; s < d.steps; ++s) {
-    t = opaque_tid();
-    apply_diag1<N, false>(x, (s == 0 ? d.tab.h_first : d.tab.h_mid) + (size_t)me * N, t);
-    fft1<N, true>(x, l1, tw, t);
-    const unsigned g = g0 + (unsigned)s;
-    const unsigned r_pair = round0 + 1u + 2u * (unsigned)s;
-    float a[RR], p[RR], theta[RR];
-#pragma unroll
-    for (int o = 0; o < RR; ++o) a[o] = x[o].x * x[o].x + x[o].y * x[o].y;
-    uint64_t* pair_w = xpar_team + ((size_t)((g & 1u) * 2u + (unsigned)pol) * nsb + me) * N;
-    const uint64_t* pair_r = xpar_team + ((size_t)((g & 1u) * 2u + (unsigned)(1 - pol)) * nsb + me) * N;
-#pragma unroll
-    for (int o = 0; o < RR; ++o) xput(pair_w + t + NT * o, a[o], r_pair);
-    {
-      float b[RR];
-      xget<RR>(pair_r, t, NT, r_pair, c.ctl, b);
-#pragma unroll
-      for (int o = 0; o < RR; ++o) p[o] = pol == 0 ? a[o] + b[o] : b[o] + a[o];  // |x|^2 + |y|^2 on both
-    }
-    uint64_t* xrow = xp_team + (size_t)(g & 1u) * nsb * N;
-    coupled_fir<N>(c, d.tab.cpad + ((size_t)(s * nsb + me) * nsb) * tap_pad, xrow, r_pair + 1u, p, theta, lf,
-                   pol == 0);
-    rotate1<N, -1>(x, theta);
-    fft1<N, false>(x, l1, tw, t);
-  }
-
-  t = opaque_tid();
-  apply_diag1<N, false>(x, d.tab.h_last + (size_t)me * N, t);
-  subband_to_polyphase1<N>(c, xs_out + pol * pol_words, round0 + 2u * (unsigned)d.steps + 1u, t, x);
-  fft1<N, true>(x, l1, tw, t);
-  scatter_block1<N>(d.out + ((size_t)inst * 2 + pol) * T, blk, d.hop, d.n_ov, T, nsb, me, t, x);
-}
-
-template <int LOGN>
-__global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void fwd_pol_kernel(FwdArgs a) {
-  constexpr int N = 1 << LOGN;
-  __shared__ __align__(16) float lf[lds_floats_pol<N>()];
-  __shared__ unsigned epoch_word;
-
-  TeamCtx c;
-  c.nsb = a.inst.n_sb;
-  const int width = 2 * c.nsb;
-  const int r = blockIdx.x / kXcds;
-  const int w = r % width;
-  c.me = w % c.nsb;
-  const int pol = w / c.nsb;
-  c.team = (r / width) * kXcds + blockIdx.x % kXcds;
-  if (c.team >= a.n_teams) return;
-  c.n_chunks = a.inst.n_chunks;
-  c.nc = a.inst.nc;
-  c.ctl = a.ctl;
-  c.tab = &a.inst.tab;
-  const int nsb = c.nsb;
-  const unsigned rounds_per_item = 2u * (unsigned)a.inst.steps + 2u;
-  uint64_t* xs_in = a.xspec + ((size_t)c.team * 2 + 0) * nsb * 4 * N;
-  uint64_t* xs_out = a.xspec + ((size_t)c.team * 2 + 1) * nsb * 4 * N;
-  uint64_t* xp_team = a.xp + (size_t)c.team * 2 * nsb * N;
-  uint64_t* xpar_team = a.xpar + (size_t)c.team * 4 * nsb * N;
-  const unsigned first = epoch_begin(a.epoch + c.team, &epoch_word);
-  unsigned iter = 0;
-  for (int item = c.team; item < a.n_items; item += a.n_teams, ++iter)
-    fwd_pol_item<N>(c, pol, a.inst, item, first + iter * rounds_per_item, iter * (unsigned)a.inst.steps, xs_in,
-                    xs_out, xp_team, xpar_team, lf);
-  epoch_end(a.epoch + c.team, first, iter * rounds_per_item, w);
-}
-
-template <int LOGN>
-__global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void fwd_pol_batch_kernel(BatchArgs a) {
-  constexpr int N = 1 << LOGN;
-  __shared__ __align__(16) float lf[lds_floats_pol<N>()];
-  __shared__ unsigned epoch_word;
-
-  const int2 wg = a.wg[blockIdx.x];
-  if (wg.x < 0) return;
-  const BatchTeam& tm = a.teams[wg.x];
-  TeamCtx c;
-  c.nsb = tm.width / 2;
-  c.me = wg.y % c.nsb;
-  const int pol = wg.y / c.nsb;
-  c.team = wg.x;
-  c.ctl = a.ctl;
-  uint64_t* xs_in = a.xspec + tm.xspec_off;
-  uint64_t* xs_out = xs_in + (size_t)c.nsb * 4 * N;
-  uint64_t* xp_team = a.xp + tm.xp_off;
-  uint64_t* xpar_team = a.xpar + tm.xpar_off;
-  unsigned* epoch = a.epoch + tm.epoch_slot;
-  const unsigned first = epoch_begin(epoch, &epoch_word);
-  for (int k = 0; k < tm.count; ++k) {
-    const BatchItem it = a.items[tm.first + k];
-    const Inst& d = a.insts[it.inst];
-    c.n_chunks = d.n_chunks;
-    c.nc = d.nc;
-    c.tab = &d.tab;
-    fwd_pol_item<N>(c, pol, d, it.sub, first + it.round_off, it.step_off, xs_in, xs_out, xp_team, xpar_team, lf);
-  }
-  epoch_end(epoch, first, tm.rounds, wg.y);
-}
-
 // ------------------------------------------------------------------ tables
 // FP32 rounding of (c, s) keeping the magnitude (see round_pair in plan.cpp).
 __device__ float2 round_pair_dev(double c, double s) {
@@ -349,18 +208,12 @@ static int launch_persistent(K kernel, const A& args, int grid, int threads, hip
 
 template <int LOGN>
 static int launch_fwd_t(const FwdArgs& args, int grid, hipStream_t s) {
-  if constexpr (pol_split_for(LOGN))
-    return launch_persistent(fwd_pol_kernel<LOGN>, args, grid, FftShape<(1 << LOGN)>::NT, s);
-  else
-    return launch_persistent(fwd_kernel<LOGN>, args, grid, FftShape<(1 << LOGN)>::NT, s);
+  return launch_persistent(fwd_kernel<LOGN>, args, grid, FftShape<(1 << LOGN)>::NT, s);
 }
 
 template <int LOGN>
 static int launch_batch_t(const BatchArgs& args, int grid, hipStream_t s) {
-  if constexpr (pol_split_for(LOGN))
-    return launch_persistent(fwd_pol_batch_kernel<LOGN>, args, grid, FftShape<(1 << LOGN)>::NT, s);
-  else
-    return launch_persistent(fwd_batch_kernel<LOGN>, args, grid, FftShape<(1 << LOGN)>::NT, s);
+  return launch_persistent(fwd_batch_kernel<LOGN>, args, grid, FftShape<(1 << LOGN)>::NT, s);
 }
 
 int launch_batch(int log_np, const BatchArgs& a, int grid, hipStream_t s) {
@@ -389,22 +242,18 @@ int threads_for(int log_np) {
 
 template <int LOGN>
 static int occ_t(int* blocks) {
-  hipError_t e;
-  if constexpr (pol_split_for(LOGN))
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fwd_pol_kernel<LOGN>, FftShape<(1 << LOGN)>::NT, 0);
-  else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fwd_kernel<LOGN>, FftShape<(1 << LOGN)>::NT, 0);
-  return e == hipSuccess ? CBESSFM_OK : CBESSFM_EHIP;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fwd_kernel<LOGN>, FftShape<(1 << LOGN)>::NT, 0) ==
+                 hipSuccess
+             ? CBESSFM_OK
+             : CBESSFM_EHIP;
 }
 
 template <int LOGN>
 static int bocc_t(int* blocks) {
-  hipError_t e;
-  if constexpr (pol_split_for(LOGN))
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fwd_pol_batch_kernel<LOGN>, FftShape<(1 << LOGN)>::NT, 0);
-  else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fwd_batch_kernel<LOGN>, FftShape<(1 << LOGN)>::NT, 0);
-  return e == hipSuccess ? CBESSFM_OK : CBESSFM_EHIP;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fwd_batch_kernel<LOGN>, FftShape<(1 << LOGN)>::NT,
+                                                      0) == hipSuccess
+             ? CBESSFM_OK
+             : CBESSFM_EHIP;
 }
 
 int batch_occupancy_per_cu(int log_np, int* blocks) {
@@ -465,12 +314,11 @@ int launch_forward(cbessfm_plan_t* p, const void* in, void* out, long long T, in
   a.epoch = p->d_epoch;
   a.xspec = p->d_xspec;
   a.xp = p->d_xp;
-  a.xpar = p->d_xpar;
   a.ctl.abort = p->d_abort;
   a.ctl.err = p->d_err;
   a.ctl.spin_limit = 1u << 22;
   const int groups = (a.n_teams + kXcds - 1) / kXcds;
-  const int grid = groups * kXcds * a.inst.n_sb * (p->pol_split ? 2 : 1);
+  const int grid = groups * kXcds * a.inst.n_sb;
   switch (p->log_np) {
     case 8: return launch_fwd_t<8>(a, grid, s);
     case 9: return launch_fwd_t<9>(a, grid, s);

@@ -49,7 +49,6 @@ struct FwdArgs {
   unsigned* epoch;    // [teams] exchange rounds completed so far by each team (device)
   uint64_t* xspec;    // [team_capacity][2 slots][n_sb][4 comps][N']  tagged spectra
   uint64_t* xp;       // [team_capacity][2 slots][n_sb][N']           tagged intensities
-  uint64_t* xpar;     // polarisation-split teams: [team_capacity][2 slots][2 pols][n_sb][N'] |.|^2 rows
   XchgCtl ctl;
 };
 
@@ -58,7 +57,6 @@ struct BatchItem {
   int inst;            // index into the instance table
   int sub;             // batch entry * nblk + block
   unsigned round_off;  // exchange rounds of the team's earlier items in this launch
-  unsigned step_off;   // steps of the team's earlier items in this launch
 };
 struct BatchTeam {
   int width;           // n_sb of every instance the team runs
@@ -67,7 +65,6 @@ struct BatchTeam {
   int epoch_slot;      // index into the epoch array
   long long xspec_off; // word offsets of its exchange buffers
   long long xp_off;
-  long long xpar_off;  // polarisation-split launches only
 };
 struct BatchArgs {
   const Inst* insts;
@@ -77,7 +74,6 @@ struct BatchArgs {
   unsigned* epoch;
   uint64_t* xspec;
   uint64_t* xp;
-  uint64_t* xpar;
   XchgCtl ctl;
 };
 
@@ -123,7 +119,6 @@ struct cbessfm_plan {
   int device;
   int cu_count;
   int threads;
-  bool pol_split;         // forward teams of 2 n_sb workgroups, one per subband and polarisation
   int team_capacity;      // forward teams whose workgroups can all be resident at once
   int bwd_team_capacity;  // the same for the adjoint kernel
   int xchg_teams;         // teams the exchange buffers are sized for
@@ -139,7 +134,6 @@ struct cbessfm_plan {
   uint64_t* d_xspec;  // tagged exchange words
   uint64_t* d_xp;
   uint64_t* d_xq;
-  uint64_t* d_xpar;   // [team_capacity][2][2][n_sb][N'] (polarisation-split teams)
   unsigned* d_epoch;  // [xchg_teams] exchange rounds completed per team
   unsigned* d_abort;  // sticky exchange-timeout word
   int* d_err;
@@ -163,7 +157,5 @@ int threads_for(int log_np);
 bool stream_capturing(hipStream_t s);
 int batch_occupancy_per_cu(int log_np, int* blocks);
 int launch_batch(int log_np, const BatchArgs& a, int grid, hipStream_t s);
-// forward teams with one workgroup per subband and polarisation (the largest N')
-constexpr bool pol_split_for(int log_np) { return log_np >= 13; }
 void fill_inst(const cbessfm_plan_t* p, const void* in, void* out, long long T, int batch, Inst& d);
 }  // namespace cbessfm

@@ -119,9 +119,6 @@ size_t xspec_bytes(const cbessfm_plan_t* p) {
 size_t xp_bytes(const cbessfm_plan_t* p) {
   return sizeof(uint64_t) * (size_t)p->xchg_teams * 2 * p->sb.n_sb * p->Np;
 }
-size_t xpar_bytes(const cbessfm_plan_t* p) {
-  return p->pol_split ? sizeof(uint64_t) * (size_t)p->team_capacity * 4 * p->sb.n_sb * p->Np : 0;
-}
 
 }  // namespace
 
@@ -213,7 +210,7 @@ void cbessfm_destroy(cbessfm_plan_t* p) {
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(p->device);
   void* bufs[] = {p->d_phase, p->d_h,  p->d_tw,    p->d_poly,  p->d_c,     p->d_cpad, p->d_ctpad,
-                  p->d_rho,   p->d_xspec, p->d_xp, p->d_xq, p->d_xpar, p->d_epoch, p->d_abort, p->d_err};
+                  p->d_rho,   p->d_xspec, p->d_xp, p->d_xq, p->d_epoch, p->d_abort, p->d_err};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   (void)hipSetDevice(prev);
@@ -264,9 +261,7 @@ int cbessfm_plan(cbessfm_plan_t** out, const cbessfm_link* link, const cbessfm_s
     delete p;
     return CBESSFM_EHIP;
   }
-  p->pol_split = cbessfm::pol_split_for(p->log_np);
-  const int fwd_width = sb->n_sb * (p->pol_split ? 2 : 1);
-  p->team_capacity = (per_cu * p->cu_count / (cbessfm::kXcds * fwd_width)) * cbessfm::kXcds;
+  p->team_capacity = (per_cu * p->cu_count / (cbessfm::kXcds * sb->n_sb)) * cbessfm::kXcds;
   p->bwd_team_capacity = (bwd_per_cu * p->cu_count / (cbessfm::kXcds * sb->n_sb)) * cbessfm::kXcds;
   if (p->team_capacity < 1 || p->bwd_team_capacity < 1) {
     delete p;
@@ -326,7 +321,6 @@ int cbessfm_plan(cbessfm_plan_t** out, const cbessfm_link* link, const cbessfm_s
   alloc((void**)&p->d_xspec, xspec_bytes(p));
   alloc((void**)&p->d_xp, xp_bytes(p));
   alloc((void**)&p->d_xq, xp_bytes(p));
-  if (p->pol_split) alloc((void**)&p->d_xpar, xpar_bytes(p));
   alloc((void**)&p->d_epoch, sizeof(unsigned) * p->xchg_teams);
   alloc((void**)&p->d_abort, sizeof(unsigned));
   alloc((void**)&p->d_err, sizeof(int));
@@ -344,7 +338,6 @@ int cbessfm_plan(cbessfm_plan_t** out, const cbessfm_link* link, const cbessfm_s
                 hipMemset(p->d_xspec, 0, xspec_bytes(p)) == hipSuccess &&
                 hipMemset(p->d_xp, 0, xp_bytes(p)) == hipSuccess &&
                 hipMemset(p->d_xq, 0, xp_bytes(p)) == hipSuccess &&
-                (!p->pol_split || hipMemset(p->d_xpar, 0, xpar_bytes(p)) == hipSuccess) &&
                 hipMemset(p->d_epoch, 0, sizeof(unsigned) * p->xchg_teams) == hipSuccess;
   if (!hip_ok || cbessfm::launch_tables(p, nullptr) || cbessfm::launch_pad_coeffs(p, p->d_c, nullptr) ||
       hipDeviceSynchronize() != hipSuccess) {
@@ -425,7 +418,6 @@ int cbessfm_status(cbessfm_plan_t* p) {
         hipMemset(p->d_abort, 0, sizeof(unsigned)) != hipSuccess ||
         hipMemset(p->d_xspec, 0, xspec_bytes(p)) != hipSuccess || hipMemset(p->d_xp, 0, xp_bytes(p)) != hipSuccess ||
         hipMemset(p->d_xq, 0, xp_bytes(p)) != hipSuccess ||
-        (p->pol_split && hipMemset(p->d_xpar, 0, xpar_bytes(p)) != hipSuccess) ||
         hipMemset(p->d_epoch, 0, sizeof(unsigned) * p->xchg_teams) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess)
       return CBESSFM_EHIP;

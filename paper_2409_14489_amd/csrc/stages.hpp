@@ -190,14 +190,12 @@ __device__ __forceinline__ void subband_to_polyphase(const TeamCtx& c, uint64_t*
 // Coupled intensity filter of eq. (15) for member `me`, circular over N':
 //   out[k] = sum_l sum_tau crow[l][tau] in_l[(k - tau + nc) mod N'],
 // crow = the member's coefficient rows ([n_sb][8 n_chunks], zero padded).
-// own: this member's row at positions t + NT o, published to the tagged
-// exchange `xrow` ([n_sb][N'], round `tag`) unless `publish` is false (a
-// workgroup whose partner publishes the same row); the other rows come from
-// the exchange.  Result at t + NT o.
+// own: this member's row at positions t + NT o; the other rows come from the
+// tagged exchange `xrow` ([n_sb][N'], round `tag`).  Result at t + NT o.
 template <int N>
 __device__ __forceinline__ void coupled_fir(const TeamCtx& c, const float* __restrict__ crow, uint64_t* xrow,
                                            unsigned tag, const float (&own)[FftShape<N>::RR],
-                                           float (&out)[FftShape<N>::RR], float* lf, bool publish = true) {
+                                           float (&out)[FftShape<N>::RR], float* lf) {
   constexpr int RR = FftShape<N>::RR, NT = FftShape<N>::NT;
   constexpr int PB = NlprLds<N>::PB;  // row l lives at lf + (l & 1) * PB
   const int t = opaque_tid();
@@ -206,7 +204,7 @@ __device__ __forceinline__ void coupled_fir(const TeamCtx& c, const float* __res
   const int hl = tap_pad - 1 - nc;  // left halo of the circular extension
   float* th = lf + 2 * PB;
 
-  if (nsb > 1 && publish) {
+  if (nsb > 1) {
 #pragma unroll
     for (int o = 0; o < RR; ++o) xput(xrow + (size_t)me * N + t + NT * o, own[o], tag);
   }
@@ -227,51 +225,66 @@ __device__ __forceinline__ void coupled_fir(const TeamCtx& c, const float* __res
 
   // The row of member l, circularly extended, is W[i] = cur[t RR + i] for this
   // thread's outputs k = t RR + q:  out[q] += sum_tau c[tau] W[q - tau + tap_pad - 1].
-  // Taps go in chunks of 8 from the last chunk down; chunk ch reads
-  // W[tap_pad - 8 ch - 8 + i], i < RR + 8, so each next chunk's window is the
-  // previous one moved by 8 (RR floats are kept, 8 are read).
+  // Outputs go in groups of QB <= 8; for each group the next row's matching
+  // part is in flight while the group is filtered.  Taps go in chunks of 8
+  // from the last chunk down; chunk ch reads W[g QB + tap_pad - 8 ch - 8 + i],
+  // i < QB + 8, so each next chunk's window is the previous one moved by 8 (QB
+  // floats are kept, 8 are read).
+  constexpr int QB = RR < 8 ? RR : 8;
+  constexpr int G = RR / QB;
   float acc[RR];
 #pragma unroll
   for (int q = 0; q < RR; ++q) acc[q] = 0.0f;
   for (int l = 0; l < nsb; ++l) {
     const float* cur = lf + (l & 1) * PB;
-    const bool fetch = (l + 1 < nsb) && (l + 1 != me);  // next row is remote
-    uint64_t w[RR];
-    if (fetch) xissue<RR>(xrow + (size_t)(l + 1) * N, t, NT, w);  // in flight during the filter
+    float* nxt = lf + ((l + 1) & 1) * PB;
+    const bool more = l + 1 < nsb;
+    const bool fetch = more && (l + 1 != me);  // next row is remote
+    const uint64_t* nrow = xrow + (size_t)(l + 1) * N;
     const float* cl = crow + (size_t)l * tap_pad;
-    float win[RR + kTapChunk];
-    int start = t * RR;  // = t RR + tap_pad - 8 n_chunks
-    load_row4<RR + kTapChunk, 0>(cur, start, win);
-    // the chunk's 8 coefficients (uniform: scalar loads), fetched one chunk ahead
-    float cf[kTapChunk];
 #pragma unroll
-    for (int tt = 0; tt < kTapChunk; ++tt) cf[tt] = cl[kTapChunk * (c.n_chunks - 1) + tt];
-    for (int ch = c.n_chunks - 1; ch >= 0; --ch) {
-      float cf_next[kTapChunk];
-      const int ch_next = ch > 0 ? ch - 1 : 0;
+    for (int g = 0; g < G; ++g) {
+      uint64_t w[QB];
+      if (fetch) xissue<QB>(nrow + NT * QB * g, t, NT, w);  // in flight during the filter
+      float win[QB + kTapChunk];
+      int start = t * RR + g * QB;  // = t RR + g QB + tap_pad - 8 n_chunks
+      load_row4<QB + kTapChunk, 0>(cur, start, win);
+      // the chunk's 8 coefficients (uniform: scalar loads), fetched one chunk ahead
+      float cf[kTapChunk];
 #pragma unroll
-      for (int tt = 0; tt < kTapChunk; ++tt) cf_next[tt] = cl[kTapChunk * ch_next + tt];
+      for (int tt = 0; tt < kTapChunk; ++tt) cf[tt] = cl[kTapChunk * (c.n_chunks - 1) + tt];
+      for (int ch = c.n_chunks - 1; ch >= 0; --ch) {
+        float cf_next[kTapChunk];
+        const int ch_next = ch > 0 ? ch - 1 : 0;
 #pragma unroll
-      for (int tt = 0; tt < kTapChunk; ++tt) {
+        for (int tt = 0; tt < kTapChunk; ++tt) cf_next[tt] = cl[kTapChunk * ch_next + tt];
 #pragma unroll
-        for (int q = 0; q < RR; ++q) acc[q] = fmaf(cf[tt], win[q - tt + kTapChunk - 1], acc[q]);
+        for (int tt = 0; tt < kTapChunk; ++tt) {
+#pragma unroll
+          for (int q = 0; q < QB; ++q) acc[g * QB + q] = fmaf(cf[tt], win[q - tt + kTapChunk - 1], acc[g * QB + q]);
+        }
+        if (ch > 0) {
+#pragma unroll
+          for (int i = 0; i < QB; ++i) win[i] = win[i + kTapChunk];
+          start += kTapChunk;
+          load_row4<kTapChunk, QB>(cur, start + QB, win);
+        }
+#pragma unroll
+        for (int tt = 0; tt < kTapChunk; ++tt) cf[tt] = cf_next[tt];
       }
-      if (ch > 0) {
+      if (more) {  // this part of the next row into the other buffer (last read before the previous barrier)
+        if (fetch) {
+          float v[QB];
+          xcomplete<QB>(nrow + NT * QB * g, t, NT, tag, c.ctl, w, v);
+          stage_row<N, QB, NT>(nxt, v, t + NT * QB * g, hl, nc);
+        } else if constexpr (G == 1) {
+          stage_row<N, RR, NT>(nxt, own, t, hl, nc);
+        } else {
+          float v[QB];
 #pragma unroll
-        for (int i = 0; i < RR; ++i) win[i] = win[i + kTapChunk];
-        start += kTapChunk;
-        load_row4<kTapChunk, RR>(cur, start + RR, win);
-      }
-#pragma unroll
-      for (int tt = 0; tt < kTapChunk; ++tt) cf[tt] = cf_next[tt];
-    }
-    if (l + 1 < nsb) {
-      if (fetch) {
-        float v[RR];
-        xcomplete<RR>(xrow + (size_t)(l + 1) * N, t, NT, tag, c.ctl, w, v);
-        stage_row<N, RR, NT>(lf + ((l + 1) & 1) * PB, v, t, hl, nc);
-      } else {
-        stage_row<N, RR, NT>(lf + ((l + 1) & 1) * PB, own, t, hl, nc);
+          for (int o = 0; o < QB; ++o) v[o] = own[g * QB + o];
+          stage_row<N, QB, NT>(nxt, v, t + NT * QB * g, hl, nc);
+        }
       }
     }
     __syncthreads();
@@ -306,110 +319,6 @@ __device__ __forceinline__ void intensity(const float2 (&x)[FftShape<N>::RR], co
 #pragma unroll
   for (int o = 0; o < FftShape<N>::RR; ++o)
     p[o] = x[o].x * x[o].x + x[o].y * x[o].y + y[o].x * y[o].x + y[o].y * y[o].y;
-}
-
-// ---------------------------------------------------------------- one polarisation
-// Variants for teams that give each subband two workgroups, one per
-// polarisation (register state of one polarisation per thread).  The member
-// owns polarisation `pol` of subband c.me; the team DFT runs among the members
-// of the same polarisation.
-
-template <int N, bool CONJ>
-__device__ __forceinline__ void apply_diag1(float2 (&x)[FftShape<N>::RR], const float2* __restrict__ h, int t) {
-  constexpr int RR = FftShape<N>::RR, NT = FftShape<N>::NT;
-#pragma unroll
-  for (int o = 0; o < RR; ++o) {
-    const float2 hv = h[t + NT * o];
-    x[o] = CONJ ? cmulc(x[o], hv) : cmul(x[o], hv);
-  }
-}
-
-template <int N>
-__device__ __forceinline__ void gather_block1(const float2* __restrict__ src, int blk, int hop, int n_ov, int T,
-                                              int boundary, int nsb, int me, int t, float2 (&x)[FftShape<N>::RR]) {
-  constexpr int RR = FftShape<N>::RR, NT = FftShape<N>::NT;
-  const int first = frame_first(blk, hop, n_ov, T, boundary);
-  const bool short_seq = T < nsb * N;
-#pragma unroll
-  for (int o = 0; o < RR; ++o) {
-    const int n = nsb * (t + NT * o) + me;
-    const int pos = frame_pos(first, n, T, boundary, short_seq);
-    const float2 v = pos >= 0 ? src[pos] : make_float2(0.f, 0.f);
-    x[o] = cscale(v, (n & 1) ? -1.0f : 1.0f);
-  }
-}
-
-template <int N>
-__device__ __forceinline__ void scatter_block1(float2* __restrict__ dst, int blk, int hop, int n_ov, int T, int nsb,
-                                               int me, int t, const float2 (&x)[FftShape<N>::RR]) {
-  constexpr int RR = FftShape<N>::RR, NT = FftShape<N>::NT;
-  const int keep_lo = n_ov / 2, keep_hi = nsb * N - n_ov / 2;
-#pragma unroll
-  for (int o = 0; o < RR; ++o) {
-    const int n = nsb * (t + NT * o) + me;
-    const int pos = blk * hop + n - keep_lo;
-    if (n >= keep_lo && n < keep_hi && pos < T) dst[pos] = cscale(x[o], (n & 1) ? -1.0f : 1.0f);
-  }
-}
-
-// Team DFT of one polarisation: src = [n_sb][2 comps][N'] spectra of the
-// members of this polarisation; x holds (and keeps using) the own spectrum.
-template <int N, bool CONJ>
-__device__ __forceinline__ void combine_spectra1(uint64_t* src, const TeamCtx& c, unsigned tag, int t,
-                                                 float2 (&x)[FftShape<N>::RR]) {
-  constexpr int RR = FftShape<N>::RR, NT = FftShape<N>::NT;
-#pragma unroll
-  for (int o = 0; o < RR; ++o) {
-    xput(src + (size_t)c.me * 2 * N + t + NT * o, x[o].x, tag);
-    xput(src + (size_t)c.me * 2 * N + N + t + NT * o, x[o].y, tag);
-  }
-  {
-    const float2 w = c.tab->wsb[(c.me * c.me) % c.nsb];
-#pragma unroll
-    for (int o = 0; o < RR; ++o) x[o] = CONJ ? cmulc(x[o], w) : cmul(x[o], w);
-  }
-  for (int n2 = 0; n2 < c.nsb; ++n2) {
-    if (n2 == c.me) continue;
-    const float2 w = c.tab->wsb[(n2 * c.me) % c.nsb];
-    const uint64_t* row = src + (size_t)n2 * 2 * N;
-    uint64_t wr[RR], wi[RR];
-    xissue<RR>(row, t, NT, wr);
-    xissue<RR>(row + N, t, NT, wi);
-    float re[RR], im[RR];
-    xcomplete<RR>(row, t, NT, tag, c.ctl, wr, re);
-    xcomplete<RR>(row + N, t, NT, tag, c.ctl, wi, im);
-#pragma unroll
-    for (int o = 0; o < RR; ++o) {
-      const float2 v = make_float2(re[o], im[o]);
-      x[o] = cadd(x[o], CONJ ? cmulc(v, w) : cmul(v, w));
-    }
-  }
-}
-
-template <int N>
-__device__ __forceinline__ void polyphase_to_subband1(const TeamCtx& c, uint64_t* xs, unsigned tag, int t,
-                                                      float2 (&x)[FftShape<N>::RR]) {
-  if (c.nsb == 1) return;
-  apply_diag1<N, false>(x, c.tab->poly_tw + (size_t)c.me * N, t);
-  combine_spectra1<N, false>(xs, c, tag, t, x);
-}
-
-template <int N>
-__device__ __forceinline__ void subband_to_polyphase1(const TeamCtx& c, uint64_t* xs, unsigned tag, int t,
-                                                      float2 (&x)[FftShape<N>::RR]) {
-  if (c.nsb == 1) return;
-  combine_spectra1<N, true>(xs, c, tag, t, x);
-  apply_diag1<N, true>(x, c.tab->poly_tw + (size_t)c.me * N, t);
-}
-
-template <int N, int SIGN>
-__device__ __forceinline__ void rotate1(float2 (&x)[FftShape<N>::RR], const float (&theta)[FftShape<N>::RR]) {
-#pragma unroll
-  for (int o = 0; o < FftShape<N>::RR; ++o) {
-    float sn, cs;
-    phase_sincos(theta[o], sn, cs);
-    x[o] = cmul(x[o], make_float2(cs, SIGN < 0 ? -sn : sn));
-  }
 }
 
 }  // namespace cbessfm

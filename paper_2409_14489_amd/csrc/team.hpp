@@ -159,17 +159,27 @@ constexpr int lds_floats() {
   return 4 * FftShape<N>::LDS_C > NlprLds<N>::FLOATS ? 4 * FftShape<N>::LDS_C : NlprLds<N>::FLOATS;
 }
 
-// Writes values held at positions t + NT o (o < RR) into a circularly extended
-// LDS row: row[pad_r(k + hl)] = v[k], plus the wrapped copies for the left
-// halo (hl samples) and the right halo (hr samples).
+// Writes values held at positions t + NT o (o < RR; t may include an offset
+// of whole NT RR' groups) into a circularly extended LDS row:
+// row[pad_r(k + hl)] = v[k], plus the wrapped copies for the left halo (hl
+// samples) and the right halo (hr samples).
 template <int N, int RR, int NT>
 __device__ __forceinline__ void stage_row(float* row, const float (&v)[RR], int t, int hl, int hr) {
 #pragma unroll
-  for (int o = 0; o < RR; ++o) {
-    const int k = t + NT * o;
-    row[pad_r(k + hl)] = v[o];
-    if (k >= N - hl) row[pad_r(k - N + hl)] = v[o];
-    if (k < hr) row[pad_r(k + N + hl)] = v[o];
+  for (int o = 0; o < RR; ++o) row[pad_r(t + NT * o + hl)] = v[o];
+  if constexpr (NT >= 256) {
+    // halos are shorter than NT (both at most 255), so only the last value
+    // can fall in the left one and only the first in the right one
+    const int k_last = t + NT * (RR - 1);
+    if (k_last >= N - hl) row[pad_r(k_last - N + hl)] = v[RR - 1];
+    if (t < hr) row[pad_r(t + N + hl)] = v[0];
+  } else {
+#pragma unroll
+    for (int o = 0; o < RR; ++o) {
+      const int k = t + NT * o;
+      if (k >= N - hl) row[pad_r(k - N + hl)] = v[o];
+      if (k < hr) row[pad_r(k + N + hl)] = v[o];
+    }
   }
 }
 

@@ -40,6 +40,7 @@ SHAPES = [
     (1, 512, 64, 2, 0.5, 3, 4000, 3, "zero", 1),
     (2, 8192, 2048, 3, 0.3, 9, 70000, 1, "circular", 3),   # third class: one workgroup per polarisation
     (1, 8192, 1024, 2, 0.5, 5, 20000, 2, "zero", 2),
+    (5, 8192, 10240, 2, 0.3, 21, 70000, 1, "circular", 4),  # a team of 10 workgroups
 ]
 
 
