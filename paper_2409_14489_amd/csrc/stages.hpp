@@ -132,30 +132,36 @@ __device__ __forceinline__ void combine_spectra(const uint64_t* src, const TeamC
     if (n2 == c.me) continue;
     const float2 w = c.tab->wsb[(n2 * c.me) % c.nsb];
     const uint64_t* row = src + (size_t)n2 * 4 * N;
-    // all four components of the member in flight at once (two at a time
-    // when the register file cannot hold them)
+    // all four components of the member in flight at once when they fit the
+    // register file, else one at a time
     constexpr bool ALL4 = RR <= 8;
-    uint64_t wxr[RR], wxi[RR], wyr[RR], wyi[RR];
-    xissue<RR>(row, t, NT, wxr);
-    xissue<RR>(row + N, t, NT, wxi);
-    if constexpr (ALL4) {
-      xissue<RR>(row + 2 * N, t, NT, wyr);
-      xissue<RR>(row + 3 * N, t, NT, wyi);
-    }
     float re[RR], im[RR];
-    xcomplete<RR>(row, t, NT, tag, c.ctl, wxr, re);
-    xcomplete<RR>(row + N, t, NT, tag, c.ctl, wxi, im);
-#pragma unroll
-    for (int o = 0; o < RR; ++o) {
-      const float2 v = make_float2(re[o], im[o]);
-      x[o] = cadd(x[o], CONJ ? cmulc(v, w) : cmul(v, w));
-    }
-    if constexpr (!ALL4) {
+    if constexpr (ALL4) {
+      uint64_t wxr[RR], wxi[RR], wyr[RR], wyi[RR];
+      xissue<RR>(row, t, NT, wxr);
+      xissue<RR>(row + N, t, NT, wxi);
       xissue<RR>(row + 2 * N, t, NT, wyr);
       xissue<RR>(row + 3 * N, t, NT, wyi);
+      xcomplete<RR>(row, t, NT, tag, c.ctl, wxr, re);
+      xcomplete<RR>(row + N, t, NT, tag, c.ctl, wxi, im);
+#pragma unroll
+      for (int o = 0; o < RR; ++o) {
+        const float2 v = make_float2(re[o], im[o]);
+        x[o] = cadd(x[o], CONJ ? cmulc(v, w) : cmul(v, w));
+      }
+      xcomplete<RR>(row + 2 * N, t, NT, tag, c.ctl, wyr, re);
+      xcomplete<RR>(row + 3 * N, t, NT, tag, c.ctl, wyi, im);
+    } else {
+      xget<RR>(row, t, NT, tag, c.ctl, re);
+      xget<RR>(row + N, t, NT, tag, c.ctl, im);
+#pragma unroll
+      for (int o = 0; o < RR; ++o) {
+        const float2 v = make_float2(re[o], im[o]);
+        x[o] = cadd(x[o], CONJ ? cmulc(v, w) : cmul(v, w));
+      }
+      xget<RR>(row + 2 * N, t, NT, tag, c.ctl, re);
+      xget<RR>(row + 3 * N, t, NT, tag, c.ctl, im);
     }
-    xcomplete<RR>(row + 2 * N, t, NT, tag, c.ctl, wyr, re);
-    xcomplete<RR>(row + 3 * N, t, NT, tag, c.ctl, wyi, im);
 #pragma unroll
     for (int o = 0; o < RR; ++o) {
       const float2 v = make_float2(re[o], im[o]);
