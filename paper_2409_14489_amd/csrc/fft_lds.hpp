@@ -162,9 +162,12 @@ __device__ __forceinline__ void dft(float2 (&v)[R]) {
 }
 
 // ------------------------------------------------------------- plan (constexpr)
-// LDS index padding that breaks the power-of-two strides of the exchanges.
-__device__ __forceinline__ int pad_c(int i) { return i + (i >> 4) + (i >> 8); }
-__host__ __device__ constexpr int pad_c_size(int n) { return n + (n >> 4) + (n >> 8) + 1; }
+// LDS index padding of the FFT exchange buffer (entries of 16 bytes): one
+// entry after every 8 keeps the 8 lanes served together by the LDS on
+// distinct banks for every pass's pattern -- consecutive positions, and the
+// stride-R writes of the first pass.
+__device__ __forceinline__ int pad_c(int i) { return i + (i >> 3); }
+__host__ __device__ constexpr int pad_c_size(int n) { return n + (n >> 3) + 1; }
 __device__ __forceinline__ int pad_f(int i) { return i + (i >> 4); }
 __host__ __device__ constexpr int pad_f_size(int n) { return n + (n >> 4) + 1; }
 
