@@ -131,7 +131,7 @@ int cbessfm_run(cbessfm_plan_t* plan, const void* field_in, void* field_out,
                 int64_t T, int32_t batch, void* stream);
 
 /* Bytes of device workspace cbessfm_backward needs for (T, batch,
- * checkpoint_every); checkpoint_every <= 0 means "store every step". */
+ * checkpoint_every); see cbessfm_backward for checkpoint_every. */
 int cbessfm_backward_workspace(const cbessfm_plan_t* plan, int64_t T, int32_t batch,
                                int32_t checkpoint_every, size_t* bytes);
 
@@ -141,9 +141,12 @@ int cbessfm_backward_workspace(const cbessfm_plan_t* plan, int64_t T, int32_t ba
  *   grad_in   device complex float32 [batch][2][T] or NULL (not computed)
  *   grad_c    device float [steps][n_sb][n_sb][n_taps], overwritten
  *   grad_rho  device float, overwritten
- * The forward trajectory is recomputed from states stored every
- * checkpoint_every steps (<= 0: every step).  workspace: device, at least
- * cbessfm_backward_workspace() bytes.  Asynchronous on stream. */
+ * checkpoint_every <= 1 (or >= steps): the forward sweep stores every step's
+ * intermediate field and phase and nothing is recomputed.  1 < k < steps:
+ * only the spectrum at the start of every k-th step is stored, and each
+ * segment of k steps is recomputed once during the reverse sweep (less
+ * workspace, about one more forward pass of work).  workspace: device, at
+ * least cbessfm_backward_workspace() bytes.  Asynchronous on stream. */
 int cbessfm_backward(cbessfm_plan_t* plan, const void* field_in, const void* grad_out,
                      void* grad_in, float* grad_c, float* grad_rho, int64_t T, int32_t batch,
                      int32_t checkpoint_every, void* workspace, size_t workspace_bytes,

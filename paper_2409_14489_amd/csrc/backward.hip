@@ -19,8 +19,12 @@
 // spectrum after the last GVD.  The block's output stage (MUX, inverse size-N
 // DFT) is adjoint to its input stage and vice versa, so both are reused.
 //
-// The forward trajectory of a block is recomputed from spectra stored every
-// `ck_every` steps (segment by segment, Griewank-style with one level).
+// The reverse step needs v and theta of its forward step.  The forward sweep
+// stores the spectrum S_s at the start of every segment of `ck_every` steps,
+// and (v, theta) of every step of the last segment; the reverse sweep
+// recomputes each earlier segment once from its spectrum, storing (v, theta)
+// per step, and then runs that segment's reverse steps on them (one level of
+// Griewank-style checkpointing; with a single segment nothing is recomputed).
 // Coefficient and split-ratio partials are written per block and reduced over
 // blocks in FP64 by a second kernel, in a fixed order.
 #include <hip/hip_runtime.h>
@@ -51,6 +55,34 @@ __device__ __forceinline__ void load_state(const float2* st, float2 (&x)[FftShap
   for (int o = 0; o < RR; ++o) {
     x[o] = st[t + NT * o];
     y[o] = st[N + t + NT * o];
+  }
+}
+
+// (v, theta) of one step: v_x, v_y (N' complex each) then theta (N' floats).
+template <int N>
+__device__ __forceinline__ void store_vtheta(float* st, const float2 (&x)[FftShape<N>::RR],
+                                             const float2 (&y)[FftShape<N>::RR], const float (&th)[FftShape<N>::RR],
+                                             int t) {
+  constexpr int RR = FftShape<N>::RR, NT = FftShape<N>::NT;
+  float2* v = reinterpret_cast<float2*>(st);
+#pragma unroll
+  for (int o = 0; o < RR; ++o) {
+    v[t + NT * o] = x[o];
+    v[N + t + NT * o] = y[o];
+    st[4 * N + t + NT * o] = th[o];
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void load_vtheta(const float* st, float2 (&x)[FftShape<N>::RR],
+                                            float2 (&y)[FftShape<N>::RR], float (&th)[FftShape<N>::RR], int t) {
+  constexpr int RR = FftShape<N>::RR, NT = FftShape<N>::NT;
+  const float2* v = reinterpret_cast<const float2*>(st);
+#pragma unroll
+  for (int o = 0; o < RR; ++o) {
+    x[o] = v[t + NT * o];
+    y[o] = v[N + t + NT * o];
+    th[o] = st[4 * N + t + NT * o];
   }
 }
 
@@ -201,9 +233,13 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdAr
   const int T = a.T;
   const int tap_pad = kTapChunk * a.n_chunks;
   const int k = a.ck_every;
-  const size_t state_sz = (size_t)2 * N;  // one member's two polarisations
-  float2* team_states = a.states + (size_t)c.team * (a.n_ck + k) * nsb * state_sz;
-  auto st = [&](int slot) { return team_states + ((size_t)slot * nsb + me) * state_sz; };
+  const size_t spec_sz = (size_t)2 * N;  // one member's spectra, two polarisations (float2)
+  const size_t vt_sz = (size_t)5 * N;    // one member's (v, theta), floats
+  float2* team_spec = a.spec + (size_t)c.team * a.n_ck * nsb * spec_sz;
+  float* team_vt = a.vtheta + (size_t)c.team * k * nsb * vt_sz;
+  auto sp = [&](int slot) { return team_spec + ((size_t)slot * nsb + me) * spec_sz; };
+  auto vt = [&](int slot) { return team_vt + ((size_t)slot * nsb + me) * vt_sz; };
+  const int last0 = (a.n_ck - 1) * k;  // first step of the last segment
   uint64_t* xs_a = a.xspec + ((size_t)c.team * 2 + 0) * nsb * 4 * N;
   uint64_t* xs_b = a.xspec + ((size_t)c.team * 2 + 1) * nsb * 4 * N;
   const double* phase_km = a.phase + (size_t)me * N;
@@ -219,8 +255,9 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdAr
     float2 x[RR], y[RR], gx[RR], gy[RR];
     double rho_acc = 0.0;
 
-    // one forward step s (0-based) on x / y, with its intensity exchange round
-    auto forward_step = [&](int s) {
+    // Forward step s (0-based) on x / y with its intensity exchange round;
+    // stores (v, theta) at `dst` if given, and stops after theta if !tail.
+    auto forward_step = [&](int s, float* dst, bool tail) {
       t = opaque_tid();
       apply_diag<N, false>(x, y, (s == 0 ? a.tab.h_first : a.tab.h_mid) + (size_t)me * N, t);
       fft<N, true>(x, y, lxy, tw, t);
@@ -230,18 +267,21 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdAr
       coupled_fir<N>(c, a.tab.cpad + ((size_t)(s * nsb + me) * nsb) * tap_pad, xrow, rnd, p, theta, lf);
       ++rnd;
       ++np;
-      rotate<N, -1>(x, y, theta);
-      fft<N, false>(x, y, lxy, tw, t);
+      if (dst != nullptr) store_vtheta<N>(dst, x, y, theta, opaque_tid());
+      if (tail) {
+        rotate<N, -1>(x, y, theta);
+        fft<N, false>(x, y, lxy, tw, t);
+      }
     };
 
-    // ---- A: forward sweep, storing S_s every k steps
+    // ---- A: forward sweep
     const float2* in_x = a.in + (size_t)inst * 2 * T;
     gather_block<N, false>(in_x, in_x + T, blk, a.hop, a.n_ov, T, a.boundary, nsb, me, t, x, y);
     fft<N, false>(x, y, lxy, tw, t);
     polyphase_to_subband<N>(c, xs_a, rnd++, t, x, y);
     for (int s = 0; s < a.steps; ++s) {
-      if (s % k == 0) store_state<N>(st(s / k), x, y, opaque_tid());
-      forward_step(s);
+      if (s % k == 0) store_state<N>(sp(s / k), x, y, opaque_tid());
+      forward_step(s, s >= last0 ? vt(s - last0) : nullptr, true);
     }
 
     // ---- B: adjoint of the output stage
@@ -258,26 +298,24 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdAr
     for (int seg = a.n_ck - 1; seg >= 0; --seg) {
       const int s0 = seg * k;
       const int s1 = min(s0 + k, a.steps);
-      t = opaque_tid();
-      load_state<N>(st(seg), x, y, t);
-      for (int j = 1; j < s1 - s0; ++j) {  // recompute S_{s0+j}
-        forward_step(s0 + j - 1);
-        store_state<N>(st(a.n_ck + j), x, y, opaque_tid());
+      if (seg != a.n_ck - 1) {  // recompute (v, theta) of the segment's steps
+        load_state<N>(sp(seg), x, y, opaque_tid());
+        for (int j = 0; j < s1 - s0; ++j) forward_step(s0 + j, vt(j), j + 1 < s1 - s0);
       }
-      for (int s = s1; s > s0; --s) {  // 1-based step s, from S_{s-1}
+      for (int s = s1; s > s0; --s) {  // 1-based step s
         t = opaque_tid();
-        const int j = s - 1 - s0;
-        load_state<N>(j == 0 ? st(seg) : st(a.n_ck + j), x, y, t);
         const float2* hs = (s == 1 ? a.tab.h_first : a.tab.h_mid) + (size_t)me * N;
-        // recompute v, p, theta of step s
-        apply_diag<N, false>(x, y, hs, t);
-        fft<N, true>(x, y, lxy, tw, t);
         float p[RR], theta[RR], tbar[RR];
+        load_vtheta<N>(vt(s - 1 - s0), x, y, theta, t);  // v, theta of step s
         intensity<N>(x, y, p);
+        // republish p for the coefficient gradient of the other members
         const unsigned tag_p = rnd++;
         uint64_t* prow = a.xp + ((size_t)c.team * 2 + (np & 1u)) * nsb * N;
         ++np;
-        coupled_fir<N>(c, a.tab.cpad + ((size_t)((s - 1) * nsb + me) * nsb) * tap_pad, prow, tag_p, p, theta, lf);
+        if (nsb > 1) {
+#pragma unroll
+          for (int o = 0; o < RR; ++o) xput(prow + (size_t)me * N + t + NT * o, p[o], tag_p);
+        }
         // g_w, theta_bar
         fft<N, true>(gx, gy, lxy, tw, t);
 #pragma unroll
@@ -304,7 +342,7 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdAr
         }
         fft<N, false>(gx, gy, lxy, tw, t);  // g_A
         if (s == 1) {                          // first GVD depends on rho
-          load_state<N>(st(0), x, y, t);
+          load_state<N>(sp(0), x, y, t);
           apply_diag<N, false>(x, y, hs, t);  // A1
           rho_acc += rho_term<N>(phase_km, a.L, t, gx, gy, x, y);
         }
@@ -461,15 +499,17 @@ int bwd_occupancy_per_cu(int log_np, int* blocks) {
 
 BwdLayout bwd_layout(const cbessfm_plan_t* p, long long T, int batch, int ck_every) {
   BwdLayout L;
-  L.k = ck_every <= 0 ? 1 : (ck_every > p->steps ? p->steps : ck_every);
+  // one segment (nothing recomputed) for ck_every <= 1 or >= steps
+  L.k = (ck_every <= 1 || ck_every > p->steps) ? p->steps : ck_every;
   L.n_ck = (p->steps + L.k - 1) / L.k;
   L.nblk = (int)((T + p->hop - 1) / p->hop);
   L.n_items = batch * L.nblk;
   L.n_teams = L.n_items < p->bwd_team_capacity ? L.n_items : p->bwd_team_capacity;
   auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
   const size_t nsb = p->sb.n_sb;
-  L.states_off = 0;
-  L.cpart_off = up(L.states_off + sizeof(float2) * (size_t)L.n_teams * (L.n_ck + L.k) * nsb * 2 * p->Np);
+  L.spec_off = 0;
+  L.vtheta_off = up(L.spec_off + sizeof(float2) * (size_t)L.n_teams * L.n_ck * nsb * 2 * p->Np);
+  L.cpart_off = up(L.vtheta_off + sizeof(float) * (size_t)L.n_teams * L.k * nsb * 5 * p->Np);
   L.rpart_off = up(L.cpart_off + sizeof(float) * (size_t)L.n_items * p->steps * nsb * nsb * p->n_taps);
   L.gin_off = up(L.rpart_off + sizeof(double) * (size_t)L.n_items * nsb);
   L.bytes = up(L.gin_off + sizeof(float2) * (size_t)L.n_items * 2 * p->N);
@@ -506,7 +546,8 @@ int launch_backward(cbessfm_plan_t* p, const void* field_in, const void* grad_ou
   a.xspec = p->d_xspec;
   a.xp = p->d_xp;
   a.xq = p->d_xq;
-  a.states = reinterpret_cast<float2*>(ws + L.states_off);
+  a.spec = reinterpret_cast<float2*>(ws + L.spec_off);
+  a.vtheta = reinterpret_cast<float*>(ws + L.vtheta_off);
   a.cpart = reinterpret_cast<float*>(ws + L.cpart_off);
   a.rpart = reinterpret_cast<double*>(ws + L.rpart_off);
   a.gin_blk = grad_in ? reinterpret_cast<float2*>(ws + L.gin_off) : nullptr;

@@ -84,7 +84,7 @@ struct BwdArgs {
   int T, n_items, nblk;
   int n_sb, steps, n_chunks, nc, n_taps, n_ov, hop, boundary;
   int n_teams;
-  int ck_every, n_ck;  // states stored every ck_every steps, n_ck of them
+  int ck_every, n_ck;  // segments of ck_every steps, n_ck of them
   unsigned rounds_per_item;
   unsigned* epoch;     // [teams] exchange rounds completed so far by each team (device)
   Tables tab;
@@ -94,7 +94,8 @@ struct BwdArgs {
   uint64_t* xspec;
   uint64_t* xp;         // tagged intensity rows
   uint64_t* xq;         // tagged theta_bar rows, [team_capacity][2][n_sb][N']
-  float2* states;       // [n_teams][n_ck + ck_every][n_sb][2][N']
+  float2* spec;         // [n_teams][n_ck][n_sb][2][N'] spectrum at each segment start
+  float* vtheta;        // [n_teams][ck_every][n_sb][5 N'] (v_x, v_y, theta) of a segment's steps
   float* cpart;         // [n_items][steps][n_sb][n_sb][n_taps]
   double* rpart;        // [n_items][n_sb]
   float2* gin_blk;      // [n_items][2][N] or null
@@ -104,7 +105,7 @@ struct BwdArgs {
 // Workspace layout of one adjoint call.
 struct BwdLayout {
   int k, n_ck, nblk, n_items, n_teams;
-  size_t states_off, cpart_off, rpart_off, gin_off, bytes;
+  size_t spec_off, vtheta_off, cpart_off, rpart_off, gin_off, bytes;
 };
 
 }  // namespace cbessfm

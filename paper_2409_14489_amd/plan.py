@@ -173,7 +173,11 @@ class Plan:
     def backward(self, field_in: torch.Tensor, grad_out: torch.Tensor, need_grad_in: bool = True,
                  checkpoint_every: int = 1, workspace: torch.Tensor | None = None, stream=None):
         """(grad_in or None, grad_c [steps][n_sb][n_sb][n_taps], grad_rho [1]) for the current
-        coefficients and split ratio, given grad_out = dL/dRe(out) + j dL/dIm(out)."""
+        coefficients and split ratio, given grad_out = dL/dRe(out) + j dL/dIm(out).
+
+        ``checkpoint_every`` <= 1 stores every step's intermediate field and
+        phase (no recompute); 1 < k < steps stores a spectrum every k steps
+        and recomputes each k-step segment once (less workspace)."""
         x = self._field(field_in)
         g = self._field(grad_out)
         if g.shape != x.shape:
