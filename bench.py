@@ -82,7 +82,7 @@ def measured_traffic():
 
 
 def algorithmic_flops_per_block(n_sb, n_sub, steps, n_taps):
-    """Flops of one overlap-and-save block (convention in the design doc):
+    """Flops of one overlap-and-save block, by this convention:
     5 n log2 n per complex DFT of size n, 6 per complex multiply, 7 per
     dual-polarisation intensity, 2 per tap of the direct-form filter of
     eq. (15); the sine/cosine of the rotation is not counted."""
@@ -414,7 +414,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
-              "(the multi-GPU sharding is described in DESIGN.md)", file=sys.stderr)
+              "(the path would shard over blocks and batch instances, one process per GPU)", file=sys.stderr)
         sys.exit(2)
     legs = set(args.legs.split(","))
 

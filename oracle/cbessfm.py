@@ -29,7 +29,7 @@ For every batch instance and every overlap-and-save block b:
 4. final GVD with dz = rho L (Sec. III-C).
 5. MUX, ``u_p = IDFT_N(U_p) / N``, keep samples [N_ov/2, N - N_ov/2).
 
-Readings of points the paper leaves open are listed in the design doc (subband
+Readings of points the paper leaves open are documented with the design (subband
 placement and scaling, DBP sign, circular FIR, framing, boundary).
 """
 from __future__ import annotations

@@ -4,7 +4,7 @@ This module only produces inputs: transmitted symbols and the received
 dual-polarisation field.  It holds none of the backpropagation arithmetic and
 is used by the tests, the oracle timing and the benchmark alike.
 
-Recipe (Sec. IV-A, with the sizes of the workloads named in the design doc):
+Recipe (Sec. IV-A, at the sizes of the named workloads in ``workloads.py``):
 * uniform i.i.d. square QAM per polarisation and channel, unit mean energy,
   numpy ``Generator(PCG64(seed))``;
 * frequency-domain root-raised-cosine pulses;
