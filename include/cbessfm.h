@@ -152,6 +152,40 @@ int cbessfm_backward(cbessfm_plan_t* plan, const void* field_in, const void* gra
                      int32_t checkpoint_every, void* workspace, size_t workspace_bytes,
                      void* stream);
 
+/* ---- Tied coefficients of the fitting protocol (Sec. III-B) ----
+ * params: device float [n_sb][n_taps]; row h is c_h, the applied coefficients
+ * (rad/W) between subbands l and l + h, tap t <-> m = t - Nc; of row 0 only
+ * the taps m >= 0 are read (c_0 is even, eq. (25)).  weights: device float
+ * [steps], w_s of assumption (i).  half_taps: host int32 [n_sb] with
+ * 0 <= Nc(h) <= Nc (assumption (iii)), or NULL for Nc everywhere.
+ * cbessfm_tie_expand writes the applied tensor, device float
+ * [steps][n_sb][n_sb][n_taps]:
+ *   C[s][i][l][m] = w_s c_{l-i}[m] (l >= i),  w_s c_{i-l}[-m] (l < i)
+ * (eqs. (23), (24)), zero where |m| > Nc(|l - i|).
+ * cbessfm_tie_reduce is its transpose: grad_params [n_sb][n_taps] from
+ * grad_c of that shape, summed in FP64 in a fixed order (unused entries of
+ * row 0 get 0).  Both return CBESSFM_EINVAL for n_sb outside 1..8, n_taps not
+ * odd in 1..255, steps < 1, a bad half_taps entry or a NULL pointer;
+ * asynchronous on stream; the caller owns every buffer. */
+int cbessfm_tie_expand(const float* params, const float* weights, int32_t steps, int32_t n_sb,
+                       int32_t n_taps, const int32_t* half_taps, float* coeffs, void* stream);
+int cbessfm_tie_reduce(const float* grad_c, const float* weights, int32_t steps, int32_t n_sb,
+                       int32_t n_taps, const int32_t* half_taps, float* grad_params, void* stream);
+
+/* Host FP64 weights of assumption (i) of Sec. III-B, in backpropagation step
+ * order: the effective length of the physical step each backpropagation step
+ * undoes, divided by the mean over steps (for equal steps within a span, the
+ * ratio of the signal powers at the step inputs).  mean_leff_km (may be NULL)
+ * receives that mean, so gamma * mean_leff_km is the nonlinear phase per
+ * watt of an average step. */
+int cbessfm_step_weights(const cbessfm_link* link, int32_t steps, double* weights, double* mean_leff_km);
+
+/* Host: half lengths Nc(h), h = 0..n_sb-1, of assumption (iii) of Sec. III-B:
+ * 2 Nc(h) + 1 is the odd integer nearest to pi L |beta2| R'^2 (h + 1), L the
+ * step length, R' = R / n_sb, capped at n_taps / 2. */
+int cbessfm_tied_half_taps(const cbessfm_link* link, int32_t n_sb, int32_t steps, int32_t n_taps,
+                           int32_t* half_taps);
+
 /* Analytic applied coefficients (host FP64), [steps][n_sb][n_sb][n_taps]:
  * c_il[m] of eq. (13) on an odd grid_m x grid_m midpoint grid (0 = n_taps)
  * with the kernel of eq. (6) integrated exactly between amplifiers (eq. (22)

@@ -12,6 +12,8 @@ _PUBLIC = {
     "CbessfmError": "_lib", "EXPORTED": "_lib", "LIB_PATH": "_lib",
     "CBESSFMFunction": "autograd", "cbessfm": "autograd",
     "Batch": "batch", "schedule": "batch", "autotune": "batch",
+    "tie": "tied", "tie_expand": "tied", "tie_reduce": "tied", "fit_tied": "tied", "step_weights": "tied",
+    "tied_half_taps": "tied", "ssfm_start": "tied", "analytic_rows": "tied", "tied_coeffs": "tied",
 }
 
 __all__ = sorted(_PUBLIC)

@@ -4,7 +4,8 @@
 the field (complex64, (2, T) or (B, 2, T)), the applied coefficients
 (float32 [steps][n_sb][n_sb][n_taps]) and the split ratio (float32 scalar
 tensor), all on the device.  The forward is ``cbessfm_run``; the backward is
-``cbessfm_backward`` (reverse sweep with recomputation from stored spectra).
+``cbessfm_backward`` (reverse sweep over the stored step fields and phases,
+or over segments recomputed from stored spectra when checkpointing).
 The plan holds one coefficient set at a time, so both passes load the
 tensors they were given before running.
 """

@@ -151,6 +151,48 @@ int cbessfm_plan_check(const cbessfm_link* link, const cbessfm_subbands* sb, int
   return CBESSFM_OK;
 }
 
+// Weights of assumption (i) of Sec. III-B: the effective length of the
+// physical step each backpropagation step undoes (K of eq. (6) at b = 0, over
+// gamma), divided by their mean.  For equal steps within a span this is the
+// ratio of the signal powers at the step inputs.
+int cbessfm_step_weights(const cbessfm_link* link, int32_t steps, double* weights, double* mean_leff_km) {
+  const int rc = check_link(link);
+  if (rc) return rc;
+  if (steps < 1 || !weights) return CBESSFM_EINVAL;
+  const double alpha = link->alpha_db_km * std::log(10.0) / 10.0;
+  const double step = link->span_km * link->n_spans / steps;
+  double sum = 0.0;
+  for (int s = 0; s < steps; ++s) {
+    const int j = steps - 1 - s;  // physical step, 0-based
+    weights[s] = step_kernel(0.0, j * step, (j + 1) * step, 0.0, alpha, link->span_km, 1.0).real();
+    sum += weights[s];
+  }
+  const double mean = sum / steps;
+  for (int s = 0; s < steps; ++s) weights[s] /= mean;
+  if (mean_leff_km) *mean_leff_km = mean;
+  return CBESSFM_OK;
+}
+
+// Assumption (iii) of Sec. III-B: 2 Nc(h) + 1 is the odd integer nearest to
+// pi L |beta2| R'^2 (h + 1) (L the step length, R' the subband rate), capped
+// at n_taps.
+int cbessfm_tied_half_taps(const cbessfm_link* link, int32_t n_sb, int32_t steps, int32_t n_taps,
+                           int32_t* half_taps) {
+  const int rc = check_link(link);
+  if (rc) return rc;
+  if (n_sb < 1 || n_sb > kMaxSubbands || steps < 1 || n_taps < 1 || (n_taps & 1) == 0 || !half_taps)
+    return CBESSFM_EINVAL;
+  const double step = link->span_km * link->n_spans / steps;
+  const double rp = link->sample_rate_hz / n_sb;
+  const double b2 = std::fabs(link->beta2_ps2_km) * 1e-24;
+  for (int h = 0; h < n_sb; ++h) {
+    const double x = kPi * step * b2 * rp * rp * (h + 1);
+    const double nc = std::floor((x - 1.0) / 2.0 + 0.5);
+    half_taps[h] = (int32_t)std::min<double>(n_taps / 2, std::max(0.0, nc));
+  }
+  return CBESSFM_OK;
+}
+
 int cbessfm_analytic_coeffs(const cbessfm_link* link, const cbessfm_subbands* sb, int32_t steps,
                             double split_ratio, int32_t n_taps, int32_t grid_m, double* out_host) {
   int rc = check_link(link);

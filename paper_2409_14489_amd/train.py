@@ -74,6 +74,48 @@ def phase_aligned_mse(z: torch.Tensor, s: torch.Tensor) -> torch.Tensor:
     return (z * rot - s).abs().pow(2).mean()
 
 
+def adam_loop(params, loss_fn, iters: int, lr: float, graph: bool = False, warmup: int = 3,
+              after_step=None, device=None):
+    """Adam on ``params`` for ``iters`` iterations of ``loss_fn()`` (which
+    returns a scalar tensor).  With ``graph`` the iteration (forward, loss,
+    backward, update) is recorded in a HIP graph after ``warmup`` eager
+    iterations on a side stream and replayed for the rest; ``iters`` counts
+    all of them.  ``after_step`` runs under no_grad after every update.
+    Returns the losses as a tensor."""
+    opt = torch.optim.Adam(params, lr=lr, capturable=graph)
+
+    def step():
+        opt.zero_grad(set_to_none=not graph)
+        loss = loss_fn()
+        loss.backward()
+        opt.step()
+        if after_step is not None:
+            with torch.no_grad():
+                after_step()
+        return loss.detach()
+
+    losses = []
+    if not graph:
+        for _ in range(iters):
+            losses.append(step())
+        return torch.stack(losses)
+    side = torch.cuda.Stream(device=device)
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(min(warmup, iters)):
+            losses.append(step())
+    torch.cuda.current_stream().wait_stream(side)
+    if iters > warmup:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            static_loss = step()
+        for _ in range(iters - warmup):
+            g.replay()
+            losses.append(static_loss.clone())
+        del g
+    return torch.stack(losses)
+
+
 def fit(plan, fields: torch.Tensor, symbols: torch.Tensor, receiver: SymbolReceiver, coeffs0, rho0: float,
         iters: int = 200, lr: float = 1e-2, checkpoint_every: int = 1, fit_rho: bool = True,
         graph: bool = False, warmup: int = 3):
@@ -92,35 +134,22 @@ def fit(plan, fields: torch.Tensor, symbols: torch.Tensor, receiver: SymbolRecei
     u = (c0 / scale).clone().requires_grad_(True)
     rho = torch.tensor(float(rho0), dtype=torch.float32, device=fields.device, requires_grad=fit_rho)
     params = [u, rho] if fit_rho else [u]
-    opt = torch.optim.Adam(params, lr=lr, capturable=graph)
 
-    def step():
-        opt.zero_grad(set_to_none=not graph)
+    def loss_fn():
         y = cbessfm(fields, (u * scale).contiguous(), rho, plan, checkpoint_every)
-        loss = phase_aligned_mse(receiver(y), symbols)
-        loss.backward()
-        opt.step()
-        with torch.no_grad():
-            rho.clamp_(0.0, 1.0)
-        return loss.detach()
+        return phase_aligned_mse(receiver(y), symbols)
 
-    losses = []
-    if not graph:
-        for _ in range(iters):
-            losses.append(step())
-        return (u * scale).detach(), rho.detach(), torch.stack(losses)
-    side = torch.cuda.Stream(device=fields.device)
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        for _ in range(min(warmup, iters)):
-            losses.append(step())
-    torch.cuda.current_stream().wait_stream(side)
-    if iters > warmup:
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
-            static_loss = step()
-        for _ in range(iters - warmup):
-            g.replay()
-            losses.append(static_loss.clone())
-        del g
-    return (u * scale).detach(), rho.detach(), torch.stack(losses)
+    losses = adam_loop(params, loss_fn, iters, lr, graph=graph, warmup=warmup,
+                       after_step=lambda: rho.clamp_(0.0, 1.0), device=fields.device)
+    return (u * scale).detach(), rho.detach(), losses
+
+
+def snr_db(plan, coeffs: torch.Tensor, rho, fields: torch.Tensor, symbols: torch.Tensor,
+           receiver: SymbolReceiver) -> float:
+    """Effective SNR of the received symbols after backpropagation with the
+    given coefficients, matched filtering, sampling and common-phase removal:
+    -10 log10 of the phase-aligned mean square error (unit-energy symbols)."""
+    rho_t = torch.as_tensor(rho, dtype=torch.float32, device=fields.device).reshape(())
+    with torch.no_grad():
+        mse = phase_aligned_mse(receiver(cbessfm(fields, coeffs.contiguous(), rho_t, plan)), symbols)
+    return -10.0 * math.log10(float(mse))
