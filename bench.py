@@ -403,14 +403,75 @@ def leg_batched(args):
     return out
 
 
+# ------------------------------------------------------------------ protocol leg
+PROTO_WORKLOAD = "5ch-64GBd-64QAM-2^13sym-15x80km-central"
+
+
+def leg_protocol(args):
+    """The paper's coefficient fitting and method comparison (Sec. III-B,
+    IV-B) on the central channel of a five-channel link: tied sequential fits
+    on two training realisations, SNR on two other realisations, complexity
+    from the paper's model."""
+    import numpy as np
+    import torch
+    from paper_2409_14489_amd import run_method
+    from paper_2409_14489_amd.train import SymbolReceiver
+    from synth import dbp_rate, workload
+
+    def data(seeds):
+        xs, ss = [], []
+        for sd in seeds:
+            x, s, w = workload(PROTO_WORKLOAD, sd)
+            xs.append(x)
+            ss.append(s[0])
+        return (torch.from_numpy(np.stack(xs).astype(np.complex64)).cuda(),
+                torch.from_numpy(np.stack(ss).astype(np.complex64)).cuda()), w
+
+    t0 = time.perf_counter()
+    train, w = data([6000, 6001])
+    test, _ = data([6100, 6101])
+    t_gen = time.perf_counter() - t0
+    wdm, ch, d = w["wdm"], w["ch"], w["dbp"]
+    rate = dbp_rate(w)
+    link = link_of(ch, rate)
+    p_w = 1e-3 * 10 ** (wdm.power_dbm_per_channel / 10)
+    rx = SymbolReceiver(train[0].shape[-1], rate, wdm.baud, wdm.rolloff, p_w)
+    block = d["n_sb"] * d["n_sub"]
+    common = dict(block=block, overlap=d["n_overlap"], n_sps=rate / wdm.baud, iters_per_row=args.proto_iters)
+    taps = 255
+    t0 = time.perf_counter()
+    methods = [run_method("edc", link, train, test, rx, **common),
+               run_method("ideal", link, train, test, rx, steps=20 * ch.n_spans, **common)]
+    for st in (1, 3, 5, 15):
+        methods.append(run_method("ssfm", link, train, test, rx, steps=st, **common))
+        methods.append(run_method("ossfm", link, train, test, rx, steps=st, **common))
+        methods.append(run_method("essfm", link, train, test, rx, steps=st, n_taps=taps, **common))
+        cands = [run_method("cb-essfm", link, train, test, rx, steps=st, n_sb=2, rho=r, n_taps=taps, **common)
+                 for r in (0.1, 0.3, 0.5)]
+        methods.append(max(cands, key=lambda m: m["snr_train_db"]))   # rho chosen on the training set
+    vs_nsb = [run_method("cb-essfm", link, train, test, rx, steps=15, n_sb=n, rho=0.5, n_taps=min(taps, block // n),
+                         **common) for n in (1, 2, 4, 8)]
+    vs_rho = [run_method("cb-essfm", link, train, test, rx, steps=15, n_sb=2, rho=r, n_taps=taps, **common)
+              for r in (0.0, 0.1, 0.2, 0.3, 0.4, 0.5)]
+    t_fit = time.perf_counter() - t0
+    keep = ("method", "steps", "n_sb", "rho", "snr_test_db", "snr_train_db", "snr_start_test_db", "rm", "half_taps")
+    trim = lambda rs: [{k: r[k] for k in keep if k in r} for r in rs]   # noqa: E731
+    return {"workload": PROTO_WORKLOAD, "dbp_rate_hz": rate, "block": block, "overlap": d["n_overlap"],
+            "train": "2 realisations (seeds 6000-6001)", "test": "2 realisations (seeds 6100-6101)",
+            "fit": f"tied sequential protocol, Adam on the adjoint gradient, {args.proto_iters} iterations per row",
+            "methods_vs_steps": trim(methods), "snr_vs_n_sb": trim(vs_nsb), "snr_vs_rho": trim(vs_rho),
+            "data_generation_s": t_gen, "fits_s": t_fit}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--legs", default="fwd,grad,batched")
+    ap.add_argument("--legs", default="fwd,grad,batched,protocol")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0)
+    ap.add_argument("--proto-iters", type=int, default=60)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
@@ -425,6 +486,8 @@ def main():
         result["grad"] = leg_grad(args)
     if "batched" in legs:
         result["batched"] = leg_batched(args)
+    if "protocol" in legs:
+        result["protocol"] = leg_protocol(args)
     print(json.dumps(result), flush=True)
 
 

@@ -152,6 +152,20 @@ int cbessfm_backward(cbessfm_plan_t* plan, const void* field_in, const void* gra
                      int32_t checkpoint_every, void* workspace, size_t workspace_bytes,
                      void* stream);
 
+/* Complexity model of Sec. III-D (host): real multiplications *rm and real
+ * additions *ra per 2D symbol of a method processing blocks of N samples with
+ * overlap N_ov at n_sps samples per symbol.
+ *   CBESSFM_CX_FREQ: CB-ESSFM with n_sb subbands and a frequency-domain
+ *     NLPR, eqs. (28)-(29) (n_c ignored; n_sb must divide N);
+ *   CBESSFM_CX_TIME: single-band ESSFM with a time-domain NLPR of 2 n_c + 1
+ *     coefficients, eqs. (30)-(31) (n_sb ignored); the SSFM and OSSFM are
+ *     n_c = 0, EDC is steps = 0.
+ * CBESSFM_EINVAL for N < 2, N_ov outside [0, N), steps < 0, n_c < 0,
+ * n_sps <= 0, an unknown kind or a NULL output. */
+enum { CBESSFM_CX_FREQ = 0, CBESSFM_CX_TIME = 1 };
+int cbessfm_complexity(int32_t kind, double n_sps, int64_t N, int64_t N_ov, int32_t steps, int32_t n_sb,
+                       int32_t n_c, double* rm, double* ra);
+
 /* ---- Tied coefficients of the fitting protocol (Sec. III-B) ----
  * params: device float [n_sb][n_taps]; row h is c_h, the applied coefficients
  * (rad/W) between subbands l and l + h, tap t <-> m = t - Nc; of row 0 only

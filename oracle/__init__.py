@@ -8,3 +8,4 @@ from .cbessfm import OraclePlan, run, run_blocks, process_block, dft_bruteforce,
 from .coeffs import Link, dbp_coefficients, physical_coefficients, kernel, kernel_eq22  # noqa: F401
 from .tied import expand as tied_expand, expand_adjoint as tied_expand_adjoint  # noqa: F401
 from .tied import step_weights, tied_half_taps, ssfm_start  # noqa: F401
+from . import complexity  # noqa: F401

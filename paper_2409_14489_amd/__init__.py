@@ -14,6 +14,7 @@ _PUBLIC = {
     "Batch": "batch", "schedule": "batch", "autotune": "batch",
     "tie": "tied", "tie_expand": "tied", "tie_reduce": "tied", "fit_tied": "tied", "step_weights": "tied",
     "tied_half_taps": "tied", "ssfm_start": "tied", "analytic_rows": "tied", "tied_coeffs": "tied",
+    "complexity": "baselines", "run_method": "baselines",
 }
 
 __all__ = sorted(_PUBLIC)

@@ -193,6 +193,43 @@ int cbessfm_tied_half_taps(const cbessfm_link* link, int32_t n_sb, int32_t steps
   return CBESSFM_OK;
 }
 
+// Complexity model of Sec. III-D, per 2D symbol: a block of N 4D samples
+// keeps N - N_ov of them, each carrying two 2D symbols at n samples per
+// symbol.  Frequency-domain CB-ESSFM: 4 size-N CFFTs, 4 N_sb N_st size-N'
+// CFFTs (split radix: N log2 N - 3N + 4 RM, 3 N log2 N - 3N + 4 RA), N_st + 1
+// dispersion steps (6N RM, 6N RA) and N_st NLPRs (N log2 N' + N (3 N_sb + 13) / 2
+// + 4 N_sb RM, 3 N log2 N' + N (5 N_sb + 11) / 2 + 4 N_sb RA).  Time-domain
+// ESSFM: N_st + 1 dispersion steps of 4 size-N CFFTs each and N_st NLPRs of
+// (11 + Nc) N RM and (11 + 2 Nc) N RA.
+int cbessfm_complexity(int32_t kind, double n_sps, int64_t N, int64_t N_ov, int32_t steps, int32_t n_sb,
+                       int32_t n_c, double* rm, double* ra) {
+  if (!(n_sps > 0.0) || N < 2 || N_ov < 0 || N_ov >= N || steps < 0 || n_c < 0 || !rm || !ra)
+    return CBESSFM_EINVAL;
+  const double n = (double)N;
+  const double per = n_sps / 2.0 / (double)(N - N_ov);  // per 2D symbol, per block
+  auto cfft_rm = [](double m) { return m * std::log2(m) - 3.0 * m + 4.0; };
+  auto cfft_ra = [](double m) { return 3.0 * m * std::log2(m) - 3.0 * m + 4.0; };
+  if (kind == CBESSFM_CX_FREQ) {
+    if (n_sb < 1 || N % n_sb) return CBESSFM_EINVAL;
+    const double np = n / n_sb, lg = std::log2(np);
+    const double m = 4.0 * cfft_rm(n) + 4.0 * n_sb * steps * cfft_rm(np) + 6.0 * n * (steps + 1) +
+                     steps * (n * lg + n * (3.0 * n_sb + 13.0) / 2.0 + 4.0 * n_sb);
+    const double a = 4.0 * cfft_ra(n) + 4.0 * n_sb * steps * cfft_ra(np) + 6.0 * n * (steps + 1) +
+                     steps * (3.0 * n * lg + n * (5.0 * n_sb + 11.0) / 2.0 + 4.0 * n_sb);
+    *rm = per * m;
+    *ra = per * a;
+    return CBESSFM_OK;
+  }
+  if (kind == CBESSFM_CX_TIME) {
+    const double m = (steps + 1) * (4.0 * cfft_rm(n) + 6.0 * n) + steps * (11.0 + n_c) * n;
+    const double a = (steps + 1) * (4.0 * cfft_ra(n) + 6.0 * n) + steps * (11.0 + 2.0 * n_c) * n;
+    *rm = per * m;
+    *ra = per * a;
+    return CBESSFM_OK;
+  }
+  return CBESSFM_EINVAL;
+}
+
 int cbessfm_analytic_coeffs(const cbessfm_link* link, const cbessfm_subbands* sb, int32_t steps,
                             double split_ratio, int32_t n_taps, int32_t grid_m, double* out_host) {
   int rc = check_link(link);

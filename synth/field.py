@@ -165,3 +165,21 @@ def random_field(shape, seed: int, power_w: float = 1.6e-3) -> np.ndarray:
     rng = rng_for(seed)
     z = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
     return z * np.sqrt(power_w / 4.0)
+
+
+def select_channel(field: np.ndarray, sample_rate: float, offset_hz: float, decim: int) -> np.ndarray:
+    """The band of width sample_rate / decim around offset_hz, shifted to
+    baseband and decimated by ``decim`` (ideal brick-wall selection in the
+    frequency domain): the single-channel input of a receiver that
+    backpropagates one WDM channel (Sec. IV-A).  T must be a multiple of decim."""
+    t_len = field.shape[-1]
+    if t_len % decim:
+        raise ValueError("record length must be a multiple of decim")
+    t_out = t_len // decim
+    shift = offset_hz * t_len / sample_rate
+    if abs(shift - round(shift)) > 1e-6:
+        raise ValueError("channel offset must fall on a DFT bin")
+    spec = np.fft.fft(field, axis=-1)
+    k = np.fft.fftfreq(t_out, d=1.0 / t_out).astype(np.int64)       # -t_out/2 .. t_out/2 - 1
+    # a T-point DFT over a t_out-point inverse: the sample values need 1 / decim
+    return np.fft.ifft(spec[..., (k + int(round(shift))) % t_len], axis=-1) / decim

@@ -6,7 +6,7 @@ workload is.  ``n_overlap`` is in full-field samples; ``n_sub`` is N' = N/N_sb.
 """
 from __future__ import annotations
 
-from .field import ChannelSpec, WdmSpec, received_field
+from .field import ChannelSpec, WdmSpec, received_field, select_channel
 
 WORKLOADS = {
     # single channel, one span, one DBP step: the small parity case
@@ -23,6 +23,17 @@ WORKLOADS = {
         ch=ChannelSpec(n_spans=15, span_km=80.0, steps_per_span=1000, nf_db=5.0),
         dbp=dict(n_sb=5, n_sub=4096, n_overlap=2560, n_steps=15, rho=0.3, n_taps=21),
     ),
+    # five 64-GBd channels, 15 spans; only the central channel is selected
+    # (decimated to 128 GS/s, 2 samples/symbol) and backpropagated, as in the
+    # paper's system of Sec. IV-A: the coefficient-fitting and comparison
+    # workload.  The overlap covers the channel's dispersion memory.
+    "5ch-64GBd-64QAM-2^13sym-15x80km-central": dict(
+        wdm=WdmSpec(n_symbols=2 ** 13, n_channels=5, baud=64e9, spacing=100e9, rolloff=0.05,
+                    qam_order=64, sample_rate=640e9, power_dbm_per_channel=3.0),
+        ch=ChannelSpec(n_spans=15, span_km=80.0, steps_per_span=50, nf_db=5.0),
+        select=dict(offset_hz=0.0, decim=5, channel=2),
+        dbp=dict(n_sb=2, n_sub=4096, n_overlap=2688, n_steps=15, rho=0.3, n_taps=45),
+    ),
     # single channel, one span, 15 fractional-span DBP steps (gradient workload)
     "1ch-32GBd-16QAM-2^14sym-1x80km-15steps": dict(
         wdm=WdmSpec(n_symbols=2 ** 14, n_channels=1, baud=32e9, spacing=100e9, rolloff=0.1,
@@ -34,7 +45,9 @@ WORKLOADS = {
 
 
 def workload(name: str, seed: int, steps_per_span: int | None = None, ase: bool = True):
-    """Seeded received field (2, T), symbols and the workload entry.
+    """Seeded received field (2, T), symbols and the workload entry.  With a
+    channel selection the field is that channel at its reduced rate
+    (``dbp_rate``) and the symbols are that channel's, shape (1, 2, n).
 
     ``steps_per_span`` overrides the forward simulator's step count (the
     received field's fine structure does not change the cost or the parity of
@@ -47,4 +60,14 @@ def workload(name: str, seed: int, steps_per_span: int | None = None, ase: bool 
                             "steps_per_span": steps_per_span or ch.steps_per_span,
                             "ase": ase})
     field, syms = received_field(w["wdm"], ch, seed)
+    sel = w.get("select")
+    if sel is not None:
+        field = select_channel(field, w["wdm"].sample_rate, sel["offset_hz"], sel["decim"])
+        syms = syms[sel["channel"]:sel["channel"] + 1]
     return field, syms, w
+
+
+def dbp_rate(w) -> float:
+    """Sampling rate of the field the workload backpropagates."""
+    sel = w.get("select")
+    return w["wdm"].sample_rate / (sel["decim"] if sel else 1)

@@ -154,3 +154,25 @@ def test_sequential_fit_in_a_graph_follows_the_eager_fit():
     assert np.allclose(le, lg, rtol=1e-4)
     assert torch.allclose(r_e, r_g, rtol=1e-3, atol=1e-6 * float(r_e.abs().max()))
     plan.close()
+
+
+def test_comparison_methods_on_the_same_kernels():
+    """EDC, SSFM, OSSFM, ESSFM and CB-ESSFM as plan configurations (Sec. IV-B):
+    each fitted method improves on its starting point, and the reported
+    complexity is the paper's model for that configuration."""
+    from paper_2409_14489_amd import complexity, run_method
+    plan, link, x, s, rx = protocol_case()
+    plan.close()
+    train = test = (x, s)
+    common = dict(block=1024, overlap=128, n_sps=2.0, iters_per_row=15)
+    edc = run_method("edc", link, train, test, rx, **common)
+    assert edc["rm"] == complexity("time", 2.0, 1024, 128, 0)["rm"]
+    ssfm = run_method("ssfm", link, train, test, rx, steps=5, **common)
+    for m, kw in (("ossfm", {}), ("essfm", dict(n_taps=15)), ("cb-essfm", dict(n_sb=2, n_taps=15, rho=0.3))):
+        r = run_method(m, link, train, test, rx, steps=5, **kw, **common)
+        print(m, r["snr_start_test_db"], "->", r["snr_test_db"], "RM", r["rm"])
+        assert r["snr_test_db"] > r["snr_start_test_db"]
+        if m != "cb-essfm":
+            assert abs(r["snr_start_test_db"] - ssfm["snr_test_db"]) < 1e-3   # both start at the SSFM
+    assert r["rm"] == complexity("cb-essfm", 2.0, 1024, 128, 5, n_sb=2)["rm"]
+    print("EDC", edc["snr_test_db"], "SSFM", ssfm["snr_test_db"])
