@@ -84,6 +84,9 @@ class OraclePlan:
     coeffs        : applied coefficients C[s][i][l][tap], shape
                     (N_st, N_sb, N_sb, 2 Nc + 1), tap index t <-> m = t - Nc
     boundary      : "circular" (default) or "zero"
+    nlpr          : "averaged" (default): one phase per subband from the total
+                    intensity, eq. (15); "dual": separate phases for the two
+                    polarisations, eqs. (20)-(21)
     """
 
     beta2_s2_km: float
@@ -96,6 +99,7 @@ class OraclePlan:
     n_overlap: int
     coeffs: np.ndarray
     boundary: str = "circular"
+    nlpr: str = "averaged"
     dft: Callable[..., np.ndarray] = dc_field(default=_dft_numpy, repr=False)
 
     def __post_init__(self) -> None:
@@ -111,6 +115,8 @@ class OraclePlan:
             raise ValueError("rho must lie in [0, 1]")
         if self.boundary not in ("circular", "zero"):
             raise ValueError("boundary must be 'circular' or 'zero'")
+        if self.nlpr not in ("averaged", "dual"):
+            raise ValueError("nlpr must be 'averaged' or 'dual'")
         self.coeffs = c
 
     @property
@@ -192,6 +198,31 @@ def coupled_fir(p: np.ndarray, c_step: np.ndarray) -> np.ndarray:
     return theta
 
 
+def dual_pol_phases(px: np.ndarray, py: np.ndarray, c_step: np.ndarray) -> np.ndarray:
+    """theta^x and theta^y of eqs. (20)-(21), shape (N_sb, 2, N').
+
+    px, py: (N_sb, N') intensities |x_l|^2, |y_l|^2.  The applied tensor C
+    carries the 3/2 cross-band factor of eq. (15) (C_il = (3/2) c_il for
+    l != i), so the paper's c_il is (2/3) C_il: the same subband acts through
+    c_ii on |x_i|^2 + |y_i|^2, another subband through c_il on 2 |x_l|^2 +
+    |y_l|^2 (co-polarised twice the orthogonal) for theta^x and on
+    |x_l|^2 + 2 |y_l|^2 for theta^y.  Same tap convention as ``coupled_fir``.
+    """
+    nsb = px.shape[0]
+    own = np.zeros_like(c_step)
+    cross = np.zeros_like(c_step)
+    for i in range(nsb):
+        for l in range(nsb):
+            if i == l:
+                own[i, l] = c_step[i, l]
+            else:
+                cross[i, l] = c_step[i, l] * (2.0 / 3.0)
+    spm = coupled_fir(px + py, own)
+    th_x = spm + coupled_fir(2.0 * px + py, cross)
+    th_y = spm + coupled_fir(px + 2.0 * py, cross)
+    return np.stack([th_x, th_y], axis=1)
+
+
 def process_block(u: np.ndarray, plan: OraclePlan) -> np.ndarray:
     """Run steps 2-5 on one block u of shape (2, N); returns (2, N)."""
     dft = plan.dft
@@ -206,9 +237,13 @@ def process_block(u: np.ndarray, plan: OraclePlan) -> np.ndarray:
         h = h_first if s == 0 else h_mid
         v_spec = v_spec * h[:, None, :]               # 3a. GVD
         v = dft(v_spec, inverse=True) / n             # 3b. subband samples
-        p = np.abs(v[:, 0]) ** 2 + np.abs(v[:, 1]) ** 2   # 3c. intensity
-        theta = coupled_fir(p, plan.coeffs[s])        # 3d. coupled FIR
-        v = v * np.exp(-1j * theta)[:, None, :]       # 3e. rotation
+        if plan.nlpr == "dual":                       # 3c-3e, eqs. (20)-(21)
+            theta = dual_pol_phases(np.abs(v[:, 0]) ** 2, np.abs(v[:, 1]) ** 2, plan.coeffs[s])
+            v = v * np.exp(-1j * theta)
+        else:
+            p = np.abs(v[:, 0]) ** 2 + np.abs(v[:, 1]) ** 2   # 3c. intensity
+            theta = coupled_fir(p, plan.coeffs[s])        # 3d. coupled FIR
+            v = v * np.exp(-1j * theta)[:, None, :]       # 3e. rotation
         v_spec = nsb * dft(v)                         # 3f. back to frequency
     v_spec = v_spec * h_last[:, None, :]              # 4.  final GVD
     return dft(mux(v_spec, plan), inverse=True) / n   # 5.  MUX + IDFT_N

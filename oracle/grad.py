@@ -31,6 +31,8 @@ def forward_torch(field_in: torch.Tensor, coeffs: torch.Tensor, rho, plan: Oracl
     last GVD) so that the two places where the split ratio enters
     (Sec. III-C) can be differentiated separately.
     """
+    if plan.nlpr != "averaged":
+        raise NotImplementedError("the gradient oracle covers the averaged NLPR of eq. (15)")
     rho_first, rho_last = (rho, rho) if not isinstance(rho, (tuple, list)) else rho
     t_len = field_in.shape[-1]
     n, nsub, nsb = plan.n_block, plan.n_sub, plan.n_sb
