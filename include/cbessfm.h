@@ -124,6 +124,19 @@ int cbessfm_set_coeffs(cbessfm_plan_t* plan, const float* dev_c, const float* de
 /* Host-side form of the split-ratio update (validated; asynchronous). */
 int cbessfm_set_split_ratio(cbessfm_plan_t* plan, double split_ratio, void* stream);
 
+/* Nonlinear phase rotation used by cbessfm_run.
+ *   CBESSFM_NLPR_AVERAGED (the default): one phase per subband from the total
+ *     intensity |x|^2 + |y|^2 of every subband, eq. (15);
+ *   CBESSFM_NLPR_DUAL_POL: separate phases for the two polarisations,
+ *     eqs. (20)-(21): other subbands act twice as strongly on the co-polarised
+ *     component (weights 2 and 1 instead of the averaged 3/2), the same
+ *     coefficients C (whose 3/2 cross-band factor is then divided out).  It
+ *     costs a second filter and exchange per step.  cbessfm_backward and
+ *     cbessfm_batch_create return CBESSFM_EUNSUPPORTED for such a plan.
+ * CBESSFM_EINVAL for another mode.  Host only; takes effect at the next run. */
+enum { CBESSFM_NLPR_AVERAGED = 0, CBESSFM_NLPR_DUAL_POL = 1 };
+int cbessfm_set_nlpr(cbessfm_plan_t* plan, int32_t mode);
+
 /* Forward backpropagation of batch fields of T samples per polarisation.
  * field_in, field_out: device, complex float32 [batch][2][T], must not
  * overlap.  T >= 1, batch >= 1.  Asynchronous on stream. */

@@ -427,6 +427,7 @@ int cbessfm_batch_create(cbessfm_batch_t** out, const cbessfm_instance* inst, in
     if (!a.plan || !a.field_in || !a.field_out || a.T < 1 || a.batch < 1 || a.T >= (1LL << 31))
       return CBESSFM_EINVAL;
     if (a.plan->device != dev) return CBESSFM_EINVAL;
+    if (a.plan->nlpr != CBESSFM_NLPR_AVERAGED) return CBESSFM_EUNSUPPORTED;  // batches run eq. (15)
     const size_t bytes = (size_t)a.batch * 2 * a.T * sizeof(float2);
     if (overlaps(a.field_in, bytes, a.field_out, bytes)) return CBESSFM_EINVAL;
     for (int j = 0; j < i; ++j) {
@@ -543,7 +544,7 @@ int cbessfm_batch_create(cbessfm_batch_t** out, const cbessfm_instance* inst, in
         it.inst = (int)j;
         it.sub = (int)(id - first_item[j]);
         it.round_off = rounds;
-        rounds += (unsigned)bt.insts[j].steps + 2u;
+        rounds += cbessfm::fwd_rounds(bt.insts[j].steps, false);
         items.push_back(it);
       }
       t.rounds = rounds;

@@ -23,7 +23,7 @@ namespace cbessfm {
 // sub = batch entry * nblk + block; the team's exchange rounds for this block
 // are round0 .. round0 + steps + 1.  xs_in / xs_out: the team's two spectrum
 // slots; xp_team: its two intensity-row slots.
-template <int N>
+template <int N, bool DUAL>
 __device__ __forceinline__ void fwd_item(TeamCtx& c, const Inst& d, int sub, unsigned round0, uint64_t* xs_in,
                                          uint64_t* xs_out, uint64_t* xp_team, float* lf) {
   using S = FftShape<N>;
@@ -51,17 +51,27 @@ __device__ __forceinline__ void fwd_item(TeamCtx& c, const Inst& d, int sub, uns
     fft<N, true>(x, y, lxy, tw, t);  // lowpass-equivalent subband samples
     float p[RR], theta[RR];
     intensity<N>(x, y, p);
-    const unsigned round = round0 + 1u + (unsigned)s;
+    const size_t crow = ((size_t)(s * nsb + me) * nsb) * tap_pad;
+    const unsigned round = round0 + 1u + (unsigned)s * (DUAL ? 2u : 1u);
     uint64_t* xrow = xp_team + (size_t)(round & 1u) * nsb * N;
-    coupled_fir<N>(c, d.tab.cpad + ((size_t)(s * nsb + me) * nsb) * tap_pad, xrow, round, p, theta, lf);
-    rotate<N, -1>(x, y, theta);
+    coupled_fir<N>(c, d.tab.cpad + crow, xrow, round, p, theta, lf);
+    if (DUAL) {
+      // theta^{x,y} = theta +- phi, phi_i = (1/3) sum_{l != i} C_il (*) (|x_l|^2 - |y_l|^2)
+      float phi[RR];
+      intensity_diff<N>(x, y, p);
+      uint64_t* drow = xp_team + (size_t)((round + 1u) & 1u) * nsb * N;
+      coupled_fir<N>(c, d.tab.cdpad + crow, drow, round + 1u, p, phi, lf);
+      rotate_dual<N>(x, y, theta, phi);
+    } else {
+      rotate<N, -1>(x, y, theta);
+    }
     fft<N, false>(x, y, lxy, tw, t);
   }
 
   // ---- final GVD, recombination, inverse size-N DFT, kept samples
   t = opaque_tid();
   apply_diag<N, false>(x, y, d.tab.h_last + (size_t)me * N, t);
-  subband_to_polyphase<N>(c, xs_out, round0 + (unsigned)d.steps + 1u, t, x, y);
+  subband_to_polyphase<N>(c, xs_out, round0 + fwd_rounds(d.steps, DUAL) - 1u, t, x, y);
   fft<N, true>(x, y, lxy, tw, t);
   float2* out_x = d.out + (size_t)inst * 2 * T;
   scatter_block<N>(out_x, out_x + T, blk, d.hop, d.n_ov, T, nsb, me, t, x, y);
@@ -70,7 +80,7 @@ __device__ __forceinline__ void fwd_item(TeamCtx& c, const Inst& d, int sub, uns
 // Single plan: team j takes blocks j, j + n_teams, ...  The n_sb members of a
 // team share blockIdx mod 8, i.e. one XCD and its L2 (workgroups are dispatched
 // round-robin over the 8 XCDs).
-template <int LOGN>
+template <int LOGN, bool DUAL>
 __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void fwd_kernel(FwdArgs a) {
   constexpr int N = 1 << LOGN;  // N'
   __shared__ __align__(16) float lf[lds_floats<N>()];
@@ -87,14 +97,14 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void fwd_kernel(FwdArgs 
   c.ctl = a.ctl;
   c.tab = &a.inst.tab;
   const int nsb = c.nsb;
-  const unsigned rounds_per_item = (unsigned)a.inst.steps + 2u;
+  const unsigned rounds_per_item = fwd_rounds(a.inst.steps, DUAL);
   uint64_t* xs_in = a.xspec + ((size_t)c.team * 2 + 0) * nsb * 4 * N;
   uint64_t* xs_out = a.xspec + ((size_t)c.team * 2 + 1) * nsb * 4 * N;
   uint64_t* xp_team = a.xp + (size_t)c.team * 2 * nsb * N;
   const unsigned first = epoch_begin(a.epoch + c.team, &epoch_word);
   unsigned iter = 0;
   for (int item = c.team; item < a.n_items; item += a.n_teams, ++iter)
-    fwd_item<N>(c, a.inst, item, first + iter * rounds_per_item, xs_in, xs_out, xp_team, lf);
+    fwd_item<N, DUAL>(c, a.inst, item, first + iter * rounds_per_item, xs_in, xs_out, xp_team, lf);
   epoch_end(a.epoch + c.team, first, iter * rounds_per_item, c.me);
 }
 
@@ -126,7 +136,7 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void fwd_batch_kernel(Ba
     c.n_chunks = d.n_chunks;
     c.nc = d.nc;
     c.tab = &d.tab;
-    fwd_item<N>(c, d, it.sub, first + it.round_off, xs_in, xs_out, xp_team, lf);
+    fwd_item<N, false>(c, d, it.sub, first + it.round_off, xs_in, xs_out, xp_team, lf);
   }
   epoch_end(epoch, first, tm.rounds, c.me);
 }
@@ -168,14 +178,17 @@ __global__ void tables_kernel(const double* __restrict__ phase, const double* __
 }
 
 // dst[s][i][l][tau] = C[s][i][l][tau] (zero for tau >= n_taps);
-// dstt[s][l][i][tau] = C[s][i][l][n_taps - 1 - tau] (the adjoint's correlation).
+// dstt[s][l][i][tau] = C[s][i][l][n_taps - 1 - tau] (the adjoint's correlation);
+// dstd[s][i][l][tau] = C[s][i][l][tau] / 3 for l != i, 0 on the diagonal.
 __global__ void pad_coeffs_kernel(const float* __restrict__ src, float* __restrict__ dst, float* __restrict__ dstt,
-                                  int steps, int nsb, int n_taps, int tap_pad) {
+                                  float* __restrict__ dstd, int steps, int nsb, int n_taps, int tap_pad) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int rows = steps * nsb * nsb;
   if (i >= rows * tap_pad) return;
   const int row = i / tap_pad, tau = i % tap_pad;
-  dst[i] = tau < n_taps ? src[(size_t)row * n_taps + tau] : 0.0f;
+  const float v = tau < n_taps ? src[(size_t)row * n_taps + tau] : 0.0f;
+  dst[i] = v;
+  dstd[i] = ((row / nsb) % nsb == row % nsb) ? 0.0f : v / 3.0f;
   const int s = row / (nsb * nsb), l = (row / nsb) % nsb, ii = row % nsb;  // row of dstt = (s, l, ii)
   dstt[i] = tau < n_taps ? src[(((size_t)s * nsb + ii) * nsb + l) * n_taps + (n_taps - 1 - tau)] : 0.0f;
 }
@@ -207,8 +220,9 @@ static int launch_persistent(K kernel, const A& args, int grid, int threads, hip
 }
 
 template <int LOGN>
-static int launch_fwd_t(const FwdArgs& args, int grid, hipStream_t s) {
-  return launch_persistent(fwd_kernel<LOGN>, args, grid, FftShape<(1 << LOGN)>::NT, s);
+static int launch_fwd_t(const FwdArgs& args, bool dual, int grid, hipStream_t s) {
+  return dual ? launch_persistent(fwd_kernel<LOGN, true>, args, grid, FftShape<(1 << LOGN)>::NT, s)
+              : launch_persistent(fwd_kernel<LOGN, false>, args, grid, FftShape<(1 << LOGN)>::NT, s);
 }
 
 template <int LOGN>
@@ -241,11 +255,12 @@ int threads_for(int log_np) {
 }
 
 template <int LOGN>
-static int occ_t(int* blocks) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fwd_kernel<LOGN>, FftShape<(1 << LOGN)>::NT, 0) ==
-                 hipSuccess
-             ? CBESSFM_OK
-             : CBESSFM_EHIP;
+static int occ_t(bool dual, int* blocks) {
+  const hipError_t e =
+      dual ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fwd_kernel<LOGN, true>, FftShape<(1 << LOGN)>::NT, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fwd_kernel<LOGN, false>, FftShape<(1 << LOGN)>::NT,
+                                                          0);
+  return e == hipSuccess ? CBESSFM_OK : CBESSFM_EHIP;
 }
 
 template <int LOGN>
@@ -268,14 +283,14 @@ int batch_occupancy_per_cu(int log_np, int* blocks) {
   }
 }
 
-int occupancy_per_cu(int log_np, int* blocks) {
+int occupancy_per_cu(int log_np, bool dual, int* blocks) {
   switch (log_np) {
-    case 8: return occ_t<8>(blocks);
-    case 9: return occ_t<9>(blocks);
-    case 10: return occ_t<10>(blocks);
-    case 11: return occ_t<11>(blocks);
-    case 12: return occ_t<12>(blocks);
-    case 13: return occ_t<13>(blocks);
+    case 8: return occ_t<8>(dual, blocks);
+    case 9: return occ_t<9>(dual, blocks);
+    case 10: return occ_t<10>(dual, blocks);
+    case 11: return occ_t<11>(dual, blocks);
+    case 12: return occ_t<12>(dual, blocks);
+    case 13: return occ_t<13>(dual, blocks);
     default: return CBESSFM_EUNSUPPORTED;
   }
 }
@@ -287,6 +302,7 @@ void fill_tables(const cbessfm_plan_t* p, Tables& tb) {
   tb.tw = p->d_tw;
   tb.poly_tw = p->d_poly;
   tb.cpad = p->d_cpad;
+  tb.cdpad = p->d_cdpad;
   for (int i = 0; i < kMaxSubbands; ++i) tb.wsb[i] = p->wsb[i];
 }
 
@@ -310,7 +326,9 @@ int launch_forward(cbessfm_plan_t* p, const void* in, void* out, long long T, in
   FwdArgs a;
   fill_inst(p, in, out, T, batch, a.inst);
   a.n_items = batch * a.inst.nblk;
-  a.n_teams = a.n_items < p->team_capacity ? a.n_items : p->team_capacity;
+  const bool dual = p->nlpr == CBESSFM_NLPR_DUAL_POL;
+  const int capacity = dual ? p->team_capacity_dual : p->team_capacity;
+  a.n_teams = a.n_items < capacity ? a.n_items : capacity;
   a.epoch = p->d_epoch;
   a.xspec = p->d_xspec;
   a.xp = p->d_xp;
@@ -320,12 +338,12 @@ int launch_forward(cbessfm_plan_t* p, const void* in, void* out, long long T, in
   const int groups = (a.n_teams + kXcds - 1) / kXcds;
   const int grid = groups * kXcds * a.inst.n_sb;
   switch (p->log_np) {
-    case 8: return launch_fwd_t<8>(a, grid, s);
-    case 9: return launch_fwd_t<9>(a, grid, s);
-    case 10: return launch_fwd_t<10>(a, grid, s);
-    case 11: return launch_fwd_t<11>(a, grid, s);
-    case 12: return launch_fwd_t<12>(a, grid, s);
-    case 13: return launch_fwd_t<13>(a, grid, s);
+    case 8: return launch_fwd_t<8>(a, dual, grid, s);
+    case 9: return launch_fwd_t<9>(a, dual, grid, s);
+    case 10: return launch_fwd_t<10>(a, dual, grid, s);
+    case 11: return launch_fwd_t<11>(a, dual, grid, s);
+    case 12: return launch_fwd_t<12>(a, dual, grid, s);
+    case 13: return launch_fwd_t<13>(a, dual, grid, s);
     default: return CBESSFM_EUNSUPPORTED;
   }
 }
@@ -340,8 +358,8 @@ int launch_tables(cbessfm_plan_t* p, hipStream_t s) {
 int launch_pad_coeffs(cbessfm_plan_t* p, const float* src, hipStream_t s) {
   const int rows = p->steps * p->sb.n_sb * p->sb.n_sb;
   const int total = rows * p->tap_pad;
-  pad_coeffs_kernel<<<(total + 255) / 256, 256, 0, s>>>(src, p->d_cpad, p->d_ctpad, p->steps, p->sb.n_sb,
-                                                       p->n_taps, p->tap_pad);
+  pad_coeffs_kernel<<<(total + 255) / 256, 256, 0, s>>>(src, p->d_cpad, p->d_ctpad, p->d_cdpad, p->steps,
+                                                       p->sb.n_sb, p->n_taps, p->tap_pad);
   return hipGetLastError() == hipSuccess ? CBESSFM_OK : CBESSFM_EHIP;
 }
 

@@ -22,6 +22,7 @@ struct Tables {
   const float2* tw;       // [N'] exp(-j 2 pi n / N')
   const float2* poly_tw;  // [n_sb][N'] exp(-j 2 pi i k / N)
   const float* cpad;      // [steps][n_sb][n_sb][tap_pad] applied coefficients, zero padded
+  const float* cdpad;     // the same with a zero diagonal, divided by 3 (dual-polarisation NLPR)
   float2 wsb[kMaxSubbands];  // exp(-j 2 pi a / n_sb)
 };
 
@@ -40,6 +41,11 @@ struct Inst {
   int n_sb, steps, n_chunks, nc, n_ov, hop, boundary;
   Tables tab;
 };
+
+// Exchange rounds of one block: input DEMUX, one per filter and step, output MUX.
+__host__ __device__ inline unsigned fwd_rounds(int steps, bool dual) {
+  return (unsigned)steps * (dual ? 2u : 1u) + 2u;
+}
 
 // Everything a single-plan forward launch needs.
 struct FwdArgs {
@@ -121,6 +127,8 @@ struct cbessfm_plan {
   int cu_count;
   int threads;
   int team_capacity;      // forward teams whose workgroups can all be resident at once
+  int team_capacity_dual; // the same for the dual-polarisation forward kernel
+  int nlpr;               // CBESSFM_NLPR_AVERAGED or CBESSFM_NLPR_DUAL_POL
   int bwd_team_capacity;  // the same for the adjoint kernel
   int xchg_teams;         // teams the exchange buffers are sized for
   // device memory
@@ -131,6 +139,7 @@ struct cbessfm_plan {
   float* d_c;         // [steps][n_sb][n_sb][n_taps] as given
   float* d_cpad;      // padded copy used by the kernels
   float* d_ctpad;     // transposed, tap-reversed padded copy (adjoint)
+  float* d_cdpad;     // padded copy with zero diagonal, / 3 (dual-polarisation NLPR)
   double* d_rho;      // current split ratio
   uint64_t* d_xspec;  // tagged exchange words
   uint64_t* d_xp;
@@ -147,7 +156,7 @@ int launch_forward(cbessfm_plan_t* p, const void* in, void* out, long long T, in
 int launch_tables(cbessfm_plan_t* p, hipStream_t s);
 int launch_pad_coeffs(cbessfm_plan_t* p, const float* src, hipStream_t s);
 int launch_copy_rho(cbessfm_plan_t* p, const float* src, hipStream_t s);
-int occupancy_per_cu(int log_np, int* blocks);
+int occupancy_per_cu(int log_np, bool dual, int* blocks);
 int bwd_occupancy_per_cu(int log_np, int* blocks);
 void fill_tables(const cbessfm_plan_t* p, Tables& tb);
 BwdLayout bwd_layout(const cbessfm_plan_t* p, long long T, int batch, int ck_every);

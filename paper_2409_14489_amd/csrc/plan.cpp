@@ -288,8 +288,8 @@ void cbessfm_destroy(cbessfm_plan_t* p) {
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(p->device);
-  void* bufs[] = {p->d_phase, p->d_h,  p->d_tw,    p->d_poly,  p->d_c,     p->d_cpad, p->d_ctpad,
-                  p->d_rho,   p->d_xspec, p->d_xp, p->d_xq, p->d_epoch, p->d_abort, p->d_err};
+  void* bufs[] = {p->d_phase, p->d_h,     p->d_tw, p->d_poly, p->d_c,     p->d_cpad,  p->d_ctpad, p->d_cdpad,
+                  p->d_rho,   p->d_xspec, p->d_xp, p->d_xq,   p->d_epoch, p->d_abort, p->d_err};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   (void)hipSetDevice(prev);
@@ -328,8 +328,9 @@ int cbessfm_plan(cbessfm_plan_t** out, const cbessfm_link* link, const cbessfm_s
   }
   p->cu_count = prop.multiProcessorCount;
   p->threads = cbessfm::threads_for(p->log_np);
-  int per_cu = 0;
-  if (cbessfm::occupancy_per_cu(p->log_np, &per_cu) != CBESSFM_OK || per_cu < 1) {
+  int per_cu = 0, per_cu_dual = 0;
+  if (cbessfm::occupancy_per_cu(p->log_np, false, &per_cu) != CBESSFM_OK || per_cu < 1 ||
+      cbessfm::occupancy_per_cu(p->log_np, true, &per_cu_dual) != CBESSFM_OK || per_cu_dual < 1) {
     delete p;
     return CBESSFM_EHIP;
   }
@@ -341,12 +342,14 @@ int cbessfm_plan(cbessfm_plan_t** out, const cbessfm_link* link, const cbessfm_s
     return CBESSFM_EHIP;
   }
   p->team_capacity = (per_cu * p->cu_count / (cbessfm::kXcds * sb->n_sb)) * cbessfm::kXcds;
+  p->team_capacity_dual = (per_cu_dual * p->cu_count / (cbessfm::kXcds * sb->n_sb)) * cbessfm::kXcds;
   p->bwd_team_capacity = (bwd_per_cu * p->cu_count / (cbessfm::kXcds * sb->n_sb)) * cbessfm::kXcds;
-  if (p->team_capacity < 1 || p->bwd_team_capacity < 1) {
+  if (p->team_capacity < 1 || p->team_capacity_dual < 1 || p->bwd_team_capacity < 1) {
     delete p;
     return CBESSFM_EUNSUPPORTED;
   }
-  p->xchg_teams = std::max(p->team_capacity, p->bwd_team_capacity);
+  p->xchg_teams = std::max(std::max(p->team_capacity, p->team_capacity_dual), p->bwd_team_capacity);
+  p->nlpr = CBESSFM_NLPR_AVERAGED;
 
   const int N = p->N, Np = p->Np, nsb = sb->n_sb;
   const size_t crows = (size_t)steps * nsb * nsb;
@@ -396,6 +399,7 @@ int cbessfm_plan(cbessfm_plan_t** out, const cbessfm_link* link, const cbessfm_s
   alloc((void**)&p->d_c, sizeof(float) * crows * p->n_taps);
   alloc((void**)&p->d_cpad, sizeof(float) * crows * p->tap_pad);
   alloc((void**)&p->d_ctpad, sizeof(float) * crows * p->tap_pad);
+  alloc((void**)&p->d_cdpad, sizeof(float) * crows * p->tap_pad);
   alloc((void**)&p->d_rho, sizeof(double));
   alloc((void**)&p->d_xspec, xspec_bytes(p));
   alloc((void**)&p->d_xp, xp_bytes(p));
@@ -504,6 +508,12 @@ int cbessfm_status(cbessfm_plan_t* p) {
   return err;
 }
 
+int cbessfm_set_nlpr(cbessfm_plan_t* p, int32_t mode) {
+  if (!p || (mode != CBESSFM_NLPR_AVERAGED && mode != CBESSFM_NLPR_DUAL_POL)) return CBESSFM_EINVAL;
+  p->nlpr = mode;
+  return CBESSFM_OK;
+}
+
 int cbessfm_backward_workspace(const cbessfm_plan_t* p, int64_t T, int32_t batch, int32_t checkpoint_every,
                                size_t* bytes) {
   if (!p || !bytes || T < 1 || batch < 1 || T >= (1LL << 31)) return CBESSFM_EINVAL;
@@ -517,6 +527,7 @@ int cbessfm_backward(cbessfm_plan_t* p, const void* field_in, const void* grad_o
   if (!p || !field_in || !grad_out || !grad_c || !grad_rho || !workspace || T < 1 || batch < 1 ||
       T >= (1LL << 31))
     return CBESSFM_EINVAL;
+  if (p->nlpr != CBESSFM_NLPR_AVERAGED) return CBESSFM_EUNSUPPORTED;  // the adjoint covers eq. (15)
   return cbessfm::launch_backward(p, field_in, grad_out, grad_in, grad_c, grad_rho, T, batch, checkpoint_every,
                                   workspace, workspace_bytes, static_cast<hipStream_t>(stream));
 }

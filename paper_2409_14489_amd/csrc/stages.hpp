@@ -327,4 +327,30 @@ __device__ __forceinline__ void intensity(const float2 (&x)[FftShape<N>::RR], co
     p[o] = x[o].x * x[o].x + x[o].y * x[o].y + y[o].x * y[o].x + y[o].y * y[o].y;
 }
 
+// Dual-polarisation NLPR (eqs. (20)-(21)): d = |x|^2 - |y|^2, the input of
+// the extra cross-band filter.
+template <int N>
+__device__ __forceinline__ void intensity_diff(const float2 (&x)[FftShape<N>::RR],
+                                               const float2 (&y)[FftShape<N>::RR], float (&d)[FftShape<N>::RR]) {
+#pragma unroll
+  for (int o = 0; o < FftShape<N>::RR; ++o)
+    d[o] = (x[o].x * x[o].x + x[o].y * x[o].y) - (y[o].x * y[o].x + y[o].y * y[o].y);
+}
+
+// x *= exp(-j (theta + phi)), y *= exp(-j (theta - phi)).
+template <int N>
+__device__ __forceinline__ void rotate_dual(float2 (&x)[FftShape<N>::RR], float2 (&y)[FftShape<N>::RR],
+                                            const float (&theta)[FftShape<N>::RR],
+                                            const float (&phi)[FftShape<N>::RR]) {
+  constexpr int RR = FftShape<N>::RR;
+#pragma unroll
+  for (int o = 0; o < RR; ++o) {
+    float sn, cs;
+    phase_sincos(theta[o] + phi[o], sn, cs);
+    x[o] = cmul(x[o], make_float2(cs, -sn));
+    phase_sincos(theta[o] - phi[o], sn, cs);
+    y[o] = cmul(y[o], make_float2(cs, -sn));
+  }
+}
+
 }  // namespace cbessfm

@@ -99,6 +99,7 @@ class Plan:
         lk, sb = link.c(), _subbands(n_sb, block_sb, overlap, boundary)
         co, keep = _coeff_struct(coeffs, n_taps, grid_m)
         self.n_taps = co.n_taps
+        self.nlpr = "averaged"
         handle = ctypes.c_void_p()
         rc = lib.cbessfm_plan(ctypes.byref(handle), ctypes.byref(lk), ctypes.byref(sb), int(steps),
                               float(split_ratio), ctypes.byref(co))
@@ -159,6 +160,15 @@ class Plan:
                 raise TypeError("rho must be a one-element float32 CUDA tensor")
             rp = ctypes.c_void_p(rho.data_ptr())
         check(lib.cbessfm_set_coeffs(self._h, cp, rp, _stream_ptr(stream)), "cbessfm_set_coeffs")
+
+    def set_nlpr(self, mode: str):
+        """'averaged' (eq. (15), the default) or 'dual' (separate phases for the
+        two polarisations, eqs. (20)-(21); forward only)."""
+        codes = {"averaged": 0, "dual": 1}
+        if mode not in codes:
+            raise ValueError("mode must be 'averaged' or 'dual'")
+        check(lib.cbessfm_set_nlpr(self._h, codes[mode]), "cbessfm_set_nlpr")
+        self.nlpr = mode
 
     def set_split_ratio(self, rho: float, stream=None):
         check(lib.cbessfm_set_split_ratio(self._h, float(rho), _stream_ptr(stream)), "cbessfm_set_split_ratio")
