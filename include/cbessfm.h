@@ -213,6 +213,25 @@ int cbessfm_step_weights(const cbessfm_link* link, int32_t steps, double* weight
 int cbessfm_tied_half_taps(const cbessfm_link* link, int32_t n_sb, int32_t steps, int32_t n_taps,
                            int32_t* half_taps);
 
+/* Free dispersion segments (Sec. III-C; the step-size distribution and
+ * per-step split ratio left to future work in Sec. V).  dev_lengths: device
+ * double [steps + 1], km: the dispersion compensated before the first NLPR,
+ * between NLPR s and s + 1, and after the last NLPR (by default (1 - rho) L,
+ * L, ..., L, rho L; their sum is normally the link length).  The plan uses
+ * these from the next run or backward on; NULL, cbessfm_set_split_ratio or a
+ * cbessfm_set_coeffs call with a split ratio return to the uniform steps.
+ * Asynchronous on stream (graph-capturable); the lengths are copied. */
+int cbessfm_set_gvd_lengths(cbessfm_plan_t* plan, const double* dev_lengths, void* stream);
+
+/* cbessfm_backward that also writes grad_gvd (device double [steps + 1], or
+ * NULL): dL/d(length of each dispersion segment), in the plan's current
+ * segment layout.  Costs one more size-N' transform per step and member.
+ * Same workspace and errors as cbessfm_backward. */
+int cbessfm_backward_gvd(cbessfm_plan_t* plan, const void* field_in, const void* grad_out,
+                         void* grad_in, float* grad_c, float* grad_rho, double* grad_gvd, int64_t T,
+                         int32_t batch, int32_t checkpoint_every, void* workspace, size_t workspace_bytes,
+                         void* stream);
+
 /* Analytic applied coefficients (host FP64), [steps][n_sb][n_sb][n_taps]:
  * c_il[m] of eq. (13) on an odd grid_m x grid_m midpoint grid (0 = n_taps)
  * with the kernel of eq. (6) integrated exactly between amplifiers (eq. (22)

@@ -87,6 +87,11 @@ class OraclePlan:
     nlpr          : "averaged" (default): one phase per subband from the total
                     intensity, eq. (15); "dual": separate phases for the two
                     polarisations, eqs. (20)-(21)
+    gvd_km        : optional lengths (km) of the N_st + 1 dispersion segments
+                    (before the first NLPR, between consecutive NLPRs, after
+                    the last one): a free step-size distribution and split
+                    ratio per step (Sec. III-C, V).  Default: (1 - rho) L,
+                    L, ..., L, rho L.
     """
 
     beta2_s2_km: float
@@ -100,6 +105,7 @@ class OraclePlan:
     coeffs: np.ndarray
     boundary: str = "circular"
     nlpr: str = "averaged"
+    gvd_km: Optional[np.ndarray] = None
     dft: Callable[..., np.ndarray] = dc_field(default=_dft_numpy, repr=False)
 
     def __post_init__(self) -> None:
@@ -117,6 +123,11 @@ class OraclePlan:
             raise ValueError("boundary must be 'circular' or 'zero'")
         if self.nlpr not in ("averaged", "dual"):
             raise ValueError("nlpr must be 'averaged' or 'dual'")
+        if self.gvd_km is not None:
+            g = np.asarray(self.gvd_km, dtype=np.float64)
+            if g.shape != (self.n_steps + 1,) or np.any(g < 0):
+                raise ValueError("gvd_km must hold N_st + 1 non-negative lengths")
+            self.gvd_km = g
         self.coeffs = c
 
     @property
@@ -130,6 +141,15 @@ class OraclePlan:
 
     def n_blocks(self, t_len: int) -> int:
         return -(-t_len // self.hop)
+
+    def gvd_lengths(self) -> np.ndarray:
+        """Lengths of the N_st + 1 dispersion segments in km."""
+        if self.gvd_km is not None:
+            return self.gvd_km
+        g = np.full(self.n_steps + 1, self.step_km)
+        g[0] = (1.0 - self.rho) * self.step_km
+        g[-1] = self.rho * self.step_km
+        return g
 
 
 # ---------------------------------------------------------------------------
@@ -227,14 +247,11 @@ def process_block(u: np.ndarray, plan: OraclePlan) -> np.ndarray:
     """Run steps 2-5 on one block u of shape (2, N); returns (2, N)."""
     dft = plan.dft
     n, nsb = plan.n_block, plan.n_sb
-    L = plan.step_km
+    seg = plan.gvd_lengths()                          # (1 - rho) L, L, ..., rho L by default
     spec = dft(u)                                     # 2.  U_p = DFT_N(u_p)
     v_spec = demux(spec, plan)                        #     DEMUX
-    h_first = gvd_filter(plan, (1.0 - plan.rho) * L)
-    h_mid = gvd_filter(plan, L)
-    h_last = gvd_filter(plan, plan.rho * L)
     for s in range(plan.n_steps):                     # 3.
-        h = h_first if s == 0 else h_mid
+        h = gvd_filter(plan, seg[s])
         v_spec = v_spec * h[:, None, :]               # 3a. GVD
         v = dft(v_spec, inverse=True) / n             # 3b. subband samples
         if plan.nlpr == "dual":                       # 3c-3e, eqs. (20)-(21)
@@ -245,7 +262,7 @@ def process_block(u: np.ndarray, plan: OraclePlan) -> np.ndarray:
             theta = coupled_fir(p, plan.coeffs[s])        # 3d. coupled FIR
             v = v * np.exp(-1j * theta)[:, None, :]       # 3e. rotation
         v_spec = nsb * dft(v)                         # 3f. back to frequency
-    v_spec = v_spec * h_last[:, None, :]              # 4.  final GVD
+    v_spec = v_spec * gvd_filter(plan, seg[-1])[:, None, :]   # 4.  final GVD
     return dft(mux(v_spec, plan), inverse=True) / n   # 5.  MUX + IDFT_N
 
 

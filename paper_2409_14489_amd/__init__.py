@@ -10,7 +10,7 @@ them without the library raises ImportError.
 _PUBLIC = {
     "LinkSpec": "plan", "Plan": "plan", "analytic_coeffs": "plan", "plan_check": "plan",
     "CbessfmError": "_lib", "EXPORTED": "_lib", "LIB_PATH": "_lib",
-    "CBESSFMFunction": "autograd", "cbessfm": "autograd",
+    "CBESSFMFunction": "autograd", "cbessfm": "autograd", "cbessfm_steps": "autograd",
     "Batch": "batch", "schedule": "batch", "autotune": "batch",
     "tie": "tied", "tie_expand": "tied", "tie_reduce": "tied", "fit_tied": "tied", "step_weights": "tied",
     "tied_half_taps": "tied", "ssfm_start": "tied", "analytic_rows": "tied", "tied_coeffs": "tied",

@@ -21,7 +21,7 @@ EXPORTED = (
     "cbessfm_batch_create", "cbessfm_batch_run", "cbessfm_batch_describe", "cbessfm_batch_status",
     "cbessfm_batch_destroy", "cbessfm_schedule", "cbessfm_autotune",
     "cbessfm_tie_expand", "cbessfm_tie_reduce", "cbessfm_step_weights", "cbessfm_tied_half_taps",
-    "cbessfm_complexity", "cbessfm_set_nlpr",
+    "cbessfm_complexity", "cbessfm_set_nlpr", "cbessfm_set_gvd_lengths", "cbessfm_backward_gvd",
 )
 
 TUNE_MEASURE = 1
@@ -117,6 +117,8 @@ def _load() -> ctypes.CDLL:
         "cbessfm_complexity": ([i32, dbl, i64, i64, i32, i32, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)],
                                ctypes.c_int),
         "cbessfm_set_nlpr": ([P, i32], ctypes.c_int),
+        "cbessfm_set_gvd_lengths": ([P, P, P], ctypes.c_int),
+        "cbessfm_backward_gvd": ([P, P, P, P, P, P, P, i64, i32, i32, P, sz, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

@@ -16,7 +16,10 @@
 //   dL/dC_s[i][l][tau] = sum_k theta_bar_i[k] p_l[(k - tau + Nc) mod N'],
 //   dL/drho = L sum_q phi_q [Im(conj(g_A1) A1) - Im(conj(g_B) B)],
 // with phi_q = 2 pi^2 beta2 f_q^2, A1 the first post-GVD spectrum and B the
-// spectrum after the last GVD.  The block's output stage (MUX, inverse size-N
+// spectrum after the last GVD.  With free dispersion segments (lengths d_j,
+// j = 0 .. N_st), dL/dd_j = -sum_q phi_q Im(conj(g_{A_j}) A_j), A_j the
+// spectrum after segment j (A_{N_st} = B); A_j for 0 < j < N_st is the DFT of
+// the stored v of step j + 1.  The block's output stage (MUX, inverse size-N
 // DFT) is adjoint to its input stage and vice versa, so both are reused.
 //
 // The reverse step needs v and theta of its forward step.  The forward sweep
@@ -192,6 +195,21 @@ __device__ __forceinline__ void coeff_grad(const TeamCtx& c, uint64_t* xrow, uns
   }
 }
 
+// Sum over the workgroup (NW waves) of one double per thread; the total is
+// returned to thread 0.  red: NW doubles of LDS.
+template <int NW>
+__device__ __forceinline__ double block_sum(double v, double* red, int t) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  __syncthreads();
+  if ((t & 63) == 0) red[t >> 6] = v;
+  __syncthreads();
+  double sum = 0.0;
+  if (t == 0)
+    for (int wv = 0; wv < NW; ++wv) sum += red[wv];
+  return sum;
+}
+
 // rho partial: sum over owned bins of phi_q L Im(conj(g) a), both polarisations.
 template <int N>
 __device__ __forceinline__ double rho_term(const double* __restrict__ phase_km, double L, int t,
@@ -259,7 +277,7 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdAr
     // stores (v, theta) at `dst` if given, and stops after theta if !tail.
     auto forward_step = [&](int s, float* dst, bool tail) {
       t = opaque_tid();
-      apply_diag<N, false>(x, y, (s == 0 ? a.tab.h_first : a.tab.h_mid) + (size_t)me * N, t);
+      apply_diag<N, false>(x, y, step_gvd(a.tab, s) + (size_t)me * N, t);
       fft<N, true>(x, y, lxy, tw, t);
       float p[RR], theta[RR];
       intensity<N>(x, y, p);
@@ -291,7 +309,15 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdAr
     gather_block<N, true>(go_x, go_x + T, blk, a.hop, a.n_ov, T, a.boundary, nsb, me, t, gx, gy);
     fft<N, false>(gx, gy, lxy, tw, t);
     polyphase_to_subband<N>(c, xs_b, rnd++, t, gx, gy);  // g_B
-    rho_acc -= rho_term<N>(phase_km, a.L, t, gx, gy, x, y);
+    {
+      const double tb = rho_term<N>(phase_km, 1.0, t, gx, gy, x, y);
+      rho_acc -= a.L * tb;
+      // dL/d(length of the last dispersion segment) = -sum phi Im(conj(g_B) B)
+      if (a.lpart != nullptr) {
+        const double tot = block_sum<NW>(-tb, rho_red, t);
+        if (t == 0) a.lpart[((size_t)item * nsb + me) * (a.steps + 1) + a.steps] = tot;
+      }
+    }
     apply_diag<N, true>(gx, gy, a.tab.h_last + (size_t)me * N, t);  // g_{S_Nst}
 
     // ---- C: reverse sweep, segment by segment
@@ -304,7 +330,7 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdAr
       }
       for (int s = s1; s > s0; --s) {  // 1-based step s
         t = opaque_tid();
-        const float2* hs = (s == 1 ? a.tab.h_first : a.tab.h_mid) + (size_t)me * N;
+        const float2* hs = step_gvd(a.tab, s - 1) + (size_t)me * N;
         float p[RR], theta[RR], tbar[RR];
         load_vtheta<N>(vt(s - 1 - s0), x, y, theta, t);  // v, theta of step s
         intensity<N>(x, y, p);
@@ -344,7 +370,18 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdAr
         if (s == 1) {                          // first GVD depends on rho
           load_state<N>(sp(0), x, y, t);
           apply_diag<N, false>(x, y, hs, t);  // A1
-          rho_acc += rho_term<N>(phase_km, a.L, t, gx, gy, x, y);
+          const double ta = rho_term<N>(phase_km, 1.0, t, gx, gy, x, y);
+          rho_acc += a.L * ta;
+          if (a.lpart != nullptr) {
+            const double tot = block_sum<NW>(-ta, rho_red, t);
+            if (t == 0) a.lpart[((size_t)item * nsb + me) * (a.steps + 1)] = tot;
+          }
+        } else if (a.lpart != nullptr) {
+          // A_s = DFT(v_s) / N' (v_s is the unscaled inverse DFT of A_s)
+          fft<N, false>(x, y, lxy, tw, t);
+          const double ta = rho_term<N>(phase_km, 1.0 / (double)N, t, gx, gy, x, y);
+          const double tot = block_sum<NW>(-ta, rho_red, t);
+          if (t == 0) a.lpart[((size_t)item * nsb + me) * (a.steps + 1) + (s - 1)] = tot;
         }
         apply_diag<N, true>(gx, gy, hs, t);  // g_{S_{s-1}}
       }
@@ -405,6 +442,22 @@ __global__ __launch_bounds__(kRedJ * kRedG) void reduce_items_kernel(const float
     __syncthreads();
   }
   if (g == 0 && j < per_item) out[j] = (float)buf[0][jj];
+}
+
+// out[j] = sum over k of part[k][j], k < n (items x members), for j < m: block j
+// sums a strided share per thread and adds the shares in a fixed tree.
+__global__ void reduce_len_kernel(const double* __restrict__ part, double* __restrict__ out, int n, int m) {
+  __shared__ double buf[256];
+  const int j = blockIdx.x;
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < n; k += 256) acc += part[(size_t)k * m + j];
+  buf[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) buf[threadIdx.x] += buf[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[j] = buf[0];
 }
 
 __global__ void reduce_rho_kernel(const double* __restrict__ part, float* __restrict__ out, int n) {
@@ -511,14 +564,15 @@ BwdLayout bwd_layout(const cbessfm_plan_t* p, long long T, int batch, int ck_eve
   L.vtheta_off = up(L.spec_off + sizeof(float2) * (size_t)L.n_teams * L.n_ck * nsb * 2 * p->Np);
   L.cpart_off = up(L.vtheta_off + sizeof(float) * (size_t)L.n_teams * L.k * nsb * 5 * p->Np);
   L.rpart_off = up(L.cpart_off + sizeof(float) * (size_t)L.n_items * p->steps * nsb * nsb * p->n_taps);
-  L.gin_off = up(L.rpart_off + sizeof(double) * (size_t)L.n_items * nsb);
+  L.lpart_off = up(L.rpart_off + sizeof(double) * (size_t)L.n_items * nsb);
+  L.gin_off = up(L.lpart_off + sizeof(double) * (size_t)L.n_items * nsb * (p->steps + 1));
   L.bytes = up(L.gin_off + sizeof(float2) * (size_t)L.n_items * 2 * p->N);
   return L;
 }
 
 int launch_backward(cbessfm_plan_t* p, const void* field_in, const void* grad_out, void* grad_in, float* grad_c,
-                    float* grad_rho, long long T, int batch, int ck_every, void* workspace, size_t ws_bytes,
-                    hipStream_t s) {
+                    float* grad_rho, double* grad_gvd, long long T, int batch, int ck_every, void* workspace,
+                    size_t ws_bytes, hipStream_t s) {
   const BwdLayout L = bwd_layout(p, T, batch, ck_every);
   if (ws_bytes < L.bytes) return CBESSFM_EWORKSPACE;
   char* ws = static_cast<char*>(workspace);
@@ -550,6 +604,7 @@ int launch_backward(cbessfm_plan_t* p, const void* field_in, const void* grad_ou
   a.vtheta = reinterpret_cast<float*>(ws + L.vtheta_off);
   a.cpart = reinterpret_cast<float*>(ws + L.cpart_off);
   a.rpart = reinterpret_cast<double*>(ws + L.rpart_off);
+  a.lpart = grad_gvd ? reinterpret_cast<double*>(ws + L.lpart_off) : nullptr;
   a.gin_blk = grad_in ? reinterpret_cast<float2*>(ws + L.gin_off) : nullptr;
   a.ctl.abort = p->d_abort;
   a.ctl.err = p->d_err;
@@ -572,6 +627,8 @@ int launch_backward(cbessfm_plan_t* p, const void* field_in, const void* grad_ou
   const int per_item = p->steps * a.n_sb * a.n_sb * p->n_taps;
   reduce_items_kernel<<<(per_item + kRedJ - 1) / kRedJ, kRedJ * kRedG, 0, s>>>(a.cpart, grad_c, a.n_items, per_item);
   reduce_rho_kernel<<<1, 256, 0, s>>>(a.rpart, grad_rho, a.n_items * a.n_sb);
+  if (grad_gvd)
+    reduce_len_kernel<<<p->steps + 1, 256, 0, s>>>(a.lpart, grad_gvd, a.n_items * a.n_sb, p->steps + 1);
   if (grad_in) {
     const long long total = (long long)batch * 2 * T;
     gather_gin_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(a.gin_blk, static_cast<float2*>(grad_in),

@@ -47,7 +47,7 @@ __device__ __forceinline__ void fwd_item(TeamCtx& c, const Inst& d, int sub, uns
   // ---- step loop (Fig. "scheme_CB-ESSFM"), spectra in subband order
   for (int s = 0; s < d.steps; ++s) {
     t = opaque_tid();
-    apply_diag<N, false>(x, y, (s == 0 ? d.tab.h_first : d.tab.h_mid) + (size_t)me * N, t);
+    apply_diag<N, false>(x, y, step_gvd(d.tab, s) + (size_t)me * N, t);
     fft<N, true>(x, y, lxy, tw, t);  // lowpass-equivalent subband samples
     float p[RR], theta[RR];
     intensity<N>(x, y, p);
@@ -177,6 +177,19 @@ __global__ void tables_kernel(const double* __restrict__ phase, const double* __
   h[2 * n + q] = round_pair_dev(c * inv_np, s * inv_np);
 }
 
+// Explicit dispersion segments: table j = exp(+j phi len[j]), scaled by 1 / N
+// for j = 0 (after the unscaled size-N input DFT) and 1 / N' otherwise.
+__global__ void gvd_tables_kernel(const double* __restrict__ phase, const double* __restrict__ len, int n_seg,
+                                  double inv_n, double inv_np, int n, float2* __restrict__ h) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)n_seg * n) return;
+  const int j = (int)(idx / n), q = (int)(idx - (long long)j * n);
+  const double scale = j == 0 ? inv_n : inv_np;
+  double sn, cs;
+  sincos(phase[q] * len[j], &sn, &cs);
+  h[idx] = round_pair_dev(cs * scale, sn * scale);
+}
+
 // dst[s][i][l][tau] = C[s][i][l][tau] (zero for tau >= n_taps);
 // dstt[s][l][i][tau] = C[s][i][l][n_taps - 1 - tau] (the adjoint's correlation);
 // dstd[s][i][l][tau] = C[s][i][l][tau] / 3 for l != i, 0 on the diagonal.
@@ -298,7 +311,8 @@ int occupancy_per_cu(int log_np, bool dual, int* blocks) {
 void fill_tables(const cbessfm_plan_t* p, Tables& tb) {
   tb.h_first = p->d_h;
   tb.h_mid = p->d_h + p->N;
-  tb.h_last = p->d_h + 2 * (size_t)p->N;
+  tb.h_last = p->d_h + (size_t)(p->gvd_explicit ? p->steps : 2) * p->N;
+  tb.h_stride = p->gvd_explicit ? p->N : 0;
   tb.tw = p->d_tw;
   tb.poly_tw = p->d_poly;
   tb.cpad = p->d_cpad;
@@ -360,6 +374,16 @@ int launch_pad_coeffs(cbessfm_plan_t* p, const float* src, hipStream_t s) {
   const int total = rows * p->tap_pad;
   pad_coeffs_kernel<<<(total + 255) / 256, 256, 0, s>>>(src, p->d_cpad, p->d_ctpad, p->d_cdpad, p->steps,
                                                        p->sb.n_sb, p->n_taps, p->tap_pad);
+  return hipGetLastError() == hipSuccess ? CBESSFM_OK : CBESSFM_EHIP;
+}
+
+int launch_gvd_tables(cbessfm_plan_t* p, const double* lengths, hipStream_t s) {
+  const int n_seg = p->steps + 1;
+  if (hipMemcpyAsync(p->d_len, lengths, sizeof(double) * n_seg, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return CBESSFM_EHIP;
+  const long long total = (long long)n_seg * p->N;
+  gvd_tables_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(p->d_phase, p->d_len, n_seg, 1.0 / (double)p->N,
+                                                                    1.0 / (double)p->Np, p->N, p->d_h);
   return hipGetLastError() == hipSuccess ? CBESSFM_OK : CBESSFM_EHIP;
 }
 

@@ -19,6 +19,7 @@ struct Tables {
   const float2* h_first;  // [N] exp(+j phi (1 - rho) L) / N,  phi = 2 pi^2 beta2 f^2, subband order
   const float2* h_mid;    // [N] exp(+j phi L) / N'
   const float2* h_last;   // [N] exp(+j phi rho L) / N'
+  int h_stride;           // 0: every middle step uses h_mid; N: step s (1-based, >= 2) uses h_mid + (s - 2) N
   const float2* tw;       // [N'] exp(-j 2 pi n / N')
   const float2* poly_tw;  // [n_sb][N'] exp(-j 2 pi i k / N)
   const float* cpad;      // [steps][n_sb][n_sb][tap_pad] applied coefficients, zero padded
@@ -104,6 +105,7 @@ struct BwdArgs {
   float* vtheta;        // [n_teams][ck_every][n_sb][5 N'] (v_x, v_y, theta) of a segment's steps
   float* cpart;         // [n_items][steps][n_sb][n_sb][n_taps]
   double* rpart;        // [n_items][n_sb]
+  double* lpart;        // [n_items][n_sb][steps + 1] dispersion-segment partials, or null
   float2* gin_blk;      // [n_items][2][N] or null
   XchgCtl ctl;
 };
@@ -111,7 +113,7 @@ struct BwdArgs {
 // Workspace layout of one adjoint call.
 struct BwdLayout {
   int k, n_ck, nblk, n_items, n_teams;
-  size_t spec_off, vtheta_off, cpart_off, rpart_off, gin_off, bytes;
+  size_t spec_off, vtheta_off, cpart_off, rpart_off, lpart_off, gin_off, bytes;
 };
 
 }  // namespace cbessfm
@@ -129,6 +131,7 @@ struct cbessfm_plan {
   int team_capacity;      // forward teams whose workgroups can all be resident at once
   int team_capacity_dual; // the same for the dual-polarisation forward kernel
   int nlpr;               // CBESSFM_NLPR_AVERAGED or CBESSFM_NLPR_DUAL_POL
+  int gvd_explicit;       // 1: dispersion segment lengths from d_len, else (1 - rho) L, L, ..., rho L
   int bwd_team_capacity;  // the same for the adjoint kernel
   int xchg_teams;         // teams the exchange buffers are sized for
   // device memory
@@ -141,6 +144,7 @@ struct cbessfm_plan {
   float* d_ctpad;     // transposed, tap-reversed padded copy (adjoint)
   float* d_cdpad;     // padded copy with zero diagonal, / 3 (dual-polarisation NLPR)
   double* d_rho;      // current split ratio
+  double* d_len;      // [steps + 1] explicit dispersion segment lengths, km
   uint64_t* d_xspec;  // tagged exchange words
   uint64_t* d_xp;
   uint64_t* d_xq;
@@ -156,13 +160,14 @@ int launch_forward(cbessfm_plan_t* p, const void* in, void* out, long long T, in
 int launch_tables(cbessfm_plan_t* p, hipStream_t s);
 int launch_pad_coeffs(cbessfm_plan_t* p, const float* src, hipStream_t s);
 int launch_copy_rho(cbessfm_plan_t* p, const float* src, hipStream_t s);
+int launch_gvd_tables(cbessfm_plan_t* p, const double* lengths, hipStream_t s);
 int occupancy_per_cu(int log_np, bool dual, int* blocks);
 int bwd_occupancy_per_cu(int log_np, int* blocks);
 void fill_tables(const cbessfm_plan_t* p, Tables& tb);
 BwdLayout bwd_layout(const cbessfm_plan_t* p, long long T, int batch, int ck_every);
 int launch_backward(cbessfm_plan_t* p, const void* field_in, const void* grad_out, void* grad_in, float* grad_c,
-                    float* grad_rho, long long T, int batch, int ck_every, void* workspace, size_t ws_bytes,
-                    hipStream_t s);
+                    float* grad_rho, double* grad_gvd, long long T, int batch, int ck_every, void* workspace,
+                    size_t ws_bytes, hipStream_t s);
 int threads_for(int log_np);
 bool stream_capturing(hipStream_t s);
 int batch_occupancy_per_cu(int log_np, int* blocks);

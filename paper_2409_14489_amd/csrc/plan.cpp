@@ -289,7 +289,7 @@ void cbessfm_destroy(cbessfm_plan_t* p) {
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(p->device);
   void* bufs[] = {p->d_phase, p->d_h,     p->d_tw, p->d_poly, p->d_c,     p->d_cpad,  p->d_ctpad, p->d_cdpad,
-                  p->d_rho,   p->d_xspec, p->d_xp, p->d_xq,   p->d_epoch, p->d_abort, p->d_err};
+                  p->d_rho,   p->d_len,   p->d_xspec, p->d_xp, p->d_xq, p->d_epoch, p->d_abort, p->d_err};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   (void)hipSetDevice(prev);
@@ -393,7 +393,7 @@ int cbessfm_plan(cbessfm_plan_t** out, const cbessfm_link* link, const cbessfm_s
     if (ok && hipMalloc(ptr, bytes) != hipSuccess) ok = false;
   };
   alloc((void**)&p->d_phase, sizeof(double) * N);
-  alloc((void**)&p->d_h, sizeof(float2) * 3 * N);
+  alloc((void**)&p->d_h, sizeof(float2) * (size_t)std::max(3, steps + 1) * N);
   alloc((void**)&p->d_tw, sizeof(float2) * Np);
   alloc((void**)&p->d_poly, sizeof(float2) * nsb * Np);
   alloc((void**)&p->d_c, sizeof(float) * crows * p->n_taps);
@@ -401,6 +401,7 @@ int cbessfm_plan(cbessfm_plan_t** out, const cbessfm_link* link, const cbessfm_s
   alloc((void**)&p->d_ctpad, sizeof(float) * crows * p->tap_pad);
   alloc((void**)&p->d_cdpad, sizeof(float) * crows * p->tap_pad);
   alloc((void**)&p->d_rho, sizeof(double));
+  alloc((void**)&p->d_len, sizeof(double) * (size_t)(steps + 1));
   alloc((void**)&p->d_xspec, xspec_bytes(p));
   alloc((void**)&p->d_xp, xp_bytes(p));
   alloc((void**)&p->d_xq, xp_bytes(p));
@@ -445,7 +446,17 @@ int cbessfm_set_coeffs(cbessfm_plan_t* p, const float* dev_c, const float* dev_r
     if (rc) return rc;
     rc = cbessfm::launch_tables(p, s);
     if (rc) return rc;
+    p->gvd_explicit = 0;
   }
+  return CBESSFM_OK;
+}
+
+int cbessfm_set_gvd_lengths(cbessfm_plan_t* p, const double* dev_lengths, void* stream) {
+  if (!p) return CBESSFM_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int rc = dev_lengths ? cbessfm::launch_gvd_tables(p, dev_lengths, s) : cbessfm::launch_tables(p, s);
+  if (rc) return rc;
+  p->gvd_explicit = dev_lengths ? 1 : 0;
   return CBESSFM_OK;
 }
 
@@ -454,6 +465,7 @@ int cbessfm_set_split_ratio(cbessfm_plan_t* p, double split_ratio, void* stream)
   if (!(split_ratio >= 0.0 && split_ratio <= 1.0)) return CBESSFM_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
   p->rho = split_ratio;
+  p->gvd_explicit = 0;
   // the value is staged through the plan-owned host copy, so wait for it
   if (hipMemcpyAsync(p->d_rho, &p->rho, sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
     return CBESSFM_EHIP;
@@ -527,9 +539,19 @@ int cbessfm_backward(cbessfm_plan_t* p, const void* field_in, const void* grad_o
   if (!p || !field_in || !grad_out || !grad_c || !grad_rho || !workspace || T < 1 || batch < 1 ||
       T >= (1LL << 31))
     return CBESSFM_EINVAL;
+  return cbessfm_backward_gvd(p, field_in, grad_out, grad_in, grad_c, grad_rho, nullptr, T, batch,
+                              checkpoint_every, workspace, workspace_bytes, stream);
+}
+
+int cbessfm_backward_gvd(cbessfm_plan_t* p, const void* field_in, const void* grad_out, void* grad_in,
+                         float* grad_c, float* grad_rho, double* grad_gvd, int64_t T, int32_t batch,
+                         int32_t checkpoint_every, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!p || !field_in || !grad_out || !grad_c || !grad_rho || !workspace || T < 1 || batch < 1 ||
+      T >= (1LL << 31))
+    return CBESSFM_EINVAL;
   if (p->nlpr != CBESSFM_NLPR_AVERAGED) return CBESSFM_EUNSUPPORTED;  // the adjoint covers eq. (15)
-  return cbessfm::launch_backward(p, field_in, grad_out, grad_in, grad_c, grad_rho, T, batch, checkpoint_every,
-                                  workspace, workspace_bytes, static_cast<hipStream_t>(stream));
+  return cbessfm::launch_backward(p, field_in, grad_out, grad_in, grad_c, grad_rho, grad_gvd, T, batch,
+                                  checkpoint_every, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

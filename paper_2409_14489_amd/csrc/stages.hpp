@@ -327,6 +327,11 @@ __device__ __forceinline__ void intensity(const float2 (&x)[FftShape<N>::RR], co
     p[o] = x[o].x * x[o].x + x[o].y * x[o].y + y[o].x * y[o].x + y[o].y * y[o].y;
 }
 
+// Dispersion table before the NLPR of step s (0-based).
+__device__ __forceinline__ const float2* step_gvd(const Tables& tb, int s) {
+  return s == 0 ? tb.h_first : tb.h_mid + (size_t)(s - 1) * tb.h_stride;
+}
+
 // Dual-polarisation NLPR (eqs. (20)-(21)): d = |x|^2 - |y|^2, the input of
 // the extra cross-band filter.
 template <int N>

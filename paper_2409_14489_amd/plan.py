@@ -170,6 +170,19 @@ class Plan:
         check(lib.cbessfm_set_nlpr(self._h, codes[mode]), "cbessfm_set_nlpr")
         self.nlpr = mode
 
+    def set_gvd_lengths(self, lengths: torch.Tensor | None, stream=None):
+        """Free dispersion segments: float64 CUDA tensor of steps + 1 lengths
+        (km) before, between and after the NLPRs; None returns to the uniform
+        steps with the current split ratio."""
+        if lengths is None:
+            check(lib.cbessfm_set_gvd_lengths(self._h, None, _stream_ptr(stream)), "cbessfm_set_gvd_lengths")
+            return
+        if not (lengths.is_cuda and lengths.dtype == torch.float64 and lengths.is_contiguous()
+                and lengths.numel() == self.steps + 1):
+            raise ValueError("lengths must be a contiguous float64 CUDA tensor of steps + 1 entries")
+        check(lib.cbessfm_set_gvd_lengths(self._h, ctypes.c_void_p(lengths.data_ptr()), _stream_ptr(stream)),
+              "cbessfm_set_gvd_lengths")
+
     def set_split_ratio(self, rho: float, stream=None):
         check(lib.cbessfm_set_split_ratio(self._h, float(rho), _stream_ptr(stream)), "cbessfm_set_split_ratio")
 
@@ -180,8 +193,13 @@ class Plan:
                                              ctypes.byref(out)), "cbessfm_backward_workspace")
         return out.value
 
+    def backward_gvd(self, field_in: torch.Tensor, grad_out: torch.Tensor, need_grad_in: bool = True,
+                     checkpoint_every: int = 1, workspace: torch.Tensor | None = None, stream=None):
+        """:meth:`backward` plus dL/d(dispersion segment lengths) [steps + 1]."""
+        return self.backward(field_in, grad_out, need_grad_in, checkpoint_every, workspace, stream, _gvd=True)
+
     def backward(self, field_in: torch.Tensor, grad_out: torch.Tensor, need_grad_in: bool = True,
-                 checkpoint_every: int = 1, workspace: torch.Tensor | None = None, stream=None):
+                 checkpoint_every: int = 1, workspace: torch.Tensor | None = None, stream=None, _gvd=False):
         """(grad_in or None, grad_c [steps][n_sb][n_sb][n_taps], grad_rho [1]) for the current
         coefficients and split ratio, given grad_out = dL/dRe(out) + j dL/dIm(out).
 
@@ -204,12 +222,16 @@ class Plan:
                              device=x.device)
         grad_rho = torch.empty(1, dtype=torch.float32, device=x.device)
         gi_ptr = ctypes.c_void_p(grad_in.data_ptr()) if grad_in is not None else ctypes.c_void_p(0)
-        check(lib.cbessfm_backward(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(g.data_ptr()), gi_ptr,
-                                   ctypes.c_void_p(grad_c.data_ptr()), ctypes.c_void_p(grad_rho.data_ptr()),
-                                   int(t_len), int(bsz), int(checkpoint_every),
-                                   ctypes.c_void_p(workspace.data_ptr()),
-                                   ctypes.c_size_t(workspace.numel() * workspace.element_size()),
-                                   _stream_ptr(stream)), "cbessfm_backward")
+        grad_gvd = torch.empty(self.steps + 1, dtype=torch.float64, device=x.device) if _gvd else None
+        gl_ptr = ctypes.c_void_p(grad_gvd.data_ptr()) if _gvd else ctypes.c_void_p(0)
+        check(lib.cbessfm_backward_gvd(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(g.data_ptr()),
+                                       gi_ptr, ctypes.c_void_p(grad_c.data_ptr()),
+                                       ctypes.c_void_p(grad_rho.data_ptr()), gl_ptr, int(t_len), int(bsz),
+                                       int(checkpoint_every), ctypes.c_void_p(workspace.data_ptr()),
+                                       ctypes.c_size_t(workspace.numel() * workspace.element_size()),
+                                       _stream_ptr(stream)), "cbessfm_backward")
+        if _gvd:
+            return grad_in, grad_c, grad_rho, grad_gvd
         return grad_in, grad_c, grad_rho
 
     def status(self) -> int:
