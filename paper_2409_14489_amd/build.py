@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libcbessfm.so")
 
-SOURCES = ["forward.hip", "backward.hip", "tied.hip", "plan.cpp", "batch.cpp"]
+SOURCES = ["forward.hip", "backward.hip", "stream.hip", "tied.hip", "plan.cpp", "batch.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -428,6 +428,7 @@ int cbessfm_batch_create(cbessfm_batch_t** out, const cbessfm_instance* inst, in
       return CBESSFM_EINVAL;
     if (a.plan->device != dev) return CBESSFM_EINVAL;
     if (a.plan->nlpr != CBESSFM_NLPR_AVERAGED) return CBESSFM_EUNSUPPORTED;  // batches run eq. (15)
+    if (a.plan->stream) return CBESSFM_EUNSUPPORTED;  // batches run the persistent kernels
     const size_t bytes = (size_t)a.batch * 2 * a.T * sizeof(float2);
     if (overlaps(a.field_in, bytes, a.field_out, bytes)) return CBESSFM_EINVAL;
     for (int j = 0; j < i; ++j) {

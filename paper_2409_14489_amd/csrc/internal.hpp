@@ -84,6 +84,34 @@ struct BatchArgs {
   XchgCtl ctl;
 };
 
+// Streaming forward of blocks larger than one CU holds (stream.hip): the
+// size-N' DFT is split into N1 = kStreamRow columns of N' / N1 samples and
+// N' / N1 rows of N1 samples.
+constexpr int kStreamRow = 4096;
+constexpr int kStreamMinLog = 14;
+constexpr int kStreamMaxLog = 17;
+constexpr size_t kStreamBudget = size_t(512) << 20;  // bytes of block state a plan keeps
+constexpr int kStreamMaxBlocks = 256;
+
+struct StreamWsb {
+  float2 w[kMaxSubbands];
+};
+
+// One wave of blocks of a streaming forward call.
+struct StreamArgs {
+  const float2* in;    // [batch][2][T]
+  float2* out;         // [batch][2][T]
+  int T, nblk;         // sequence length, blocks per batch entry
+  int item0, nb;       // first item (batch entry * nblk + block) of the wave, items in it
+  int n_sb, np, n2;    // subbands, N', N' / N1
+  int n_ov, hop, boundary;
+  float2* st;          // [nb][n_sb][2][N'] block state
+  float* pb;           // [nb][n_sb][N'] intensities
+  float* th;           // [nb][n_sb][N'] filtered phases
+  const float2* tw2;   // [N2][N1] exp(-j 2 pi n1 k2 / N')
+  const float2* twr;   // [N1] exp(-j 2 pi n / N1)
+};
+
 // Everything an adjoint launch needs.
 struct BwdArgs {
   const float2* in;    // [batch][2][T] forward input
@@ -135,10 +163,11 @@ struct cbessfm_plan {
   int bwd_team_capacity;  // the same for the adjoint kernel
   int xchg_teams;         // teams the exchange buffers are sized for
   // device memory
-  double* d_phase;    // [N] 2 pi^2 beta2 f^2 per km, subband order (FP64)
-  float2* d_h;        // [3][N]
-  float2* d_tw;       // [N']
-  float2* d_poly;     // [n_sb][N']
+  double* d_phase;    // [N] 2 pi^2 beta2 f^2 per km, subband order (FP64); streaming plans keep
+                      // each subband's N' entries in the permuted order of stream.hip
+  float2* d_h;        // [3][N] (same order as d_phase)
+  float2* d_tw;       // [N'] exp(-j 2 pi n / N'); streaming plans: [N2][N1] column twiddles, then [N1]
+  float2* d_poly;     // [n_sb][N'] (streaming plans: permuted order)
   float* d_c;         // [steps][n_sb][n_sb][n_taps] as given
   float* d_cpad;      // padded copy used by the kernels
   float* d_ctpad;     // transposed, tap-reversed padded copy (adjoint)
@@ -152,6 +181,12 @@ struct cbessfm_plan {
   unsigned* d_abort;  // sticky exchange-timeout word
   int* d_err;
   float2 wsb[cbessfm::kMaxSubbands];
+  // streaming forward (N' > 8192): block state of st_blocks blocks
+  int stream;
+  int st_blocks;
+  float2* d_st;
+  float* d_pb;
+  float* d_th;
 };
 
 namespace cbessfm {
@@ -173,4 +208,6 @@ bool stream_capturing(hipStream_t s);
 int batch_occupancy_per_cu(int log_np, int* blocks);
 int launch_batch(int log_np, const BatchArgs& a, int grid, hipStream_t s);
 void fill_inst(const cbessfm_plan_t* p, const void* in, void* out, long long T, int batch, Inst& d);
+// stream.hip
+int launch_stream_forward(cbessfm_plan_t* p, const void* in, void* out, long long T, int batch, hipStream_t s);
 }  // namespace cbessfm

@@ -43,7 +43,9 @@ int check_link(const cbessfm_link* link) {
 int check_layout(const cbessfm_subbands* sb) {
   if (!sb) return CBESSFM_EINVAL;
   if (sb->n_sb < 1 || sb->n_sb > kMaxSubbands) return CBESSFM_EINVAL;
-  if (!is_pow2(sb->block_sb) || sb->block_sb < 256 || sb->block_sb > 8192) return CBESSFM_EUNSUPPORTED;
+  if (!is_pow2(sb->block_sb) || sb->block_sb < 256 || sb->block_sb > (1 << cbessfm::kStreamMaxLog))
+    return CBESSFM_EUNSUPPORTED;
+  if (sb->block_sb > 8192 && sb->block_sb < (1 << cbessfm::kStreamMinLog)) return CBESSFM_EUNSUPPORTED;
   const long long n = (long long)sb->n_sb * sb->block_sb;
   if (sb->overlap < 0 || sb->overlap >= n || (sb->overlap & 1)) return CBESSFM_EINVAL;
   if (sb->boundary != 0 && sb->boundary != 1) return CBESSFM_EINVAL;
@@ -288,8 +290,9 @@ void cbessfm_destroy(cbessfm_plan_t* p) {
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(p->device);
-  void* bufs[] = {p->d_phase, p->d_h,     p->d_tw, p->d_poly, p->d_c,     p->d_cpad,  p->d_ctpad, p->d_cdpad,
-                  p->d_rho,   p->d_len,   p->d_xspec, p->d_xp, p->d_xq, p->d_epoch, p->d_abort, p->d_err};
+  void* bufs[] = {p->d_phase, p->d_h,     p->d_tw,    p->d_poly, p->d_c,     p->d_cpad,  p->d_ctpad,
+                  p->d_cdpad, p->d_rho,   p->d_len,   p->d_xspec, p->d_xp,  p->d_xq,    p->d_epoch,
+                  p->d_abort, p->d_err,   p->d_st,    p->d_pb,    p->d_th};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   (void)hipSetDevice(prev);
@@ -327,6 +330,15 @@ int cbessfm_plan(cbessfm_plan_t** out, const cbessfm_link* link, const cbessfm_s
     return CBESSFM_EHIP;
   }
   p->cu_count = prop.multiProcessorCount;
+  p->stream = p->log_np >= cbessfm::kStreamMinLog;
+  if (p->stream) {
+    // block state of as many blocks as the budget holds, up to a cap
+    const size_t per_block = (size_t)sb->n_sb * p->Np * (sizeof(float2) * 2 + sizeof(float) * 2);
+    p->st_blocks = (int)std::max<size_t>(1, std::min<size_t>(cbessfm::kStreamBudget / per_block,
+                                                              (size_t)cbessfm::kStreamMaxBlocks));
+    p->threads = cbessfm::kStreamRow / 8;
+    p->team_capacity = p->st_blocks;
+  } else {
   p->threads = cbessfm::threads_for(p->log_np);
   int per_cu = 0, per_cu_dual = 0;
   if (cbessfm::occupancy_per_cu(p->log_np, false, &per_cu) != CBESSFM_OK || per_cu < 1 ||
@@ -349,26 +361,47 @@ int cbessfm_plan(cbessfm_plan_t** out, const cbessfm_link* link, const cbessfm_s
     return CBESSFM_EUNSUPPORTED;
   }
   p->xchg_teams = std::max(std::max(p->team_capacity, p->team_capacity_dual), p->bwd_team_capacity);
+  }
   p->nlpr = CBESSFM_NLPR_AVERAGED;
 
   const int N = p->N, Np = p->Np, nsb = sb->n_sb;
   const size_t crows = (size_t)steps * nsb * nsb;
+  // Streaming plans hold spectra with bin k2 + N2 k1 of a subband at position
+  // k1 + N1 k2 (the order the four-step transform leaves them in); every
+  // per-bin table follows that order.
+  const int n1 = cbessfm::kStreamRow, n2 = p->stream ? Np / n1 : 1;
+  auto bin_of = [&](int pos) { return p->stream ? (pos % n1) * n2 + pos / n1 : pos; };
   // ---- host tables in FP64
   std::vector<double> phase(N);
   const double beta2 = link->beta2_ps2_km * 1e-24;
   for (int q = 0; q < N; ++q) {  // subband order: q' = i N' + j  <->  bin q' - N/2
-    const double f = (double)(q - N / 2) * link->sample_rate_hz / N;
+    const int qb = (q / Np) * Np + bin_of(q % Np);
+    const double f = (double)(qb - N / 2) * link->sample_rate_hz / N;
     phase[q] = 2.0 * kPi * kPi * beta2 * f * f;
   }
-  std::vector<float2> tw(Np), poly((size_t)nsb * Np);
-  for (int n = 0; n < Np; ++n) {
-    const double a = -2.0 * kPi * n / Np;
-    tw[n] = cbessfm::round_pair(std::cos(a), std::sin(a));
+  const int n_tw = p->stream ? Np + n1 : Np;
+  std::vector<float2> tw(n_tw), poly((size_t)nsb * Np);
+  if (p->stream) {
+    for (int k = 0; k < n2; ++k)  // column twiddles exp(-j 2 pi n1 k2 / N')
+      for (int j = 0; j < n1; ++j) {
+        const double a = -2.0 * kPi * (double)((long long)j * k % Np) / Np;
+        tw[(size_t)k * n1 + j] = cbessfm::round_pair(std::cos(a), std::sin(a));
+      }
+    for (int n = 0; n < n1; ++n) {  // row transform table
+      const double a = -2.0 * kPi * n / n1;
+      tw[(size_t)Np + n] = cbessfm::round_pair(std::cos(a), std::sin(a));
+    }
+  } else {
+    for (int n = 0; n < Np; ++n) {
+      const double a = -2.0 * kPi * n / Np;
+      tw[n] = cbessfm::round_pair(std::cos(a), std::sin(a));
+    }
   }
   for (int i = 0; i < nsb; ++i)
-    for (int k = 0; k < Np; ++k) {
+    for (int q = 0; q < Np; ++q) {
+      const int k = bin_of(q);
       const double a = -2.0 * kPi * (double)((long long)i * k % N) / N;
-      poly[(size_t)i * Np + k] = cbessfm::round_pair(std::cos(a), std::sin(a));
+      poly[(size_t)i * Np + q] = cbessfm::round_pair(std::cos(a), std::sin(a));
     }
   for (int a = 0; a < kMaxSubbands; ++a) {
     const double ang = -2.0 * kPi * a / nsb;
@@ -394,7 +427,7 @@ int cbessfm_plan(cbessfm_plan_t** out, const cbessfm_link* link, const cbessfm_s
   };
   alloc((void**)&p->d_phase, sizeof(double) * N);
   alloc((void**)&p->d_h, sizeof(float2) * (size_t)std::max(3, steps + 1) * N);
-  alloc((void**)&p->d_tw, sizeof(float2) * Np);
+  alloc((void**)&p->d_tw, sizeof(float2) * n_tw);
   alloc((void**)&p->d_poly, sizeof(float2) * nsb * Np);
   alloc((void**)&p->d_c, sizeof(float) * crows * p->n_taps);
   alloc((void**)&p->d_cpad, sizeof(float) * crows * p->tap_pad);
@@ -402,10 +435,17 @@ int cbessfm_plan(cbessfm_plan_t** out, const cbessfm_link* link, const cbessfm_s
   alloc((void**)&p->d_cdpad, sizeof(float) * crows * p->tap_pad);
   alloc((void**)&p->d_rho, sizeof(double));
   alloc((void**)&p->d_len, sizeof(double) * (size_t)(steps + 1));
-  alloc((void**)&p->d_xspec, xspec_bytes(p));
-  alloc((void**)&p->d_xp, xp_bytes(p));
-  alloc((void**)&p->d_xq, xp_bytes(p));
-  alloc((void**)&p->d_epoch, sizeof(unsigned) * p->xchg_teams);
+  if (p->stream) {
+    const size_t cells = (size_t)p->st_blocks * nsb * Np;
+    alloc((void**)&p->d_st, sizeof(float2) * 2 * cells);
+    alloc((void**)&p->d_pb, sizeof(float) * cells);
+    alloc((void**)&p->d_th, sizeof(float) * cells);
+  } else {
+    alloc((void**)&p->d_xspec, xspec_bytes(p));
+    alloc((void**)&p->d_xp, xp_bytes(p));
+    alloc((void**)&p->d_xq, xp_bytes(p));
+    alloc((void**)&p->d_epoch, sizeof(unsigned) * p->xchg_teams);
+  }
   alloc((void**)&p->d_abort, sizeof(unsigned));
   alloc((void**)&p->d_err, sizeof(int));
   if (!ok) {
@@ -413,16 +453,16 @@ int cbessfm_plan(cbessfm_plan_t** out, const cbessfm_link* link, const cbessfm_s
     return CBESSFM_ENOMEM;
   }
   bool hip_ok = hipMemcpy(p->d_phase, phase.data(), sizeof(double) * N, hipMemcpyHostToDevice) == hipSuccess &&
-                hipMemcpy(p->d_tw, tw.data(), sizeof(float2) * Np, hipMemcpyHostToDevice) == hipSuccess &&
+                hipMemcpy(p->d_tw, tw.data(), sizeof(float2) * n_tw, hipMemcpyHostToDevice) == hipSuccess &&
                 hipMemcpy(p->d_poly, poly.data(), sizeof(float2) * nsb * Np, hipMemcpyHostToDevice) == hipSuccess &&
                 hipMemcpy(p->d_c, c.data(), sizeof(float) * c.size(), hipMemcpyHostToDevice) == hipSuccess &&
                 hipMemcpy(p->d_rho, &split_ratio, sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
                 hipMemset(p->d_err, 0, sizeof(int)) == hipSuccess &&
                 hipMemset(p->d_abort, 0, sizeof(unsigned)) == hipSuccess &&
-                hipMemset(p->d_xspec, 0, xspec_bytes(p)) == hipSuccess &&
-                hipMemset(p->d_xp, 0, xp_bytes(p)) == hipSuccess &&
-                hipMemset(p->d_xq, 0, xp_bytes(p)) == hipSuccess &&
-                hipMemset(p->d_epoch, 0, sizeof(unsigned) * p->xchg_teams) == hipSuccess;
+                (p->stream || (hipMemset(p->d_xspec, 0, xspec_bytes(p)) == hipSuccess &&
+                               hipMemset(p->d_xp, 0, xp_bytes(p)) == hipSuccess &&
+                               hipMemset(p->d_xq, 0, xp_bytes(p)) == hipSuccess &&
+                               hipMemset(p->d_epoch, 0, sizeof(unsigned) * p->xchg_teams) == hipSuccess));
   if (!hip_ok || cbessfm::launch_tables(p, nullptr) || cbessfm::launch_pad_coeffs(p, p->d_c, nullptr) ||
       hipDeviceSynchronize() != hipSuccess) {
     cbessfm_destroy(p);
@@ -481,6 +521,8 @@ int cbessfm_run(cbessfm_plan_t* p, const void* field_in, void* field_out, int64_
   const char* b = static_cast<const char*>(field_out);
   const long long bytes = (long long)batch * 2 * T * 8;
   if (a < b + bytes && b < a + bytes) return CBESSFM_EINVAL;  // in and out must not overlap
+  if (p->stream)
+    return cbessfm::launch_stream_forward(p, field_in, field_out, T, batch, static_cast<hipStream_t>(stream));
   return cbessfm::launch_forward(p, field_in, field_out, T, batch, static_cast<hipStream_t>(stream));
 }
 
@@ -505,7 +547,7 @@ int cbessfm_status(cbessfm_plan_t* p) {
   if (hipSetDevice(p->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return CBESSFM_EHIP;
   int err = 0;
   if (hipMemcpy(&err, p->d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return CBESSFM_EHIP;
-  if (err) {
+  if (err && !p->stream) {
     // An exchange wait gave up.  Workgroups of that launch may have written
     // words with tags a later launch would reuse, so the exchange state is
     // reset along with the sticky words.
@@ -522,6 +564,7 @@ int cbessfm_status(cbessfm_plan_t* p) {
 
 int cbessfm_set_nlpr(cbessfm_plan_t* p, int32_t mode) {
   if (!p || (mode != CBESSFM_NLPR_AVERAGED && mode != CBESSFM_NLPR_DUAL_POL)) return CBESSFM_EINVAL;
+  if (p->stream && mode != CBESSFM_NLPR_AVERAGED) return CBESSFM_EUNSUPPORTED;  // streaming runs eq. (15)
   p->nlpr = mode;
   return CBESSFM_OK;
 }
@@ -529,6 +572,7 @@ int cbessfm_set_nlpr(cbessfm_plan_t* p, int32_t mode) {
 int cbessfm_backward_workspace(const cbessfm_plan_t* p, int64_t T, int32_t batch, int32_t checkpoint_every,
                                size_t* bytes) {
   if (!p || !bytes || T < 1 || batch < 1 || T >= (1LL << 31)) return CBESSFM_EINVAL;
+  if (p->stream) return CBESSFM_EUNSUPPORTED;
   *bytes = cbessfm::bwd_layout(p, T, batch, checkpoint_every).bytes;
   return CBESSFM_OK;
 }
@@ -549,7 +593,7 @@ int cbessfm_backward_gvd(cbessfm_plan_t* p, const void* field_in, const void* gr
   if (!p || !field_in || !grad_out || !grad_c || !grad_rho || !workspace || T < 1 || batch < 1 ||
       T >= (1LL << 31))
     return CBESSFM_EINVAL;
-  if (p->nlpr != CBESSFM_NLPR_AVERAGED) return CBESSFM_EUNSUPPORTED;  // the adjoint covers eq. (15)
+  if (p->nlpr != CBESSFM_NLPR_AVERAGED || p->stream) return CBESSFM_EUNSUPPORTED;  // the adjoint covers eq. (15)
   return cbessfm::launch_backward(p, field_in, grad_out, grad_in, grad_c, grad_rho, grad_gvd, T, batch,
                                   checkpoint_every, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
 }

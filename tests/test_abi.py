@@ -46,7 +46,10 @@ LINK = LinkSpec(n_spans=15, sample_rate_hz=640e9)
     (dict(n_sb=9), -1),
     (dict(block_sb=4000), -2),
     (dict(block_sb=128), -2),
-    (dict(block_sb=16384), -2),
+    (dict(block_sb=16384), 0),        # streaming path
+    (dict(block_sb=2 ** 17), 0),
+    (dict(block_sb=2 ** 18), -2),
+    (dict(block_sb=2 ** 17, overlap=5 * 2 ** 17), -1),
     (dict(overlap=3), -1),
     (dict(overlap=-2), -1),
     (dict(overlap=5 * 4096), -1),
