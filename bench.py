@@ -16,13 +16,20 @@ Two more legs are reported in the same line:
            oracle on one realisation;
   batched  64 uneven instances (1-5 channels, 5-40 spans, 1-40 steps, 2^12 -
            2^18 symbols per channel), N' / N_ov from the measured autotuner,
-           one graph-replayed batch against 64 separate launches.
+           one graph-replayed batch against 64 separate launches;
+  protocol the paper's tied coefficient fits and method comparison on the
+           central channel of a five-channel link;
+  longlink 5 channels, 2^20 symbols per channel, 40 x 80 km: the streaming
+           path (N' = 2^17, N_ov = 196608) over a sweep of 1 - 80 steps,
+           throughput, device-memory roofline, SNR against dispersion-only
+           compensation, sampled oracle parity.
 
 Options:
   --gpus N      only 1 is supported (one GPU per process and per box)
   --steps K     timed passes of the primary workload (default 200)
   --warmup W    untimed passes (default 20)
-  --legs L      comma list of fwd,grad,batched (default all)
+  --legs L      comma list of grad,batched,protocol,longlink (default all;
+                the primary forward always runs)
   --no-cpu      skip the oracle timing (and the full-size parity check)
   --copy-mib M  after timing, one plain device copy of M MiB (counter calibration)
 """
@@ -482,18 +489,145 @@ def leg_protocol(args):
         cands = [run_method("cb-essfm", link, train, test, rx, steps=st, n_sb=2, rho=r, n_taps=taps, **common)
                  for r in (0.1, 0.3, 0.5)]
         methods.append(max(cands, key=lambda m: m["snr_train_db"]))   # rho chosen on the training set
+    best15 = methods[-1]["rho"]
+    free = [run_method("cb-essfm-free", link, train, test, rx, steps=st, n_sb=2, rho=best15, n_taps=taps, **common)
+            for st in (15, 30)]
     vs_nsb = [run_method("cb-essfm", link, train, test, rx, steps=15, n_sb=n, rho=0.5, n_taps=min(taps, block // n),
                          **common) for n in (1, 2, 4, 8)]
     vs_rho = [run_method("cb-essfm", link, train, test, rx, steps=15, n_sb=2, rho=r, n_taps=taps, **common)
               for r in (0.0, 0.1, 0.2, 0.3, 0.4, 0.5)]
     t_fit = time.perf_counter() - t0
-    keep = ("method", "steps", "n_sb", "rho", "snr_test_db", "snr_train_db", "snr_start_test_db", "rm", "half_taps")
+    keep = ("method", "steps", "n_sb", "rho", "snr_test_db", "snr_train_db", "snr_start_test_db", "rm", "half_taps",
+            "snr_tied_test_db", "snr_tied_train_db", "gvd_km")
     trim = lambda rs: [{k: r[k] for k in keep if k in r} for r in rs]   # noqa: E731
     return {"workload": PROTO_WORKLOAD, "dbp_rate_hz": rate, "block": block, "overlap": d["n_overlap"],
             "train": "2 realisations (seeds 6000-6001)", "test": "2 realisations (seeds 6100-6101)",
             "fit": f"tied sequential protocol, Adam on the adjoint gradient, {args.proto_iters} iterations per row",
             "methods_vs_steps": trim(methods), "snr_vs_n_sb": trim(vs_nsb), "snr_vs_rho": trim(vs_rho),
+            "free_steps": trim(free),
             "data_generation_s": t_gen, "fits_s": t_fit}
+
+
+# ------------------------------------------------------------------ long link: streaming path, step sweep
+LONG_WORKLOAD = "5ch-64GBd-64QAM-2^20sym-40x80km"
+LONG_GEN_STEPS_PER_SPAN = 20   # forward-link simulator steps per span for the long-link field
+
+
+def stream_bytes_per_block(n_sb, n_sub, n_ov, steps, n_taps):
+    """Device-memory bytes one block moves through the streaming kernels, each
+    kernel reading and writing its operands once: per (subband, sample) cell
+    of 16 B (both polarisations) the row kernel reads and writes the cell,
+    the intensity kernel reads it and writes 4 B, the filter reads the
+    intensities (with its halo) and writes 4 B, the rotation kernel reads the
+    cell and 4 B and writes the cell; the block's input read and kept output
+    write, the forward/inverse block transforms and the two MUX/DEMUX passes
+    add the rest."""
+    n = n_sb * n_sub
+    nc = n_taps // 2
+    per_step = 32 + (16 + 4) + (4 * (1 + 2 * nc / 256) + 4) + (16 + 4 + 16)
+    head = 16 + 16 + 32 + (32 if n_sb > 1 else 0)                  # read input, column pass, row pass, DEMUX
+    tail = 32 + (32 + 32 if n_sb > 1 else 0) + 16 + 16 * (n - n_ov) / n
+    return n * (head + steps * per_step + tail)
+
+
+def leg_longlink(args):
+    """Five channels over 40 x 80 km (N' = 2^17 per subband, N_ov = 196608):
+    throughput, device-memory roofline and SNR against dispersion-only
+    compensation for each step count of the sweep, analytic coefficients;
+    sampled parity with the FP64 oracle at 5 and 80 steps."""
+    import numpy as np
+    import torch
+    from paper_2409_14489_amd import Plan, analytic_coeffs
+    from paper_2409_14489_amd.train import SymbolReceiver, phase_aligned_mse
+    from synth import workload
+
+    t0 = time.perf_counter()
+    x128, syms, w = workload(LONG_WORKLOAD, 5001, steps_per_span=LONG_GEN_STEPS_PER_SPAN)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    d, wdm, ch = w["dbp"], w["wdm"], w["ch"]
+    link = link_of(ch, wdm.sample_rate)
+    xin = x128.to(torch.complex64).contiguous()
+    del x128
+    t_len = xin.shape[-1]
+    yout = torch.empty_like(xin)
+    p_w = 1e-3 * 10 ** (wdm.power_dbm_per_channel / 10)
+    offsets = (np.arange(wdm.n_channels) - (wdm.n_channels - 1) / 2.0) * wdm.spacing
+    sym_t = torch.from_numpy(syms.astype(np.complex64)).cuda()
+
+    def snr_per_channel(y):
+        out = []
+        for c, off in enumerate(offsets):
+            rx = SymbolReceiver(t_len, wdm.sample_rate, wdm.baud, wdm.rolloff, p_w, offset_hz=float(off))
+            out.append(-10 * math.log10(float(phase_aligned_mse(rx(y)[None], sym_t[c][None]))))
+            del rx
+        return out
+
+    n2d = wdm.n_channels * 2 * wdm.n_symbols
+    stream = torch.cuda.current_stream()
+    reps = max(3, min(20, args.steps // 10))
+    rows = []
+    parity = None
+    for steps in (0,) + tuple(d["step_sweep"]):
+        edc = steps == 0
+        st = 1 if edc else steps
+        coeffs = (np.zeros((1, d["n_sb"], d["n_sb"], 1), np.float32) if edc else
+                  analytic_coeffs(link, d["n_sb"], st, d["rho"], d["n_taps"]).astype(np.float32))
+        plan = Plan(link, d["n_sb"], d["n_sub"], d["n_overlap"], st, d["rho"], coeffs=coeffs)
+        for _ in range(2):
+            plan.run(xin, out=yout)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            plan.run(xin, out=yout)
+        graph.replay()
+        run_s = timed_events(stream, graph.replay, reps)
+        if plan.status() != 0:
+            raise RuntimeError("device error flag set in the long-link run")
+        del graph
+        nblk = plan.n_blocks(t_len)
+        moved = stream_bytes_per_block(d["n_sb"], d["n_sub"], d["n_overlap"], st, coeffs.shape[-1]) * nblk
+        snr = snr_per_channel(yout)
+        row = {"steps": st, "method": "edc" if edc else "cb-essfm (analytic)", "ms_per_run": run_s * 1e3,
+               "value": n2d / run_s, "unit": "2D-symbols/s",
+               "hbm_roofline": {"bound": "hbm", "achieved": moved / run_s / 1e9, "peak": PEAK_HBM_GBS,
+                                "unit": "GB/s", "frac": moved / run_s / 1e9 / PEAK_HBM_GBS,
+                                "bytes_per_run": moved},
+               "min_bytes_frac": 2 * 2 * t_len * 8 / run_s / 1e9 / PEAK_HBM_GBS,
+               "snr_db_per_channel": snr, "snr_db_central": snr[len(snr) // 2]}
+        rows.append(row)
+        if not args.no_cpu and st in (5, 80) and not edc:
+            import oracle
+            x_host = xin.cpu().numpy().astype(np.complex128)
+            oplan = oracle_plan({**d, "n_steps": st}, wdm.sample_rate, ch.span_km * ch.n_spans / st, coeffs,
+                                ch.beta2_ps2_km)
+            pick = [0, nblk - 1] if st == 5 else [nblk // 2]
+            c0 = time.perf_counter()
+            p0 = time.process_time()
+            ref = oracle.run_blocks(x_host, oplan, pick)
+            cpu_s = time.perf_counter() - c0
+            proc_s = time.process_time() - p0
+            got = yout.cpu().numpy().astype(np.complex128)
+            num = den = 0.0
+            for b, r in ref.items():
+                seg = got[:, b * plan.hop:b * plan.hop + r.shape[-1]]
+                r = r[:, :seg.shape[-1]]
+                num += float(np.sum(np.abs(seg - r) ** 2))
+                den += float(np.sum(np.abs(r) ** 2))
+            per_blk_2d = plan.hop / (wdm.sample_rate / wdm.baud) * 2   # 2D symbols per kept hop
+            parity = parity or {}
+            parity[f"steps_{st}"] = {"blocks": pick, "rel_l2": (num / den) ** 0.5,
+                      "cpu_baseline": {"value": per_blk_2d * len(pick) / cpu_s, "unit": "2D-symbols/s",
+                                       "cores": max(1, round(proc_s / cpu_s)), "kind": "oracle",
+                                       "sample": f"{len(pick)} blocks of N = {plan.block}, {st} steps, "
+                                                 f"{cpu_s:.1f} s"}}
+        plan.close()
+    return {"workload": LONG_WORKLOAD, "T": t_len, "n_sb": d["n_sb"], "block_sb": d["n_sub"],
+            "overlap": d["n_overlap"], "n_taps": d["n_taps"], "split_ratio": d["rho"],
+            "kernels": "streaming forward (stream.hip), graph-replayed",
+            "data": f"seeded 5-channel field, 40 x 80 km Manakov link simulated on the device at "
+                    f"{LONG_GEN_STEPS_PER_SPAN} steps/span, ASE at NF {ch.nf_db:g} dB",
+            "coefficients": "analytic (the adjoint does not cover the streaming path)",
+            "sweep": rows, "parity_sampled": parity, "data_generation_s": t_gen}
 
 
 def main():
@@ -501,7 +635,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--legs", default="fwd,grad,batched,protocol")
+    ap.add_argument("--legs", default="fwd,grad,batched,protocol,longlink")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0)
     ap.add_argument("--proto-iters", type=int, default=60)
@@ -521,6 +655,8 @@ def main():
         result["batched"] = leg_batched(args)
     if "protocol" in legs:
         result["protocol"] = leg_protocol(args)
+    if "longlink" in legs:
+        result["longlink"] = leg_longlink(args)
     print(json.dumps(result), flush=True)
 
 

@@ -19,6 +19,7 @@ The received field is in sqrt(W).
 from __future__ import annotations
 
 from dataclasses import dataclass
+import math
 
 import numpy as np
 
@@ -183,3 +184,68 @@ def select_channel(field: np.ndarray, sample_rate: float, offset_hz: float, deci
     k = np.fft.fftfreq(t_out, d=1.0 / t_out).astype(np.int64)       # -t_out/2 .. t_out/2 - 1
     # a T-point DFT over a t_out-point inverse: the sample values need 1 / decim
     return np.fft.ifft(spec[..., (k + int(round(shift))) % t_len], axis=-1) / decim
+
+
+def received_field_torch(spec: WdmSpec, ch: ChannelSpec, seed: int, device="cuda"):
+    """The same recipe as ``received_field`` evaluated with torch on ``device``
+    in complex128, for records too long for the CPU generator (tens of
+    millions of samples over thousands of link steps).  Symbols come from the
+    same numpy generator; the ASE noise from a torch generator seeded with
+    ``seed`` on the device.  Returns (field (2, T) complex128 on the device,
+    symbols (n_ch, 2, n) numpy)."""
+    import torch
+    rng = rng_for(seed)
+    sps = spec.sample_rate / spec.baud
+    if abs(sps - round(sps)) > 1e-9:
+        raise ValueError("sample_rate must be an integer multiple of the baud rate")
+    sps = int(round(sps))
+    t_len = spec.n_symbols * sps
+    df = spec.sample_rate / t_len
+    syms = qam_symbols(spec.qam_order, (spec.n_channels, 2, spec.n_symbols), rng)
+    f = torch.fft.fftfreq(t_len, d=1.0 / spec.sample_rate, dtype=torch.float64, device=device)
+    af = f.abs()
+    f1, f2 = (1.0 - spec.rolloff) * spec.baud / 2.0, (1.0 + spec.rolloff) * spec.baud / 2.0
+    rrc = (af <= f1).to(torch.float64)
+    if spec.rolloff > 0:
+        mid = (af > f1) & (af <= f2)
+        rrc = torch.where(mid, torch.sqrt(0.5 * (1.0 + torch.cos(math.pi / (spec.rolloff * spec.baud) * (af - f1)))),
+                          rrc)
+    p_ch = 1e-3 * 10.0 ** (spec.power_dbm_per_channel / 10.0)
+    offsets = (np.arange(spec.n_channels) - (spec.n_channels - 1) / 2.0) * spec.spacing
+    q = torch.arange(t_len, device=device) % spec.n_symbols
+    field = torch.zeros((2, t_len), dtype=torch.complex128, device=device)
+    for c in range(spec.n_channels):
+        shift = offsets[c] / df
+        if abs(shift - round(shift)) > 1e-6:
+            raise ValueError("channel offset must fall on a DFT bin")
+        a_spec = torch.fft.fft(torch.from_numpy(syms[c]).to(device), dim=-1)
+        x = torch.fft.ifft(torch.roll(a_spec[:, q] * rrc, int(round(shift)), dims=-1), dim=-1)
+        x *= math.sqrt(p_ch / float(torch.mean(torch.sum(x.abs() ** 2, dim=0))))
+        field += x
+        del a_spec, x
+    if ch.n_spans < 1:
+        return field, syms
+    alpha = ch.alpha_db_km * np.log(10.0) / 10.0
+    beta2 = ch.beta2_ps2_km * 1e-24
+    dz = ch.span_km / ch.steps_per_span
+    half_lin = torch.exp(torch.complex(-alpha * dz / 4.0 * torch.ones_like(f), -2.0 * np.pi ** 2 * beta2 * f * f * (dz / 2.0)))
+    gain = np.exp(alpha * ch.span_km)
+    ase_var = (10.0 ** (ch.nf_db / 10.0) / 2.0) * PLANCK * NU0 * (gain - 1.0) * spec.sample_rate
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    u = field
+    for _ in range(ch.n_spans):
+        sp = torch.fft.fft(u, dim=-1)
+        for _ in range(ch.steps_per_span):
+            sp *= half_lin
+            u = torch.fft.ifft(sp, dim=-1)
+            pw = u.real ** 2 + u.imag ** 2
+            u *= torch.exp(-1j * ch.gamma_w_km * dz * pw.sum(dim=0))[None]
+            sp = torch.fft.fft(u, dim=-1)
+            sp *= half_lin
+        u = torch.fft.ifft(sp, dim=-1) * math.sqrt(gain)
+        del sp
+        if ch.ase:
+            noise = torch.randn(u.shape, dtype=torch.complex128, device=device, generator=gen)
+            u += math.sqrt(ase_var / 2.0) * math.sqrt(2.0) * noise   # randn complex has E|z|^2 = 1
+    return u, syms

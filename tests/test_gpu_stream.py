@@ -131,3 +131,25 @@ def test_stream_rejects_what_it_does_not_cover():
     with pytest.raises(CbessfmError):
         g.set_nlpr("dual")
     g.close()
+
+
+def test_stream_long_link_full_size_sampled():
+    """The long-link shape at full size: 5 subbands of N' = 2^17, N_ov = 196608,
+    T = 5 x 2^21 per polarisation (23 blocks), 21 taps, 80 steps over
+    40 x 80 km; one block (the last, ragged) against the oracle at 80 steps and
+    two blocks at 10 steps."""
+    power = 8e-3
+    n_sb, block_sb, n_ov, t_len = 5, 2 ** 17, 196608, 5 * 2 ** 21
+    x = random_field((2, t_len), 41, power_w=power)
+    for steps, blocks in ((10, [0, 11]), (80, [22])):
+        c = rand_coeffs(steps, n_sb, 21, 0.02, power, steps)
+        g = gpu_plan(n_sb, block_sb, n_ov, steps, 0.3, c, spans=40, rate=640e9)
+        assert g.n_blocks(t_len) == 23
+        y = run_gpu(g, x)
+        o = oracle_plan(n_sb, block_sb, n_ov, steps, 0.3, c, spans=40, rate=640e9)
+        for b, v in oracle.run_blocks(x, o, blocks).items():
+            seg = y[:, b * g.hop:b * g.hop + v.shape[-1]]
+            err = rel_l2(seg, v[:, :seg.shape[-1]])
+            print(f"{steps} steps, block {b}: rel L2 {err:.3e}")
+            assert err < TOL
+        g.close()
