@@ -9,6 +9,8 @@ Every method is a configuration of the CB-ESSFM plan:
 * OSSFM: the SSFM with that one coefficient fitted (Nc = 0);
 * ESSFM: one subband, rho = 0.5, 2 Nc + 1 taps from rule (iii), fitted;
 * CB-ESSFM: N_sb subbands, fitted rows, optimised rho;
+* CB-ESSFM with free steps: the tied fit, then every step's coefficients and
+  all dispersion segment lengths fitted jointly on the adjoint (Sec. V);
 * ideal DBP: the SSFM with many steps per span.
 
 Fits follow the tied protocol of Sec. III-B (``tied.fit_tied``) on training
@@ -27,7 +29,7 @@ import torch
 from ._lib import check, lib
 from .plan import LinkSpec, Plan, analytic_coeffs
 from .tied import fit_tied, ssfm_start, tied_coeffs, tied_half_taps
-from .train import SymbolReceiver, snr_db
+from .train import SymbolReceiver, fit_steps, snr_db, snr_db_steps
 
 CX_FREQ, CX_TIME = 0, 1
 
@@ -53,7 +55,8 @@ def _plan(link, n_sb, block_sb, overlap, steps, rho, n_taps):
 
 def run_method(method: str, link: LinkSpec, train, test, receiver: SymbolReceiver, *, steps: int = 1,
                n_sb: int = 1, block: int = 8192, overlap: int = 0, n_sps: float = 2.0, rho: float = 0.5,
-               n_taps: int = 1, iters_per_row: int = 60, lr: float = 2e-2, graph: bool = True) -> dict:
+               n_taps: int = 1, iters_per_row: int = 60, lr: float = 2e-2, graph: bool = True,
+               free_iters: int = 150, free_lr: float = 2e-3) -> dict:
     """SNR (on ``test``) and complexity of one method; ``train`` / ``test`` are
     (fields (B, 2, T), symbols (B, 2, n)) device tensors.  ``block`` is the
     full-field block N."""
@@ -80,7 +83,7 @@ def run_method(method: str, link: LinkSpec, train, test, receiver: SymbolReceive
         n_sb, rho = 1, 0.5
         half = tied_half_taps(link, 1, steps, n_taps)
         kind = ("time", int(half[0]))
-    elif method == "cb-essfm":
+    elif method in ("cb-essfm", "cb-essfm-free"):
         half = tied_half_taps(link, n_sb, steps, n_taps)
         kind = ("cb-essfm", 0)
     else:
@@ -101,6 +104,17 @@ def run_method(method: str, link: LinkSpec, train, test, receiver: SymbolReceive
             res.update(complexity("time", n_sps, block, overlap, steps, n_c=kind[1]))
         else:
             res.update(complexity("cb-essfm", n_sps, block, overlap, steps, n_sb=n_sb))
+        if method == "cb-essfm-free":
+            # then every step's coefficients and all dispersion segment lengths, jointly
+            step_km = link.length_km / steps
+            l0 = np.full(steps + 1, step_km)
+            l0[0], l0[-1] = (1.0 - rho) * step_km, rho * step_km
+            c_free, lengths, _ = fit_steps(plan, train[0], train[1], receiver, c, l0, iters=free_iters,
+                                           lr=free_lr, graph=graph)
+            res.update(snr_tied_test_db=res["snr_test_db"], snr_tied_train_db=res["snr_train_db"],
+                       snr_train_db=snr_db_steps(plan, c_free, lengths, train[0], train[1], receiver),
+                       snr_test_db=snr_db_steps(plan, c_free, lengths, test[0], test[1], receiver),
+                       gvd_km=[float(v) for v in lengths.cpu().numpy()])
     finally:
         plan.close()
     return res

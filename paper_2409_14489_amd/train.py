@@ -14,7 +14,7 @@ import math
 
 import torch
 
-from .autograd import cbessfm
+from .autograd import cbessfm, cbessfm_steps
 
 
 def rrc_amplitude(f: torch.Tensor, baud: float, rolloff: float) -> torch.Tensor:
@@ -152,4 +152,51 @@ def snr_db(plan, coeffs: torch.Tensor, rho, fields: torch.Tensor, symbols: torch
     rho_t = torch.as_tensor(rho, dtype=torch.float32, device=fields.device).reshape(())
     with torch.no_grad():
         mse = phase_aligned_mse(receiver(cbessfm(fields, coeffs.contiguous(), rho_t, plan)), symbols)
+    return -10.0 * math.log10(float(mse))
+
+
+def fit_steps(plan, fields: torch.Tensor, symbols: torch.Tensor, receiver: SymbolReceiver, coeffs0, lengths0,
+              iters: int = 150, lr: float = 2e-3, lr_lengths: float | None = None, fit_lengths: bool = True,
+              checkpoint_every: int = 1, graph: bool = False, warmup: int = 3):
+    """Joint fit of per-step coefficients and the N_st + 1 dispersion segment
+    lengths (the step-size distribution and split per step that Sec. V leaves
+    to future work).  The lengths are total * softmax(z), so they stay
+    positive and keep their sum; Adam on (C / scale) at ``lr`` and on z at
+    ``lr_lengths`` (default ``lr``).  The fit starts from a solution that is
+    already fitted, so it is kept only where it lowers the training loss:
+    if the final loss exceeds the starting one the start is returned.
+    Returns (coeffs, lengths (float64), losses)."""
+    dev = fields.device
+    c0 = torch.as_tensor(coeffs0, dtype=torch.float32, device=dev)
+    scale = c0.abs().max().clamp_min(1e-12)
+    u = (c0 / scale).clone().requires_grad_(True)
+    l0 = torch.as_tensor(lengths0, dtype=torch.float64, device=dev)
+    total = float(l0.sum())
+    z = torch.log(l0 / total).clone().requires_grad_(fit_lengths)
+
+    def loss_fn():
+        lengths = total * torch.softmax(z, 0)
+        y = cbessfm_steps(fields, (u * scale).contiguous(), lengths, plan, checkpoint_every)
+        return phase_aligned_mse(receiver(y), symbols)
+
+    groups = [{"params": [u], "lr": lr}]
+    if fit_lengths:
+        groups.append({"params": [z], "lr": lr if lr_lengths is None else lr_lengths})
+    losses = adam_loop(groups, loss_fn, iters, lr, graph=graph, warmup=warmup, device=dev)
+    c_fit, l_fit = (u * scale).detach(), (total * torch.softmax(z, 0)).detach()
+    with torch.no_grad():
+        start = phase_aligned_mse(receiver(cbessfm_steps(fields, c0.contiguous(), l0.contiguous(), plan)), symbols)
+        end = phase_aligned_mse(receiver(cbessfm_steps(fields, c_fit.contiguous(), l_fit.contiguous(), plan)),
+                                symbols)
+    if float(end) > float(start):
+        return c0.clone(), l0.clone(), losses
+    return c_fit, l_fit, losses
+
+
+def snr_db_steps(plan, coeffs: torch.Tensor, lengths: torch.Tensor, fields: torch.Tensor, symbols: torch.Tensor,
+                 receiver: SymbolReceiver) -> float:
+    """``snr_db`` with free dispersion segment lengths."""
+    with torch.no_grad():
+        mse = phase_aligned_mse(receiver(cbessfm_steps(fields, coeffs.contiguous(), lengths.contiguous(), plan)),
+                                symbols)
     return -10.0 * math.log10(float(mse))
