@@ -167,6 +167,7 @@ __global__ __launch_bounds__(kColThreads) void st_head_kernel(StreamArgs a) {
   const int first = frame_first(blk, a.hop, a.n_ov, T, a.boundary);
   const bool short_seq = T < nsb * NP;
   float2* base = a.st + ((size_t)w * nsb + ap) * 2 * NP;
+#pragma unroll 1
   for (int pol = 0; pol < 2; ++pol) {
     float2 v[N2];
 #pragma unroll
@@ -186,7 +187,7 @@ __global__ __launch_bounds__(kColThreads) void st_head_kernel(StreamArgs a) {
 // DFT, optional pointwise filter h (permuted order, subband i at i N'),
 // optional inverse size-N1 DFT.  blockIdx.x = i N2 + k2.
 template <bool FWD, bool GVD, bool INV>
-__global__ __launch_bounds__(kRowNT) void st_row_kernel(float2* __restrict__ st, const float2* __restrict__ h,
+__global__ __launch_bounds__(kRowNT, 4) void st_row_kernel(float2* __restrict__ st, const float2* __restrict__ h,
                                                         const float2* __restrict__ twr, int nsb, int n2,
                                                         int np) {
   __shared__ __align__(16) float4 lxy[FftShape<kRow>::LDS_C];
@@ -280,6 +281,7 @@ __global__ __launch_bounds__(kColThreads) void st_intensity_kernel(const float2*
   float p[N2];
 #pragma unroll
   for (int k = 0; k < N2; ++k) p[k] = 0.0f;
+#pragma unroll 1
   for (int pol = 0; pol < 2; ++pol) {
     float2 v[N2];
     load_col<N2>(st + (arr * 2 + pol) * NP, n1, v);
@@ -294,40 +296,67 @@ __global__ __launch_bounds__(kColThreads) void st_intensity_kernel(const float2*
 
 // Coupled filter of eq. (15), circular over N':
 //   theta_i[n] = sum_l sum_tau C_s[i][l][tau] p_l[(n - tau + nc) mod N'].
-// A workgroup filters 256 consecutive n of one block for every subband i; the
-// rows p_l with a halo of nc on each side are staged in LDS once.
+// A workgroup filters kFirOut consecutive n of one block for every subband i;
+// each thread takes kFirQ consecutive outputs.  The rows p_l, extended
+// circularly by tap_pad - 1 - nc on the left and nc on the right, are staged
+// in LDS once.  Taps go in chunks of 8 over the zero-padded coefficient rows
+// (uniform across the workgroup, so they are scalar loads of 8 words); for
+// each chunk a thread reads a window of kFirQ + 7 intensities and does
+// 8 kFirQ multiply-adds per output subband.
+constexpr int kFirQ = 4;
+constexpr int kFirOut = 256 * kFirQ;
+
 __global__ __launch_bounds__(256) void st_fir_kernel(const float* __restrict__ pb, float* __restrict__ th,
                                                      const float* __restrict__ cs, int nsb, int np, int nc,
-                                                     int n_taps, int tap_pad) {
-  constexpr int W = 256 + kMaxTaps - 1;
+                                                     int tap_pad) {
+  constexpr int W = kFirOut + 256;  // >= kFirOut + tap_pad - 1, tap_pad <= 256
   __shared__ float tile[kMaxSubbands][W];
-  const int n0 = blockIdx.x * 256;
+  const int n0 = blockIdx.x * kFirOut;
   const size_t arr0 = (size_t)blockIdx.y * nsb;
-  const int span = 256 + 2 * nc;
+  const int hl = tap_pad - 1 - nc;
+  const int span = kFirOut + tap_pad - 1;
   for (int l = 0; l < nsb; ++l) {
     const float* row = pb + (arr0 + l) * np;
     for (int j = threadIdx.x; j < span; j += 256) {
-      int q = n0 - nc + j;
+      int q = n0 - hl + j;
       q = q < 0 ? q + np : (q >= np ? q - np : q);
       tile[l][j] = row[q];
     }
   }
   __syncthreads();
   const int t = threadIdx.x;
-  float acc[kMaxSubbands];
+  float acc[kMaxSubbands][kFirQ];
 #pragma unroll
-  for (int i = 0; i < kMaxSubbands; ++i) acc[i] = 0.0f;
+  for (int i = 0; i < kMaxSubbands; ++i)
+#pragma unroll
+    for (int q = 0; q < kFirQ; ++q) acc[i][q] = 0.0f;
+  const int n_chunks = tap_pad / kTapChunk;
   for (int l = 0; l < nsb; ++l) {
-    for (int tau = 0; tau < n_taps; ++tau) {
-      const float v = tile[l][t - tau + 2 * nc];
+    const float* tl = tile[l] + t * kFirQ + tap_pad - 1 - (kTapChunk - 1);
+    for (int ch = 0; ch < n_chunks; ++ch) {
+      // taps tau = 8 ch + u use win[q + 7 - u] for output q
+      float win[kFirQ + kTapChunk - 1];
 #pragma unroll
-      for (int i = 0; i < kMaxSubbands; ++i)
-        if (i < nsb) acc[i] = fmaf(cs[((size_t)i * nsb + l) * tap_pad + tau], v, acc[i]);
+      for (int m = 0; m < kFirQ + kTapChunk - 1; ++m) win[m] = tl[m - kTapChunk * ch];
+#pragma unroll
+      for (int i = 0; i < kMaxSubbands; ++i) {
+        if (i < nsb) {
+          const float* ci = cs + ((size_t)i * nsb + l) * tap_pad + kTapChunk * ch;
+#pragma unroll
+          for (int u = 0; u < kTapChunk; ++u) {
+            const float cv = ci[u];
+#pragma unroll
+            for (int q = 0; q < kFirQ; ++q) acc[i][q] = fmaf(cv, win[q + kTapChunk - 1 - u], acc[i][q]);
+          }
+        }
+      }
     }
   }
 #pragma unroll
   for (int i = 0; i < kMaxSubbands; ++i)
-    if (i < nsb) th[(arr0 + i) * np + n0 + t] = acc[i];
+    if (i < nsb)
+      *reinterpret_cast<float4*>(th + (arr0 + i) * np + n0 + t * kFirQ) =
+          make_float4(acc[i][0], acc[i][1], acc[i][2], acc[i][3]);
 }
 
 // Rotation of eq. (3): inverse column pass, x, y *= exp(-j theta_i[n]),
@@ -345,6 +374,7 @@ __global__ __launch_bounds__(kColThreads) void st_rotate_kernel(float2* __restri
   const float* src = th + arr * NP + n1;
 #pragma unroll
   for (int k = 0; k < N2; ++k) theta[k] = src[kRow * k];
+#pragma unroll 1
   for (int pol = 0; pol < 2; ++pol) {
     float2* a = st + (arr * 2 + pol) * NP;
     float2 v[N2];
@@ -376,6 +406,7 @@ __global__ __launch_bounds__(kColThreads) void st_tail_kernel(StreamArgs a) {
   const int keep_lo = a.n_ov / 2, keep_hi = nsb * NP - a.n_ov / 2;
   float2* dx = a.out + (size_t)inst * 2 * T;
   const float2* base = a.st + ((size_t)w * nsb + ap) * 2 * NP;
+#pragma unroll 1
   for (int pol = 0; pol < 2; ++pol) {
     float2 v[N2];
     load_col<N2>(base + (size_t)pol * NP, n1, v);
@@ -426,8 +457,8 @@ int run_wave(const StreamArgs& a, const Tables& tb, const float* cpad, int steps
       ok = ok && row<true, true, true>(a, h, s);
     st_intensity_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(a.st, a.pb, a.tw2, nsb);
     ok = ok && ok_launch();
-    st_fir_kernel<<<dim3(a.np / 256, a.nb), 256, 0, s>>>(a.pb, a.th, cpad + (size_t)st * nsb * nsb * tap_pad, nsb,
-                                                         a.np, nc, n_taps, tap_pad);
+    st_fir_kernel<<<dim3(a.np / kFirOut, a.nb), 256, 0, s>>>(a.pb, a.th, cpad + (size_t)st * nsb * nsb * tap_pad,
+                                                             nsb, a.np, nc, tap_pad);
     ok = ok && ok_launch();
     st_rotate_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(a.st, a.th, a.tw2, nsb);
     ok = ok && ok_launch();
