@@ -74,7 +74,8 @@ typedef struct {
 /* Block and subband layout (Sec. III-A). */
 typedef struct {
   int32_t n_sb;      /* N_sb, 1..8 */
-  int32_t block_sb;  /* N' = N / N_sb, power of two in [256, 8192] */
+  int32_t block_sb;  /* N' = N / N_sb, power of two in [256, 8192] (one CU per
+                        subband block) or [2^14, 2^17] (streamed block state) */
   int32_t overlap;   /* N_ov, full-field samples, even, 0 <= N_ov < N */
   int32_t boundary;  /* 0: circular sequence; 1: zeros outside [0, T) */
 } cbessfm_subbands;
@@ -159,7 +160,14 @@ int cbessfm_backward_workspace(const cbessfm_plan_t* plan, int64_t T, int32_t ba
  * only the spectrum at the start of every k-th step is stored, and each
  * segment of k steps is recomputed once during the reverse sweep (less
  * workspace, about one more forward pass of work).  workspace: device, at
- * least cbessfm_backward_workspace() bytes.  Asynchronous on stream. */
+ * least cbessfm_backward_workspace() bytes.  Asynchronous on stream.
+ * Plans with N' >= 2^14 (streamed block state) run the same derivative as a
+ * sequence of per-stage kernels over waves of blocks; their workspace holds,
+ * per wave, the block state at every segment start and after every step of
+ * one segment, so it grows with steps / k + k.  Every checkpoint spacing
+ * gives the same result bit for bit.  Errors: CBESSFM_EINVAL (NULL required
+ * pointer, T or batch out of range), CBESSFM_EWORKSPACE, CBESSFM_EUNSUPPORTED
+ * (dual-polarisation NLPR plan), CBESSFM_EHIP. */
 int cbessfm_backward(cbessfm_plan_t* plan, const void* field_in, const void* grad_out,
                      void* grad_in, float* grad_c, float* grad_rho, int64_t T, int32_t batch,
                      int32_t checkpoint_every, void* workspace, size_t workspace_bytes,

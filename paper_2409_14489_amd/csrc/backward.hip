@@ -629,12 +629,18 @@ int launch_backward(cbessfm_plan_t* p, const void* field_in, const void* grad_ou
   reduce_rho_kernel<<<1, 256, 0, s>>>(a.rpart, grad_rho, a.n_items * a.n_sb);
   if (grad_gvd)
     reduce_len_kernel<<<p->steps + 1, 256, 0, s>>>(a.lpart, grad_gvd, a.n_items * a.n_sb, p->steps + 1);
-  if (grad_in) {
-    const long long total = (long long)batch * 2 * T;
-    gather_gin_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(a.gin_blk, static_cast<float2*>(grad_in),
-                                                                       (int)T, p->N, p->hop, p->sb.overlap, a.nblk,
-                                                                       batch, p->sb.boundary);
-  }
+  if (hipGetLastError() != hipSuccess) return CBESSFM_EHIP;
+  if (grad_in)
+    return launch_gather_gin(a.gin_blk, static_cast<float2*>(grad_in), T, p->N, p->hop, p->sb.overlap, a.nblk, batch,
+                             p->sb.boundary, s);
+  return CBESSFM_OK;
+}
+
+int launch_gather_gin(const float2* blk_g, float2* gin, long long T, int N, int hop, int n_ov, int nblk, int batch,
+                      int boundary, hipStream_t s) {
+  const long long total = (long long)batch * 2 * T;
+  gather_gin_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(blk_g, gin, (int)T, N, hop, n_ov, nblk, batch,
+                                                                     boundary);
   return hipGetLastError() == hipSuccess ? CBESSFM_OK : CBESSFM_EHIP;
 }
 

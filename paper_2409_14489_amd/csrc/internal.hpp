@@ -112,6 +112,16 @@ struct StreamArgs {
   const float2* twr;   // [N1] exp(-j 2 pi n / N1)
 };
 
+// Workspace layout of one streaming adjoint call (stream.hip): byte offsets
+// of its arrays; k steps per checkpoint segment, n_ck segments, waves of nb
+// blocks, `state` complex words per block state.
+struct StreamBwdLayout {
+  int k, n_ck, nblk, nb;
+  size_t state;
+  size_t ck_off, slot_off, work_off, g_off, theta_off, tbar_off, cpart_off, rpart_off, accc_off, acct_off, gin_off,
+      bytes;
+};
+
 // Everything an adjoint launch needs.
 struct BwdArgs {
   const float2* in;    // [batch][2][T] forward input
@@ -210,4 +220,12 @@ int launch_batch(int log_np, const BatchArgs& a, int grid, hipStream_t s);
 void fill_inst(const cbessfm_plan_t* p, const void* in, void* out, long long T, int batch, Inst& d);
 // stream.hip
 int launch_stream_forward(cbessfm_plan_t* p, const void* in, void* out, long long T, int batch, hipStream_t s);
+StreamBwdLayout stream_bwd_layout(const cbessfm_plan_t* p, long long T, int batch, int ck_every, bool gin);
+int launch_stream_backward(cbessfm_plan_t* p, const void* field_in, const void* grad_out, void* grad_in,
+                           float* grad_c, float* grad_rho, double* grad_gvd, long long T, int batch, int ck_every,
+                           void* workspace, size_t ws_bytes, hipStream_t s);
+// backward.hip: grad_in[inst][pol][pos] = sum of the block input cotangents
+// blk_g[inst nblk + b][pol][n] of every block position that reads pos.
+int launch_gather_gin(const float2* blk_g, float2* gin, long long T, int N, int hop, int n_ov, int nblk, int batch,
+                      int boundary, hipStream_t s);
 }  // namespace cbessfm

@@ -572,8 +572,8 @@ int cbessfm_set_nlpr(cbessfm_plan_t* p, int32_t mode) {
 int cbessfm_backward_workspace(const cbessfm_plan_t* p, int64_t T, int32_t batch, int32_t checkpoint_every,
                                size_t* bytes) {
   if (!p || !bytes || T < 1 || batch < 1 || T >= (1LL << 31)) return CBESSFM_EINVAL;
-  if (p->stream) return CBESSFM_EUNSUPPORTED;
-  *bytes = cbessfm::bwd_layout(p, T, batch, checkpoint_every).bytes;
+  *bytes = p->stream ? cbessfm::stream_bwd_layout(p, T, batch, checkpoint_every, true).bytes
+                     : cbessfm::bwd_layout(p, T, batch, checkpoint_every).bytes;
   return CBESSFM_OK;
 }
 
@@ -593,7 +593,11 @@ int cbessfm_backward_gvd(cbessfm_plan_t* p, const void* field_in, const void* gr
   if (!p || !field_in || !grad_out || !grad_c || !grad_rho || !workspace || T < 1 || batch < 1 ||
       T >= (1LL << 31))
     return CBESSFM_EINVAL;
-  if (p->nlpr != CBESSFM_NLPR_AVERAGED || p->stream) return CBESSFM_EUNSUPPORTED;  // the adjoint covers eq. (15)
+  if (p->nlpr != CBESSFM_NLPR_AVERAGED) return CBESSFM_EUNSUPPORTED;  // the adjoint covers eq. (15)
+  if (p->stream)
+    return cbessfm::launch_stream_backward(p, field_in, grad_out, grad_in, grad_c, grad_rho, grad_gvd, T, batch,
+                                           checkpoint_every, workspace, workspace_bytes,
+                                           static_cast<hipStream_t>(stream));
   return cbessfm::launch_backward(p, field_in, grad_out, grad_in, grad_c, grad_rho, grad_gvd, T, batch,
                                   checkpoint_every, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
 }

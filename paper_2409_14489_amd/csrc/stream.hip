@@ -184,17 +184,19 @@ __global__ __launch_bounds__(kColThreads) void st_head_kernel(StreamArgs a) {
 }
 
 // Row pass of row k2 of array (block w, subband i): optional forward size-N1
-// DFT, optional pointwise filter h (permuted order, subband i at i N'),
-// optional inverse size-N1 DFT.  blockIdx.x = i N2 + k2.
-template <bool FWD, bool GVD, bool INV>
-__global__ __launch_bounds__(kRowNT, 4) void st_row_kernel(float2* __restrict__ st, const float2* __restrict__ h,
+// DFT, optional pointwise filter h (permuted order, subband i at i N'; conj(h)
+// when CONJ, the adjoint's filter), optional inverse size-N1 DFT.  Reads src,
+// writes dst (the same array for an in-place pass).  blockIdx.x = i N2 + k2.
+template <bool FWD, bool GVD, bool INV, bool CONJ = false>
+__global__ __launch_bounds__(kRowNT, 4) void st_row_kernel(const float2* src, float2* dst,
+                                                        const float2* __restrict__ h,
                                                         const float2* __restrict__ twr, int nsb, int n2,
                                                         int np) {
   __shared__ __align__(16) float4 lxy[FftShape<kRow>::LDS_C];
   const int i = blockIdx.x / n2, k2 = blockIdx.x - (blockIdx.x / n2) * n2;
-  const int w = blockIdx.y;
-  float2* bx = st + ((size_t)w * nsb + i) * 2 * np + (size_t)k2 * kRow;
-  float2* by = bx + np;
+  const size_t off = ((size_t)blockIdx.y * nsb + i) * 2 * np + (size_t)k2 * kRow;
+  const float2* bx = src + off;
+  const float2* by = bx + np;
   const int t = threadIdx.x;
   float2 x[kRowRR], y[kRowRR];
 #pragma unroll
@@ -208,15 +210,17 @@ __global__ __launch_bounds__(kRowNT, 4) void st_row_kernel(float2* __restrict__ 
 #pragma unroll
     for (int o = 0; o < kRowRR; ++o) {
       const float2 hv = hr[t + kRowNT * o];
-      x[o] = cmul(x[o], hv);
-      y[o] = cmul(y[o], hv);
+      x[o] = CONJ ? cmulc(x[o], hv) : cmul(x[o], hv);
+      y[o] = CONJ ? cmulc(y[o], hv) : cmul(y[o], hv);
     }
   }
   if constexpr (INV) fft<kRow, true>(x, y, lxy, twr, t);
+  float2* ox = dst + off;
+  float2* oy = ox + np;
 #pragma unroll
   for (int o = 0; o < kRowRR; ++o) {
-    bx[t + kRowNT * o] = x[o];
-    by[t + kRowNT * o] = y[o];
+    ox[t + kRowNT * o] = x[o];
+    oy[t + kRowNT * o] = y[o];
   }
 }
 
@@ -359,10 +363,10 @@ __global__ __launch_bounds__(256) void st_fir_kernel(const float* __restrict__ p
           make_float4(acc[i][0], acc[i][1], acc[i][2], acc[i][3]);
 }
 
-// Rotation of eq. (3): inverse column pass, x, y *= exp(-j theta_i[n]),
-// forward column pass, in place.
+// Rotation of eq. (3): inverse column pass of src, x, y *= exp(-j theta_i[n]),
+// forward column pass into dst (the same array for an in-place pass).
 template <int N2>
-__global__ __launch_bounds__(kColThreads) void st_rotate_kernel(float2* __restrict__ st,
+__global__ __launch_bounds__(kColThreads) void st_rotate_kernel(const float2* src, float2* dst,
                                                                 const float* __restrict__ th,
                                                                 const float2* __restrict__ tw2, int nsb) {
   constexpr int NP = kRow * N2;
@@ -371,14 +375,13 @@ __global__ __launch_bounds__(kColThreads) void st_rotate_kernel(float2* __restri
   const int n1 = (blockIdx.x - i * GROUPS) * kColThreads + threadIdx.x;
   const size_t arr = (size_t)blockIdx.y * nsb + i;
   float theta[N2];
-  const float* src = th + arr * NP + n1;
+  const float* tsrc = th + arr * NP + n1;
 #pragma unroll
-  for (int k = 0; k < N2; ++k) theta[k] = src[kRow * k];
+  for (int k = 0; k < N2; ++k) theta[k] = tsrc[kRow * k];
 #pragma unroll 1
   for (int pol = 0; pol < 2; ++pol) {
-    float2* a = st + (arr * 2 + pol) * NP;
     float2 v[N2];
-    load_col<N2>(a, n1, v);
+    load_col<N2>(src + (arr * 2 + pol) * NP, n1, v);
     col_inverse<N2>(tw2, n1, v);
 #pragma unroll
     for (int k = 0; k < N2; ++k) {
@@ -387,7 +390,7 @@ __global__ __launch_bounds__(kColThreads) void st_rotate_kernel(float2* __restri
       v[k] = cmul(v[k], make_float2(cs, -sn));
     }
     col_forward<N2>(tw2, n1, v);
-    store_col<N2>(a, n1, v);
+    store_col<N2>(dst + (arr * 2 + pol) * NP, n1, v);
   }
 }
 
@@ -420,69 +423,442 @@ __global__ __launch_bounds__(kColThreads) void st_tail_kernel(StreamArgs a) {
   }
 }
 
+// ------------------------------------------------------------------ adjoint
+// Reverse-mode derivative of the streaming forward (the same map as the
+// persistent kernels differentiate).  Every linear stage is unitary up to a
+// real scale or is an unnormalised DFT, so its adjoint is a stage the
+// forward already has: the adjoint of a forward column pass is the inverse
+// column pass and vice versa, the adjoint of a row pass [F1, h, G1] is
+// [F1, conj(h), G1], the adjoint of the MUX is the DEMUX.  The adjoint state
+// G (the cotangent dL/dRe + j dL/dIm of the forward state) lives in arrays of
+// the same layout.
+
+// Adjoint of st_tail_kernel: the cotangent of every kept output sample goes
+// back to its block position ((-1)^n, polyphase split, forward column pass);
+// samples the block does not keep get zero.
+template <int N2>
+__global__ __launch_bounds__(kColThreads) void st_adj_tail_kernel(StreamArgs a, const float2* __restrict__ gout) {
+  constexpr int NP = kRow * N2;
+  const int g = blockIdx.x * kColThreads + threadIdx.x;
+  if (g >= a.n_sb * kRow) return;
+  const int w = blockIdx.y;
+  const int item = a.item0 + w;
+  const int inst = item / a.nblk, blk = item - inst * a.nblk;
+  const int nsb = a.n_sb, ap = g % nsb, n1 = g / nsb;
+  const int T = a.T;
+  const int keep_lo = a.n_ov / 2, keep_hi = nsb * NP - a.n_ov / 2;
+  const float2* src = gout + (size_t)inst * 2 * T;
+  float2* base = a.st + ((size_t)w * nsb + ap) * 2 * NP;
+#pragma unroll 1
+  for (int pol = 0; pol < 2; ++pol) {
+    float2 v[N2];
+#pragma unroll
+    for (int k = 0; k < N2; ++k) {
+      const int n = ap + nsb * (n1 + kRow * k);
+      const int pos = blk * a.hop + n - keep_lo;
+      float2 u = make_float2(0.f, 0.f);
+      if (n >= keep_lo && n < keep_hi && pos < T) u = src[(size_t)pol * T + pos];
+      v[k] = cscale(u, (n & 1) ? -1.0f : 1.0f);
+    }
+    col_forward<N2>(a.tw2, n1, v);
+    store_col<N2>(base + (size_t)pol * NP, n1, v);
+  }
+}
+
+// Adjoint of st_head_kernel up to the framing: inverse column pass of the
+// polyphase component, (-1)^n; writes the block's input cotangent
+// gin_blk[item][pol][n] for every block sample n (summed over overlapping
+// blocks afterwards).
+template <int N2>
+__global__ __launch_bounds__(kColThreads) void st_adj_head_kernel(StreamArgs a, float2* __restrict__ gin_blk) {
+  constexpr int NP = kRow * N2;
+  const int g = blockIdx.x * kColThreads + threadIdx.x;
+  if (g >= a.n_sb * kRow) return;
+  const int w = blockIdx.y;
+  const int item = a.item0 + w;
+  const int nsb = a.n_sb, ap = g % nsb, n1 = g / nsb;
+  const size_t N = (size_t)nsb * NP;
+  float2* dst = gin_blk + (size_t)item * 2 * N;
+  const float2* base = a.st + ((size_t)w * nsb + ap) * 2 * NP;
+#pragma unroll 1
+  for (int pol = 0; pol < 2; ++pol) {
+    float2 v[N2];
+    load_col<N2>(base + (size_t)pol * NP, n1, v);
+    col_inverse<N2>(a.tw2, n1, v);
+#pragma unroll
+    for (int k = 0; k < N2; ++k) {
+      const int n = ap + nsb * (n1 + kRow * k);
+      dst[(size_t)pol * N + n] = cscale(v[k], (n & 1) ? -1.0f : 1.0f);
+    }
+  }
+}
+
+// Phase cotangent of the rotation v' = v exp(-j theta) (eq. (3)):
+//   theta_bar_i[n] = sum_pol Im(conj(g'[n]) v'[n]),
+// with g' the inverse column pass of the adjoint state g (the adjoint of the
+// forward column pass) and v' = inverse column pass of the stored forward
+// state sf / N2 (the unnormalised pair multiplies by N2); also
+// p_i[n] = sum_pol |v'[n]|^2 (the rotation keeps |v|).
+template <int N2>
+__global__ __launch_bounds__(kColThreads) void st_adj_phase_kernel(const float2* __restrict__ g,
+                                                                   const float2* __restrict__ sf,
+                                                                   float* __restrict__ tbar, float* __restrict__ pb,
+                                                                   const float2* __restrict__ tw2, int nsb) {
+  constexpr int NP = kRow * N2;
+  constexpr int GROUPS = kRow / kColThreads;
+  const int i = blockIdx.x / GROUPS;
+  const int n1 = (blockIdx.x - i * GROUPS) * kColThreads + threadIdx.x;
+  const size_t arr = (size_t)blockIdx.y * nsb + i;
+  float p[N2], q[N2];
+#pragma unroll
+  for (int k = 0; k < N2; ++k) p[k] = q[k] = 0.0f;
+#pragma unroll 1
+  for (int pol = 0; pol < 2; ++pol) {
+    float2 vg[N2], vf[N2];
+    load_col<N2>(g + (arr * 2 + pol) * NP, n1, vg);
+    col_inverse<N2>(tw2, n1, vg);
+    load_col<N2>(sf + (arr * 2 + pol) * NP, n1, vf);
+    col_inverse<N2>(tw2, n1, vf);
+#pragma unroll
+    for (int k = 0; k < N2; ++k) {
+      vf[k] = cscale(vf[k], 1.0f / N2);
+      p[k] = fmaf(vf[k].x, vf[k].x, fmaf(vf[k].y, vf[k].y, p[k]));
+      q[k] = fmaf(vg[k].x, vf[k].y, fmaf(-vg[k].y, vf[k].x, q[k]));
+    }
+  }
+  float* dp = pb + arr * NP + n1;
+  float* dq = tbar + arr * NP + n1;
+#pragma unroll
+  for (int k = 0; k < N2; ++k) {
+    dp[kRow * k] = p[k];
+    dq[kRow * k] = q[k];
+  }
+}
+
+// Adjoint of the rotation and intensity: with v = v' exp(+j theta) (v' from
+// the stored state as in st_adj_phase_kernel),
+//   g_v = g' exp(+j theta) + 2 p_bar v,
+// then the forward column pass (the adjoint of the inverse column pass that
+// produced v), in place over g.
+template <int N2>
+__global__ __launch_bounds__(kColThreads) void st_adj_rotate_kernel(float2* __restrict__ g,
+                                                                    const float2* __restrict__ sf,
+                                                                    const float* __restrict__ th,
+                                                                    const float* __restrict__ pbar,
+                                                                    const float2* __restrict__ tw2, int nsb) {
+  constexpr int NP = kRow * N2;
+  constexpr int GROUPS = kRow / kColThreads;
+  const int i = blockIdx.x / GROUPS;
+  const int n1 = (blockIdx.x - i * GROUPS) * kColThreads + threadIdx.x;
+  const size_t arr = (size_t)blockIdx.y * nsb + i;
+  float theta[N2], p2[N2];
+#pragma unroll
+  for (int k = 0; k < N2; ++k) {
+    theta[k] = th[arr * NP + n1 + kRow * k];
+    p2[k] = 2.0f * pbar[arr * NP + n1 + kRow * k];
+  }
+#pragma unroll 1
+  for (int pol = 0; pol < 2; ++pol) {
+    float2 vg[N2], vf[N2];
+    load_col<N2>(g + (arr * 2 + pol) * NP, n1, vg);
+    col_inverse<N2>(tw2, n1, vg);
+    load_col<N2>(sf + (arr * 2 + pol) * NP, n1, vf);
+    col_inverse<N2>(tw2, n1, vf);
+#pragma unroll
+    for (int k = 0; k < N2; ++k) {
+      float sn, cs;
+      phase_sincos(theta[k], sn, cs);
+      const float2 e = make_float2(cs, sn);
+      const float2 v = cmul(cscale(vf[k], 1.0f / N2), e);
+      const float2 gr = cmul(vg[k], e);
+      vg[k] = make_float2(fmaf(p2[k], v.x, gr.x), fmaf(p2[k], v.y, gr.y));
+    }
+    col_forward<N2>(tw2, n1, vg);
+    store_col<N2>(g + (arr * 2 + pol) * NP, n1, vg);
+  }
+}
+
+// Coefficient cotangent of eq. (15) over one block's kCgOut consecutive
+// samples n0 .. n0 + kCgOut - 1:
+//   part[i][l][tau] = sum_n theta_bar_i[n] p_l[(n - tau + nc) mod N'].
+// Thread work items are (l, tau) pairs, each over a contiguous share of the
+// samples (pairs x shares <= 256); the shares are added in LDS in a fixed
+// order.  LDS (dynamic): p rows with a halo of nc each side, theta_bar rows,
+// the share partials.
+constexpr int kCgOut = 512;
+
+__host__ __device__ inline int cg_shares(int npair) {
+  int sh = 1;
+  while (2 * sh * npair <= 256 && sh < 64) sh *= 2;
+  return sh;
+}
+__host__ inline size_t cg_lds_bytes(int nsb, int n_taps) {
+  const int npair = nsb * n_taps;
+  const int sh = npair > 256 ? 1 : cg_shares(npair);
+  return sizeof(float) * ((size_t)nsb * (kCgOut + n_taps - 1) + (size_t)nsb * kCgOut +
+                          (npair > 256 ? 0 : (size_t)sh * npair * nsb));
+}
+
+__global__ __launch_bounds__(256) void st_cgrad_kernel(const float* __restrict__ tbar, const float* __restrict__ pb,
+                                                       float* __restrict__ part, int nsb, int np, int n_taps) {
+  extern __shared__ float cg_lds[];
+  const int nc = n_taps / 2;
+  const int pw = kCgOut + n_taps - 1;  // p row width
+  float* ptile = cg_lds;
+  float* ttile = cg_lds + (size_t)nsb * pw;
+  float* red = ttile + (size_t)nsb * kCgOut;
+  const int n0 = blockIdx.x * kCgOut;
+  const size_t arr0 = (size_t)blockIdx.y * nsb;
+  const int t = threadIdx.x;
+  for (int l = 0; l < nsb; ++l) {
+    const float* prow = pb + (arr0 + l) * np;
+    for (int j = t; j < pw; j += 256) {
+      int q = n0 - nc + j;
+      q = q < 0 ? q + np : (q >= np ? q - np : q);
+      ptile[l * pw + j] = prow[q];
+    }
+    const float* trow = tbar + (arr0 + l) * np + n0;
+    for (int j = t; j < kCgOut; j += 256) ttile[l * kCgOut + j] = trow[j];
+  }
+  __syncthreads();
+  const int npair = nsb * n_taps;
+  const bool wide = npair > 256;
+  const int sh = wide ? 1 : cg_shares(npair);
+  const int len = kCgOut / sh;
+  const size_t out0 = ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * nsb * npair;
+  const int items = wide ? npair : sh * npair;
+  for (int wi = t; wi < items; wi += 256) {
+    const int pr = wide ? wi : wi % npair;
+    const int sp = wide ? 0 : wi / npair;
+    const int l = pr / n_taps, tau = pr - (pr / n_taps) * n_taps;
+    // p_l[n - tau + nc] sits at ptile[l][n - n0 - tau + 2 nc]
+    const float* prow = ptile + l * pw + 2 * nc - tau;
+    float acc[kMaxSubbands];
+#pragma unroll
+    for (int i = 0; i < kMaxSubbands; ++i) acc[i] = 0.0f;
+    for (int n = sp * len; n < (sp + 1) * len; ++n) {
+      const float pv = prow[n];
+#pragma unroll
+      for (int i = 0; i < kMaxSubbands; ++i)
+        if (i < nsb) acc[i] = fmaf(ttile[i * kCgOut + n], pv, acc[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < kMaxSubbands; ++i) {
+      if (i < nsb) {
+        if (wide)
+          part[out0 + ((size_t)i * nsb + l) * n_taps + tau] = acc[i];
+        else
+          red[((size_t)sp * npair + pr) * nsb + i] = acc[i];
+      }
+    }
+  }
+  if (!wide) {
+    __syncthreads();
+    for (int j = t; j < npair * nsb; j += 256) {
+      const int pr = j / nsb, i = j - (j / nsb) * nsb;
+      float sum = 0.0f;
+      for (int sp = 0; sp < sh; ++sp) sum += red[((size_t)sp * npair + pr) * nsb + i];
+      const int l = pr / n_taps, tau = pr - (pr / n_taps) * n_taps;
+      part[out0 + ((size_t)i * nsb + l) * n_taps + tau] = sum;
+    }
+  }
+}
+
+// Adjoint row pass across a dispersion filter Y = h X, with the derivative of
+// h = exp(j phi dz) / scale in its segment length dz (Sec. III-C):
+//   part[row] = sum phi Im(conj(Gy) Y)   (dL/d dz = -sum over rows),
+// Gy = F1(g) (G_FWD) or g, X = F1(xs) (X_FWD) or xs.  STORE writes
+// conj(h) Gy back to g, through the inverse row DFT when INV.
+template <bool G_FWD, bool X_FWD, bool STORE, bool INV>
+__global__ __launch_bounds__(kRowNT, 2) void st_gvd_adj_kernel(float2* g, const float2* __restrict__ xs,
+                                                              const float2* __restrict__ h,
+                                                              const double* __restrict__ phase,
+                                                              double* __restrict__ part,
+                                                              const float2* __restrict__ twr, int nsb, int n2,
+                                                              int np) {
+  __shared__ __align__(16) float4 lxy[FftShape<kRow>::LDS_C];
+  __shared__ double red[kRowNT / 64];
+  const int i = blockIdx.x / n2, k2 = blockIdx.x - (blockIdx.x / n2) * n2;
+  const size_t off = ((size_t)blockIdx.y * nsb + i) * 2 * np + (size_t)k2 * kRow;
+  const int t = threadIdx.x;
+  float2 gx[kRowRR], gy[kRowRR];
+#pragma unroll
+  for (int o = 0; o < kRowRR; ++o) {
+    gx[o] = g[off + t + kRowNT * o];
+    gy[o] = g[off + np + t + kRowNT * o];
+  }
+  if constexpr (G_FWD) fft<kRow, false>(gx, gy, lxy, twr, t);
+  double acc = 0.0;
+  {
+    float2 x[kRowRR], y[kRowRR];
+#pragma unroll
+    for (int o = 0; o < kRowRR; ++o) {
+      x[o] = xs[off + t + kRowNT * o];
+      y[o] = xs[off + np + t + kRowNT * o];
+    }
+    if constexpr (X_FWD) fft<kRow, false>(x, y, lxy, twr, t);
+    const size_t hoff = (size_t)i * np + (size_t)k2 * kRow;
+#pragma unroll
+    for (int o = 0; o < kRowRR; ++o) {
+      const float2 hv = h[hoff + t + kRowNT * o];
+      const float2 yx = cmul(x[o], hv), yy = cmul(y[o], hv);
+      const float im = fmaf(gx[o].x, yx.y, fmaf(-gx[o].y, yx.x, fmaf(gy[o].x, yy.y, -gy[o].y * yy.x)));
+      acc += phase[hoff + t + kRowNT * o] * (double)im;
+      if constexpr (STORE) {
+        gx[o] = cmulc(gx[o], hv);
+        gy[o] = cmulc(gy[o], hv);
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+  if ((t & 63) == 0) red[t >> 6] = acc;
+  __syncthreads();
+  if (t == 0) {
+    double sum = 0.0;
+    for (int wv = 0; wv < kRowNT / 64; ++wv) sum += red[wv];
+    part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = sum;
+  }
+  if constexpr (STORE) {
+    if constexpr (INV) fft<kRow, true>(gx, gy, lxy, twr, t);
+#pragma unroll
+    for (int o = 0; o < kRowRR; ++o) {
+      g[off + t + kRowNT * o] = gx[o];
+      g[off + np + t + kRowNT * o] = gy[o];
+    }
+  }
+}
+
+// acc[j] += sum over r < n_rows of part[r][j] (FP64, fixed order: thread
+// (jj, g) of a 64 x 16 block sums rows g, g + 16, ...; the 16 sums are added
+// in a fixed tree).
+constexpr int kAccJ = 64, kAccG = 16;
+__global__ __launch_bounds__(kAccJ * kAccG) void st_acc_rows_kernel(const float* __restrict__ part, int n_rows,
+                                                                   int per_row, double* __restrict__ acc) {
+  __shared__ double buf[kAccG][kAccJ];
+  const int jj = threadIdx.x % kAccJ, gg = threadIdx.x / kAccJ;
+  const int j = blockIdx.x * kAccJ + jj;
+  double s = 0.0;
+  if (j < per_row)
+    for (int r = gg; r < n_rows; r += kAccG) s += (double)part[(size_t)r * per_row + j];
+  buf[gg][jj] = s;
+  __syncthreads();
+  for (int w = kAccG / 2; w > 0; w >>= 1) {
+    if (gg < w) buf[gg][jj] += buf[gg + w][jj];
+    __syncthreads();
+  }
+  if (gg == 0 && j < per_row) acc[j] += buf[0][jj];
+}
+
+// *acc += sum of part[0 .. n) (FP64, fixed order).
+__global__ __launch_bounds__(256) void st_acc_sum_kernel(const double* __restrict__ part, int n,
+                                                        double* __restrict__ acc) {
+  __shared__ double buf[256];
+  double s = 0.0;
+  for (int k = threadIdx.x; k < n; k += 256) s += part[k];
+  buf[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) buf[threadIdx.x] += buf[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *acc += buf[0];
+}
+
+__global__ void st_zero_kernel(double* __restrict__ p, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = 0.0;
+}
+
+// Final gradients: dL/dC from the FP64 sums; acc_t[j] = sum phi Im(conj(Gy) Y)
+// over dispersion segment j, so dL/d(length j) = -acc_t[j] and, with the
+// first and last segments (1 - rho) L and rho L,
+// dL/drho = L (acc_t[0] - acc_t[steps]).
+__global__ void st_bwd_finish_kernel(const double* __restrict__ acc_c, int n_c, const double* __restrict__ acc_t,
+                                     int steps, double L, float* __restrict__ grad_c, float* __restrict__ grad_rho,
+                                     double* __restrict__ grad_gvd) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n_c) grad_c[k] = (float)acc_c[k];
+  if (k == 0) *grad_rho = (float)(L * (acc_t[0] - acc_t[steps]));
+  if (grad_gvd != nullptr && k <= steps) grad_gvd[k] = -acc_t[k];
+}
+
 // ------------------------------------------------------------------ launcher
 namespace {
 
 bool ok_launch() { return hipGetLastError() == hipSuccess; }
 
-template <bool FWD, bool GVD, bool INV>
-bool row(const StreamArgs& a, const float2* h, hipStream_t s) {
-  st_row_kernel<FWD, GVD, INV><<<dim3(a.n_sb * a.n2, a.nb), kRowNT, 0, s>>>(a.st, h, a.twr, a.n_sb, a.n2, a.np);
+template <bool FWD, bool GVD, bool INV, bool CONJ = false>
+bool row(const StreamArgs& a, const float2* src, float2* dst, const float2* h, hipStream_t s) {
+  st_row_kernel<FWD, GVD, INV, CONJ>
+      <<<dim3(a.n_sb * a.n2, a.nb), kRowNT, 0, s>>>(src, dst, h, a.twr, a.n_sb, a.n2, a.np);
   return ok_launch();
+}
+
+const float2* step_filter(const Tables& tb, int st) {
+  return st == 0 ? tb.h_first : tb.h_mid + (size_t)(st - 1) * tb.h_stride;
+}
+
+// Block input: framing, polyphase column pass and (n_sb > 1) row pass and
+// DEMUX into the subband spectra, in a.st.
+template <int N2>
+bool wave_input(const StreamArgs& a, const Tables& tb, hipStream_t s) {
+  const int nsb = a.n_sb;
+  const dim3 col_grid((nsb * kRow + kColThreads - 1) / kColThreads, a.nb);
+  st_head_kernel<N2><<<col_grid, kColThreads, 0, s>>>(a);
+  bool ok = ok_launch();
+  if (nsb > 1) {
+    StreamWsb wsb;
+    for (int k = 0; k < kMaxSubbands; ++k) wsb.w[k] = tb.wsb[k];
+    ok = ok && row<true, false, false>(a, a.st, a.st, nullptr, s);
+    st_mix_kernel<false><<<dim3(a.np / 256, a.nb), 256, 0, s>>>(a.st, tb.poly_tw, wsb, nsb, a.np);
+    ok = ok && ok_launch();
+  }
+  return ok;
+}
+
+// Step st (0-based) from state src to state dst: row pass with the step's
+// dispersion filter into work, intensity, coupled filter into theta,
+// rotation from work into dst.
+template <int N2>
+bool wave_step(const StreamArgs& a, const Tables& tb, const float* cpad, int st, int n_taps, int tap_pad,
+               const float2* src, float2* work, float* theta, float2* dst, hipStream_t s) {
+  const int nsb = a.n_sb;
+  const dim3 sb_grid(nsb * (kRow / kColThreads), a.nb);
+  const float2* h = step_filter(tb, st);
+  bool ok = (st == 0 && nsb > 1) ? row<false, true, true>(a, src, work, h, s) : row<true, true, true>(a, src, work, h, s);
+  st_intensity_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(work, a.pb, a.tw2, nsb);
+  ok = ok && ok_launch();
+  st_fir_kernel<<<dim3(a.np / kFirOut, a.nb), 256, 0, s>>>(a.pb, theta, cpad + (size_t)st * nsb * nsb * tap_pad,
+                                                           nsb, a.np, n_taps / 2, tap_pad);
+  ok = ok && ok_launch();
+  st_rotate_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(work, dst, theta, a.tw2, nsb);
+  return ok && ok_launch();
 }
 
 template <int N2>
 int run_wave(const StreamArgs& a, const Tables& tb, const float* cpad, int steps, int n_taps, int tap_pad,
              hipStream_t s) {
   const int nsb = a.n_sb;
-  const dim3 col_grid((nsb * kRow + kColThreads - 1) / kColThreads, a.nb);
-  const dim3 sb_grid(nsb * (kRow / kColThreads), a.nb);
-  const dim3 mix_grid(a.np / 256, a.nb);
-  StreamWsb wsb;
-  for (int k = 0; k < kMaxSubbands; ++k) wsb.w[k] = tb.wsb[k];
-  const int nc = n_taps / 2;
-  bool ok = true;
-  st_head_kernel<N2><<<col_grid, kColThreads, 0, s>>>(a);
-  ok = ok && ok_launch();
+  bool ok = wave_input<N2>(a, tb, s);
+  for (int st = 0; st < steps && ok; ++st)
+    ok = wave_step<N2>(a, tb, cpad, st, n_taps, tap_pad, a.st, a.st, a.th, a.st, s);
   if (nsb > 1) {
-    ok = ok && row<true, false, false>(a, nullptr, s);
-    st_mix_kernel<false><<<mix_grid, 256, 0, s>>>(a.st, tb.poly_tw, wsb, nsb, a.np);
+    StreamWsb wsb;
+    for (int k = 0; k < kMaxSubbands; ++k) wsb.w[k] = tb.wsb[k];
+    ok = ok && row<true, true, false>(a, a.st, a.st, tb.h_last, s);
+    st_mix_kernel<true><<<dim3(a.np / 256, a.nb), 256, 0, s>>>(a.st, tb.poly_tw, wsb, nsb, a.np);
     ok = ok && ok_launch();
-  }
-  for (int st = 0; st < steps && ok; ++st) {
-    const float2* h = st == 0 ? tb.h_first : tb.h_mid + (size_t)(st - 1) * tb.h_stride;
-    if (st == 0 && nsb > 1)
-      ok = ok && row<false, true, true>(a, h, s);
-    else
-      ok = ok && row<true, true, true>(a, h, s);
-    st_intensity_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(a.st, a.pb, a.tw2, nsb);
-    ok = ok && ok_launch();
-    st_fir_kernel<<<dim3(a.np / kFirOut, a.nb), 256, 0, s>>>(a.pb, a.th, cpad + (size_t)st * nsb * nsb * tap_pad,
-                                                             nsb, a.np, nc, tap_pad);
-    ok = ok && ok_launch();
-    st_rotate_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(a.st, a.th, a.tw2, nsb);
-    ok = ok && ok_launch();
-  }
-  if (nsb > 1) {
-    ok = ok && row<true, true, false>(a, tb.h_last, s);
-    st_mix_kernel<true><<<mix_grid, 256, 0, s>>>(a.st, tb.poly_tw, wsb, nsb, a.np);
-    ok = ok && ok_launch();
-    ok = ok && row<false, false, true>(a, nullptr, s);
+    ok = ok && row<false, false, true>(a, a.st, a.st, nullptr, s);
   } else {
-    ok = ok && row<true, true, true>(a, tb.h_last, s);
+    ok = ok && row<true, true, true>(a, a.st, a.st, tb.h_last, s);
   }
-  st_tail_kernel<N2><<<col_grid, kColThreads, 0, s>>>(a);
+  st_tail_kernel<N2><<<dim3((nsb * kRow + kColThreads - 1) / kColThreads, a.nb), kColThreads, 0, s>>>(a);
   ok = ok && ok_launch();
   return ok ? CBESSFM_OK : CBESSFM_EHIP;
 }
 
-}  // namespace
-
-int launch_stream_forward(cbessfm_plan_t* p, const void* in, void* out, long long T, int batch, hipStream_t s) {
-  if (p->nlpr != CBESSFM_NLPR_AVERAGED) return CBESSFM_EUNSUPPORTED;
-  Tables tb;
-  fill_tables(p, tb);
-  StreamArgs a;
+void fill_stream_args(const cbessfm_plan_t* p, const void* in, void* out, long long T, StreamArgs& a) {
   a.in = static_cast<const float2*>(in);
   a.out = static_cast<float2*>(out);
   a.T = (int)T;
@@ -498,6 +874,16 @@ int launch_stream_forward(cbessfm_plan_t* p, const void* in, void* out, long lon
   a.th = p->d_th;
   a.tw2 = p->d_tw;
   a.twr = p->d_tw + p->Np;
+}
+
+}  // namespace
+
+int launch_stream_forward(cbessfm_plan_t* p, const void* in, void* out, long long T, int batch, hipStream_t s) {
+  if (p->nlpr != CBESSFM_NLPR_AVERAGED) return CBESSFM_EUNSUPPORTED;
+  Tables tb;
+  fill_tables(p, tb);
+  StreamArgs a;
+  fill_stream_args(p, in, out, T, a);
   const int items = batch * a.nblk;
   for (int item0 = 0; item0 < items; item0 += p->st_blocks) {
     a.item0 = item0;
@@ -512,6 +898,208 @@ int launch_stream_forward(cbessfm_plan_t* p, const void* in, void* out, long lon
     }
     if (rc) return rc;
   }
+  return CBESSFM_OK;
+}
+
+// ---- adjoint launcher
+// Workspace of one adjoint call, for waves of up to st_blocks blocks:
+//   ck     [n_ck] states S_{c k} at every segment start (S_0 = subband spectra)
+//   slot   [k] states after the steps of the current segment
+//   work   one state (row-pass output of a forward step)
+//   g      one state (the adjoint state)
+//   theta  [k] phase arrays of the segment's steps
+//   tbar   one phase-cotangent array
+//   cpart  coefficient partials of one step, [N' / kCgOut x nb][n_sb][n_sb][n_taps]
+//   rpart  dispersion-derivative partials of one row pass, [n_sb N2 nb]
+//   acc_c  FP64 [steps][n_sb][n_sb][n_taps], acc_t FP64 [steps + 1]
+//   gin    [batch nblk][2][N] block input cotangents (only with grad_in)
+// A state is [nb][n_sb][2][N'] complex; p and p_bar use the plan's arrays.
+StreamBwdLayout stream_bwd_layout(const cbessfm_plan_t* p, long long T, int batch, int ck_every, bool gin) {
+  StreamBwdLayout L;
+  L.k = (ck_every <= 1 || ck_every > p->steps) ? p->steps : ck_every;
+  L.n_ck = (p->steps + L.k - 1) / L.k;
+  L.nblk = (int)((T + p->hop - 1) / p->hop);
+  const int items = batch * L.nblk;
+  L.nb = items < p->st_blocks ? items : p->st_blocks;
+  const size_t nsb = p->sb.n_sb, cells = (size_t)L.nb * nsb * p->Np;
+  L.state = cells * 2;
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t sbytes = up(sizeof(float2) * L.state);
+  L.ck_off = 0;
+  L.slot_off = L.ck_off + sbytes * L.n_ck;
+  L.work_off = L.slot_off + sbytes * L.k;
+  L.g_off = L.work_off + sbytes;
+  L.theta_off = L.g_off + sbytes;
+  L.tbar_off = L.theta_off + up(sizeof(float) * cells) * L.k;
+  L.cpart_off = L.tbar_off + up(sizeof(float) * cells);
+  const size_t n_cg = (size_t)(p->Np / kCgOut) * L.nb;
+  L.rpart_off = L.cpart_off + up(sizeof(float) * n_cg * nsb * nsb * p->n_taps);
+  L.accc_off = L.rpart_off + up(sizeof(double) * nsb * (p->Np / kRow) * L.nb);
+  L.acct_off = L.accc_off + up(sizeof(double) * (size_t)p->steps * nsb * nsb * p->n_taps);
+  L.gin_off = L.acct_off + up(sizeof(double) * (size_t)(p->steps + 1));
+  L.bytes = L.gin_off + (gin ? up(sizeof(float2) * (size_t)items * 2 * p->N) : 0);
+  return L;
+}
+
+namespace {
+
+struct StreamBwdCall {
+  const cbessfm_plan_t* p;
+  Tables tb;
+  StreamBwdLayout L;
+  char* ws;
+  const float2* gout;
+  bool want_gvd, want_gin;
+  hipStream_t s;
+  size_t sbytes() const { return (sizeof(float2) * L.state + 255) & ~(size_t)255; }
+  size_t tbytes() const { return (sizeof(float) * (L.state / 2) + 255) & ~(size_t)255; }
+  float2* ck(int c) const { return reinterpret_cast<float2*>(ws + L.ck_off + sbytes() * c); }
+  // state after q steps
+  float2* S(int q) const {
+    if (q % L.k == 0 && q / L.k < L.n_ck) return ck(q / L.k);
+    return reinterpret_cast<float2*>(ws + L.slot_off + sbytes() * ((q - 1) % L.k));
+  }
+  float* TH(int st) const { return reinterpret_cast<float*>(ws + L.theta_off + tbytes() * (st % L.k)); }
+  float2* work() const { return reinterpret_cast<float2*>(ws + L.work_off); }
+  float2* G() const { return reinterpret_cast<float2*>(ws + L.g_off); }
+  float* tbar() const { return reinterpret_cast<float*>(ws + L.tbar_off); }
+  float* cpart() const { return reinterpret_cast<float*>(ws + L.cpart_off); }
+  double* rpart() const { return reinterpret_cast<double*>(ws + L.rpart_off); }
+  double* acc_c() const { return reinterpret_cast<double*>(ws + L.accc_off); }
+  double* acc_t() const { return reinterpret_cast<double*>(ws + L.acct_off); }
+  float2* gin() const { return reinterpret_cast<float2*>(ws + L.gin_off); }
+};
+
+// Row pass of the adjoint across filter h with the segment-length derivative
+// summed into acc_t[seg].
+template <bool G_FWD, bool X_FWD, bool STORE, bool INV>
+bool gvd_adj(const StreamBwdCall& c, const StreamArgs& a, const float2* xs, const float2* h, int seg) {
+  const dim3 grid(a.n_sb * a.n2, a.nb);
+  st_gvd_adj_kernel<G_FWD, X_FWD, STORE, INV>
+      <<<grid, kRowNT, 0, c.s>>>(c.G(), xs, h, c.p->d_phase, c.rpart(), a.twr, a.n_sb, a.n2, a.np);
+  bool ok = ok_launch();
+  st_acc_sum_kernel<<<1, 256, 0, c.s>>>(c.rpart(), (int)(grid.x * grid.y), c.acc_t() + seg);
+  return ok && ok_launch();
+}
+
+template <int N2>
+int bwd_wave(const StreamBwdCall& c, StreamArgs a) {
+  const cbessfm_plan_t* p = c.p;
+  const Tables& tb = c.tb;
+  const int nsb = a.n_sb, steps = p->steps, k = c.L.k;
+  const int n_taps = p->n_taps, tap_pad = p->tap_pad;
+  const int per_step = nsb * nsb * n_taps;
+  const dim3 col_grid((nsb * kRow + kColThreads - 1) / kColThreads, a.nb);
+  const dim3 sb_grid(nsb * (kRow / kColThreads), a.nb);
+  const dim3 cg_grid(a.np / kCgOut, a.nb);
+  const size_t cg_lds = cg_lds_bytes(nsb, n_taps);
+  StreamWsb wsb;
+  for (int j = 0; j < kMaxSubbands; ++j) wsb.w[j] = tb.wsb[j];
+  hipStream_t s = c.s;
+  // forward sweep: S_0 into ck(0), every step, segment starts kept
+  a.st = c.ck(0);
+  bool ok = wave_input<N2>(a, tb, s);
+  for (int st = 0; st < steps && ok; ++st)
+    ok = wave_step<N2>(a, tb, p->d_cpad, st, n_taps, tap_pad, c.S(st), c.work(), c.TH(st), c.S(st + 1), s);
+  // adjoint of the output stage, into G = dL/dS_steps
+  a.st = c.G();
+  st_adj_tail_kernel<N2><<<col_grid, kColThreads, 0, s>>>(a, c.gout);
+  ok = ok && ok_launch();
+  if (nsb > 1) {
+    ok = ok && row<true, false, false>(a, c.G(), c.G(), nullptr, s);
+    st_mix_kernel<false><<<dim3(a.np / 256, a.nb), 256, 0, s>>>(c.G(), tb.poly_tw, wsb, nsb, a.np);
+    ok = ok && ok_launch();
+    ok = ok && gvd_adj<false, true, true, true>(c, a, c.S(steps), tb.h_last, steps);
+  } else {
+    ok = ok && gvd_adj<true, true, true, true>(c, a, c.S(steps), tb.h_last, steps);
+  }
+  // reverse sweep, segment by segment
+  for (int seg = c.L.n_ck - 1; seg >= 0 && ok; --seg) {
+    const int s0 = seg * k, s1 = s0 + k < steps ? s0 + k : steps;
+    if (seg != c.L.n_ck - 1)
+      for (int st = s0; st < s1 && ok; ++st)
+        ok = wave_step<N2>(a, tb, p->d_cpad, st, n_taps, tap_pad, c.S(st), c.work(), c.TH(st), c.S(st + 1), s);
+    for (int st = s1 - 1; st >= s0 && ok; --st) {
+      st_adj_phase_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(c.G(), c.S(st + 1), c.tbar(), a.pb, a.tw2, nsb);
+      ok = ok && ok_launch();
+      // p_bar = C^T applied to theta_bar (transposed, tap-reversed rows)
+      st_fir_kernel<<<dim3(a.np / kFirOut, a.nb), 256, 0, s>>>(
+          c.tbar(), a.th, p->d_ctpad + (size_t)st * per_step / n_taps * tap_pad, nsb, a.np, n_taps / 2, tap_pad);
+      ok = ok && ok_launch();
+      st_cgrad_kernel<<<cg_grid, 256, cg_lds, s>>>(c.tbar(), a.pb, c.cpart(), nsb, a.np, n_taps);
+      ok = ok && ok_launch();
+      st_acc_rows_kernel<<<(per_step + kAccJ - 1) / kAccJ, kAccJ * kAccG, 0, s>>>(
+          c.cpart(), (int)(cg_grid.x * cg_grid.y), per_step, c.acc_c() + (size_t)st * per_step);
+      ok = ok && ok_launch();
+      st_adj_rotate_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(c.G(), c.S(st + 1), c.TH(st), a.th, a.tw2, nsb);
+      ok = ok && ok_launch();
+      if (st > 0) {
+        if (c.want_gvd)
+          ok = ok && gvd_adj<true, true, true, true>(c, a, c.S(st), step_filter(tb, st), st);
+        else
+          ok = ok && row<true, true, true, true>(a, c.G(), c.G(), step_filter(tb, st), s);
+      } else if (nsb > 1) {
+        ok = ok && gvd_adj<true, false, true, false>(c, a, c.S(0), tb.h_first, 0);
+      } else {
+        ok = ok && gvd_adj<true, true, true, true>(c, a, c.S(0), tb.h_first, 0);
+      }
+    }
+  }
+  // adjoint of the input stage: block input cotangents
+  if (c.want_gin && ok) {
+    if (nsb > 1) {
+      st_mix_kernel<true><<<dim3(a.np / 256, a.nb), 256, 0, s>>>(c.G(), tb.poly_tw, wsb, nsb, a.np);
+      ok = ok_launch() && row<false, false, true>(a, c.G(), c.G(), nullptr, s);
+    }
+    st_adj_head_kernel<N2><<<col_grid, kColThreads, 0, s>>>(a, c.gin());
+    ok = ok && ok_launch();
+  }
+  return ok ? CBESSFM_OK : CBESSFM_EHIP;
+}
+
+}  // namespace
+
+int launch_stream_backward(cbessfm_plan_t* p, const void* field_in, const void* grad_out, void* grad_in,
+                           float* grad_c, float* grad_rho, double* grad_gvd, long long T, int batch, int ck_every,
+                           void* workspace, size_t ws_bytes, hipStream_t s) {
+  if (p->nlpr != CBESSFM_NLPR_AVERAGED) return CBESSFM_EUNSUPPORTED;
+  StreamBwdCall c;
+  c.p = p;
+  fill_tables(p, c.tb);
+  c.L = stream_bwd_layout(p, T, batch, ck_every, grad_in != nullptr);
+  if (ws_bytes < c.L.bytes) return CBESSFM_EWORKSPACE;
+  c.ws = static_cast<char*>(workspace);
+  c.gout = static_cast<const float2*>(grad_out);
+  c.want_gvd = grad_gvd != nullptr;
+  c.want_gin = grad_in != nullptr;
+  c.s = s;
+  const int n_c = p->steps * p->sb.n_sb * p->sb.n_sb * p->n_taps;
+  st_zero_kernel<<<(n_c + 255) / 256, 256, 0, s>>>(c.acc_c(), n_c);
+  st_zero_kernel<<<(p->steps + 1 + 255) / 256, 256, 0, s>>>(c.acc_t(), p->steps + 1);
+  if (!ok_launch()) return CBESSFM_EHIP;
+  StreamArgs a;
+  fill_stream_args(p, field_in, nullptr, T, a);
+  const int items = batch * a.nblk;
+  for (int item0 = 0; item0 < items; item0 += p->st_blocks) {
+    a.item0 = item0;
+    a.nb = items - item0 < p->st_blocks ? items - item0 : p->st_blocks;
+    int rc;
+    switch (p->log_np) {
+      case 14: rc = bwd_wave<4>(c, a); break;
+      case 15: rc = bwd_wave<8>(c, a); break;
+      case 16: rc = bwd_wave<16>(c, a); break;
+      case 17: rc = bwd_wave<32>(c, a); break;
+      default: rc = CBESSFM_EUNSUPPORTED;
+    }
+    if (rc) return rc;
+  }
+  const int n_fin = n_c > p->steps + 1 ? n_c : p->steps + 1;
+  st_bwd_finish_kernel<<<(n_fin + 255) / 256, 256, 0, s>>>(c.acc_c(), n_c, c.acc_t(), p->steps, p->step_km, grad_c,
+                                                           grad_rho, grad_gvd);
+  if (!ok_launch()) return CBESSFM_EHIP;
+  if (grad_in != nullptr)
+    return launch_gather_gin(c.gin(), static_cast<float2*>(grad_in), T, p->N, p->hop, p->sb.overlap, a.nblk, batch,
+                             p->sb.boundary, s);
   return CBESSFM_OK;
 }
 

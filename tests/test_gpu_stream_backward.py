@@ -1,0 +1,95 @@
+"""Parity of the streaming adjoint (blocks of N' = 2^14 .. 2^17 per subband)
+with the FP64 gradient oracle, through the C ABI.
+
+Same bars as the persistent adjoint: relative L2 error <= 1e-5 for dL/dC and
+dL/dfield_in; dL/drho resolved to 1e-5 of the sum of its two terms (the
+derivative through the first and through the last dispersion segment, which
+nearly cancel); dL/d(segment lengths) to relative L2 1e-5.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle.grad import vjp, vjp_lengths
+from synth import random_field
+
+from test_gpu_backward import TOL, check_case, gpu_grads, plans, rand_coeffs, rel, rho_scale
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("n_sb,block_sb,steps,taps,ck", [
+    (1, 2 ** 14, 3, 5, 1), (2, 2 ** 14, 3, 7, 2), (3, 2 ** 15, 2, 9, 1), (1, 2 ** 16, 2, 11, 1),
+    (5, 2 ** 16, 2, 21, 1),
+])
+def test_stream_gradients_match_fp64_oracle(n_sb, block_sb, steps, taps, ck):
+    """Three blocks and a ragged tail."""
+    n = n_sb * block_sb
+    errs = check_case(n_sb, block_sb, n // 8, steps, 0.3, taps, 2 * n + 55, ck=ck, seed=n_sb * 7 + steps)
+    assert max(errs.values()) < TOL, errs
+
+
+def test_stream_gradients_long_link_block_shape():
+    """The long-link block shape: 5 subbands of N' = 2^17, N_ov = 196608,
+    21 taps, 640 GS/s, over three blocks (T = 2 hops + 1000), 2 steps over one
+    80 km span, every step stored."""
+    errs = check_case(5, 2 ** 17, 196608, 2, 0.3, 21, 2 * 458752 + 1000, ck=1, seed=3, need_in=True, phase=0.2,
+                      rate=640e9)
+    assert max(errs.values()) < TOL, errs
+
+
+def test_stream_gradients_wide_filter_zero_boundary_batch_short_sequence():
+    # 2 subbands x 255 taps: more (l, tau) pairs than threads per workgroup
+    errs = check_case(2, 2 ** 14, 4096, 2, 0.5, 255, 50000, seed=4, phase=0.3)
+    assert max(errs.values()) < TOL, errs
+    errs = check_case(2, 2 ** 14, 1024, 2, 0.6, 5, 40000, batch=3, boundary="zero", seed=5)
+    assert max(errs.values()) < TOL, errs
+    errs = check_case(3, 2 ** 14, 512, 2, 0.2, 5, 1001, seed=6)   # T < N: one block, wrapped
+    assert max(errs.values()) < TOL, errs
+
+
+@pytest.mark.parametrize("ck", [1, 2, 3, 5])
+def test_stream_checkpointing_is_exact_and_deterministic(ck):
+    """Recomputation repeats the forward kernels on the same inputs, so every
+    checkpoint spacing gives the same bits as storing every step; the
+    workspace shrinks with the spacing."""
+    power = 4e-3
+    x = random_field((2, 45000), 21, power_w=power)
+    gout = random_field((2, 45000), 22, power_w=1.0)
+    c = rand_coeffs(5, 2, 5, 0.5, power, 3)
+    g, o = plans(2, 2 ** 14, 4096, 5, 0.4, c, rate=128e9)
+    ref = gpu_grads(g, x, gout, ck=1)
+    got = gpu_grads(g, x, gout, ck=ck)
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]) and got[2] == ref[2]
+    ogi, ogc, ogr = vjp(x, o, gout)
+    assert rel(got[0], ogi) < TOL and rel(got[1], ogc) < TOL
+    assert abs(got[2] - ogr) < TOL * rho_scale(x, o, gout)
+    if 1 < ck < 5:
+        assert g.backward_workspace(45000, 1, ck) < g.backward_workspace(45000, 1, 1)
+    g.close()
+
+
+def test_stream_segment_length_gradients():
+    """dL/d(length of every dispersion segment) and dL/dC against the oracle,
+    with free (non-uniform) segment lengths and recomputation every 2 steps."""
+    import oracle
+    power = 4e-3
+    steps = 4
+    x = random_field((2, 60000), 31, power_w=power).astype(np.complex64)
+    gout = random_field((2, 60000), 32, power_w=1.0).astype(np.complex64)
+    c = rand_coeffs(steps, 2, 7, 0.5, power, 5)
+    g, _ = plans(2, 2 ** 14, 4096, steps, 0.3, c, rate=128e9)
+    lengths = np.array([9.0, 22.0, 17.0, 25.0, 7.0])
+    g.set_gvd_lengths(torch.from_numpy(lengths).cuda())
+    o = oracle.OraclePlan(-21.7e-24, 128e9, 80.0 / steps, steps, 0.3, 2, 2 * 2 ** 14, 4096,
+                          c.astype(np.float32).astype(np.float64), gvd_km=lengths)
+    xt = torch.from_numpy(x).cuda()
+    gt = torch.from_numpy(gout).cuda()
+    gi, gc, _, gl = g.backward_gvd(xt, gt, need_grad_in=True, checkpoint_every=2)
+    torch.cuda.synchronize()
+    assert g.status() == 0
+    ogi, ogc, ogl = vjp_lengths(x.astype(np.complex128), o, gout.astype(np.complex128))
+    errs = dict(c=rel(gc.cpu().numpy(), ogc), inp=rel(gi.cpu().numpy(), ogi), gvd=rel(gl.cpu().numpy(), ogl))
+    print(errs, gl.cpu().numpy(), ogl)
+    assert max(errs.values()) < TOL, errs
+    g.close()
