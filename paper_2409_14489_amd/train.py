@@ -122,7 +122,9 @@ def fit(plan, fields: torch.Tensor, symbols: torch.Tensor, receiver: SymbolRecei
     """Adam on (C, rho) for ``iters`` iterations; returns (coeffs, rho, losses).
 
     fields: complex64 (B, 2, T) on the device; symbols: complex64 (B, 2, n)
-    transmitted symbols of the channel the receiver selects.  The update of C
+    transmitted symbols of the channel the receiver selects (or sequences of
+    receivers and symbol tensors, one per channel: the loss is then the mean
+    of the channels' MSEs).  The update of C
     is taken in units of the initial coefficients' scale so that one learning
     rate suits every tap.  With ``graph`` the whole iteration (forward,
     loss, adjoint, Adam update) is recorded once in a HIP graph after
@@ -137,11 +139,20 @@ def fit(plan, fields: torch.Tensor, symbols: torch.Tensor, receiver: SymbolRecei
 
     def loss_fn():
         y = cbessfm(fields, (u * scale).contiguous(), rho, plan, checkpoint_every)
-        return phase_aligned_mse(receiver(y), symbols)
+        return receiver_mse(y, receiver, symbols)
 
     losses = adam_loop(params, loss_fn, iters, lr, graph=graph, warmup=warmup,
                        after_step=lambda: rho.clamp_(0.0, 1.0), device=fields.device)
     return (u * scale).detach(), rho.detach(), losses
+
+
+def receiver_mse(y: torch.Tensor, receiver, symbols) -> torch.Tensor:
+    """Phase-aligned MSE of one channel, or the mean over channels when
+    ``receiver`` and ``symbols`` are sequences (one receiver and one symbol
+    tensor per WDM channel)."""
+    if isinstance(receiver, (list, tuple)):
+        return sum(phase_aligned_mse(r(y), s) for r, s in zip(receiver, symbols)) / len(receiver)
+    return phase_aligned_mse(receiver(y), symbols)
 
 
 def snr_db(plan, coeffs: torch.Tensor, rho, fields: torch.Tensor, symbols: torch.Tensor,
@@ -151,7 +162,7 @@ def snr_db(plan, coeffs: torch.Tensor, rho, fields: torch.Tensor, symbols: torch
     -10 log10 of the phase-aligned mean square error (unit-energy symbols)."""
     rho_t = torch.as_tensor(rho, dtype=torch.float32, device=fields.device).reshape(())
     with torch.no_grad():
-        mse = phase_aligned_mse(receiver(cbessfm(fields, coeffs.contiguous(), rho_t, plan)), symbols)
+        mse = receiver_mse(cbessfm(fields, coeffs.contiguous(), rho_t, plan), receiver, symbols)
     return -10.0 * math.log10(float(mse))
 
 
