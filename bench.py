@@ -24,14 +24,16 @@ Two more legs are reported in the same line:
            throughput, device-memory roofline, SNR against dispersion-only
            compensation with analytic coefficients and with coefficients and
            split ratio fitted on the device (streaming adjoint, checkpoints
-           every 8 steps) on a second realisation, sampled oracle parity.
+           every 8 steps) on a second realisation, sampled oracle parity;
+  streamgrad the streaming forward and adjoint at the long-link block shape
+           (10 steps, 23 blocks, random field): times and workspace.
 
 Options:
   --gpus N      only 1 is supported (one GPU per process and per box)
   --steps K     timed passes of the primary workload (default 200)
   --warmup W    untimed passes (default 20)
-  --legs L      comma list of grad,batched,protocol,longlink (default all;
-                the primary forward always runs)
+  --legs L      comma list of grad,batched,protocol,longlink,streamgrad
+                (default all; the primary forward always runs)
   --no-cpu      skip the oracle timing (and the full-size parity check)
   --copy-mib M  after timing, one plain device copy of M MiB (counter calibration)
   --fit-iters F Adam iterations per step count of the long-link fit (default 20)
@@ -61,11 +63,16 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fwd_kernel_5ch_64GBd_2p16sym_15x8
 KERNEL_SOURCES = ["paper_2409_14489_amd/csrc/*.hip", "paper_2409_14489_amd/csrc/*.hpp",
                   "paper_2409_14489_amd/csrc/*.cpp", "include/cbessfm.h",
                   "paper_2409_14489_amd/build.py"]
+# the translation unit of the forward kernel the counters were taken on
+FWD_KERNEL_SOURCES = ["paper_2409_14489_amd/csrc/forward.hip", "paper_2409_14489_amd/csrc/fft_lds.hpp",
+                      "paper_2409_14489_amd/csrc/stages.hpp", "paper_2409_14489_amd/csrc/team.hpp",
+                      "paper_2409_14489_amd/csrc/sincos.hpp", "paper_2409_14489_amd/csrc/internal.hpp",
+                      "include/cbessfm.h", "paper_2409_14489_amd/build.py"]
 
 
-def kernel_source_digest() -> str:
+def kernel_source_digest(patterns=None) -> str:
     h = hashlib.sha256()
-    for pat in KERNEL_SOURCES:
+    for pat in patterns or KERNEL_SOURCES:
         for f in sorted(glob.glob(os.path.join(ROOT, pat))):
             h.update(os.path.relpath(f, ROOT).encode())
             with open(f, "rb") as fh:
@@ -75,7 +82,7 @@ def kernel_source_digest() -> str:
 
 def measured_traffic():
     """HBM bytes per launch from the committed counter summary, if it was taken
-    on the kernel sources as they are now; else None."""
+    on the forward kernel's sources as they are now; else None."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -83,7 +90,7 @@ def measured_traffic():
         if ":" in line and line.strip().startswith("- "):
             k, v = line.strip()[2:].split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256") != kernel_source_digest():
+    if kv.get("fwd_kernel_source_sha256") != kernel_source_digest(FWD_KERNEL_SOURCES):
         return None
     try:
         return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
@@ -208,7 +215,8 @@ def leg_forward(args):
                    "overlap": d["n_overlap"], "steps": d["n_steps"], "split_ratio": d["rho"],
                    "n_taps": d["n_taps"], "blocks": nblk, "kernel": "cbessfm::fwd_kernel<12>",
                    "threads_per_group": plan.info().threads_per_group,
-                   "kernel_source_sha256": kernel_source_digest()},
+                   "kernel_source_sha256": kernel_source_digest(),
+                   "fwd_kernel_source_sha256": kernel_source_digest(FWD_KERNEL_SOURCES)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "flops_per_launch": flops, "kernel_ms": kernel_s * 1e3},
@@ -679,12 +687,48 @@ def leg_longlink(args):
             "sweep": rows, "fit_memory": memory, "parity_sampled": parity, "data_generation_s": t_gen}
 
 
+def leg_streamgrad(args):
+    """Streaming forward and adjoint at the long-link block shape (5 subbands
+    of N' = 2^17, N_ov = 196608, 21 analytic taps, 40 x 80 km in 10 steps) on
+    a seeded complex Gaussian field of 23 blocks: HIP-event times of the
+    forward and of the adjoint with recomputation every 8 steps (which also
+    runs the forward sweep), and the adjoint's workspace."""
+    import numpy as np
+    import torch
+    from paper_2409_14489_amd import LinkSpec, Plan, analytic_coeffs
+
+    steps, ck = 10, 8
+    link = LinkSpec(beta2_ps2_km=-21.7, n_spans=40, span_km=80.0, sample_rate_hz=640e9)
+    c = analytic_coeffs(link, 5, steps, 0.3, 21).astype(np.float32)
+    plan = Plan(link, 5, 2 ** 17, 196608, steps, 0.3, coeffs=c)
+    t_len = 5 * 2 ** 21
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1)
+    x = (torch.randn((2, t_len), dtype=torch.complex64, device="cuda", generator=gen) * 0.05).contiguous()
+    go = torch.randn((2, t_len), dtype=torch.complex64, device="cuda", generator=gen).contiguous()
+    y = plan.run(x)
+    ws = torch.empty(plan.backward_workspace(t_len, 1, ck), dtype=torch.uint8, device="cuda")
+    plan.backward(x, go, need_grad_in=False, checkpoint_every=ck, workspace=ws)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    fwd_s = timed_events(stream, lambda: plan.run(x, out=y), 5)
+    bwd_s = timed_events(stream, lambda: plan.backward(x, go, need_grad_in=False, checkpoint_every=ck,
+                                                        workspace=ws), 2)
+    if plan.status() != 0:
+        raise RuntimeError("device error flag set in the streaming adjoint run")
+    out = {"shape": "5 subbands x N' = 2^17, N_ov = 196608, 21 taps, 10 steps, T = 5 x 2^21 (23 blocks)",
+           "forward_ms": fwd_s * 1e3, "adjoint_ms": bwd_s * 1e3, "checkpoint_every": ck,
+           "workspace_bytes": plan.backward_workspace(t_len, 1, ck)}
+    plan.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--legs", default="fwd,grad,batched,protocol,longlink")
+    ap.add_argument("--legs", default="fwd,grad,batched,protocol,longlink,streamgrad")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0)
     ap.add_argument("--proto-iters", type=int, default=60)
@@ -707,6 +751,8 @@ def main():
         result["protocol"] = leg_protocol(args)
     if "longlink" in legs:
         result["longlink"] = leg_longlink(args)
+    if "streamgrad" in legs:
+        result["streamgrad"] = leg_streamgrad(args)
     print(json.dumps(result), flush=True)
 
 

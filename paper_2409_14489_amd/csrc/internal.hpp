@@ -118,8 +118,8 @@ struct StreamArgs {
 struct StreamBwdLayout {
   int k, n_ck, nblk, nb;
   size_t state;
-  size_t ck_off, slot_off, work_off, g_off, theta_off, tbar_off, cpart_off, rpart_off, accc_off, acct_off, gin_off,
-      bytes;
+  size_t ck_off, slot_off, work_off, g_off, v_off, theta_off, tbar_off, cpart_off, rpart_off, accc_off, acct_off,
+      csum_off, gin_off, bytes;
 };
 
 // Everything an adjoint launch needs.

@@ -498,10 +498,13 @@ __global__ __launch_bounds__(kColThreads) void st_adj_head_kernel(StreamArgs a, 
 // with g' the inverse column pass of the adjoint state g (the adjoint of the
 // forward column pass) and v' = inverse column pass of the stored forward
 // state sf / N2 (the unnormalised pair multiplies by N2); also
-// p_i[n] = sum_pol |v'[n]|^2 (the rotation keeps |v|).
+// p_i[n] = sum_pol |v'[n]|^2 (the rotation keeps |v|).  v' is written to vt
+// (time samples n = n1 + N1 k2 at position n1 + N1 k2, the state layout) for
+// st_adj_rotate_kernel, so only one column of 32 samples is live at a time.
 template <int N2>
 __global__ __launch_bounds__(kColThreads) void st_adj_phase_kernel(const float2* __restrict__ g,
                                                                    const float2* __restrict__ sf,
+                                                                   float2* __restrict__ vt,
                                                                    float* __restrict__ tbar, float* __restrict__ pb,
                                                                    const float2* __restrict__ tw2, int nsb) {
   constexpr int NP = kRow * N2;
@@ -509,40 +512,57 @@ __global__ __launch_bounds__(kColThreads) void st_adj_phase_kernel(const float2*
   const int i = blockIdx.x / GROUPS;
   const int n1 = (blockIdx.x - i * GROUPS) * kColThreads + threadIdx.x;
   const size_t arr = (size_t)blockIdx.y * nsb + i;
-  float p[N2], q[N2];
+  {
+    float p[N2];
 #pragma unroll
-  for (int k = 0; k < N2; ++k) p[k] = q[k] = 0.0f;
+    for (int k = 0; k < N2; ++k) p[k] = 0.0f;
+#pragma unroll 1
+    for (int pol = 0; pol < 2; ++pol) {
+      float2 vf[N2];
+      load_col<N2>(sf + (arr * 2 + pol) * NP, n1, vf);
+      col_inverse<N2>(tw2, n1, vf);
+#pragma unroll
+      for (int k = 0; k < N2; ++k) {
+        vf[k] = cscale(vf[k], 1.0f / N2);
+        p[k] = fmaf(vf[k].x, vf[k].x, fmaf(vf[k].y, vf[k].y, p[k]));
+      }
+      store_col<N2>(vt + (arr * 2 + pol) * NP, n1, vf);
+    }
+    float* dp = pb + arr * NP + n1;
+#pragma unroll
+    for (int k = 0; k < N2; ++k) dp[kRow * k] = p[k];
+  }
+  float q[N2];
+#pragma unroll
+  for (int k = 0; k < N2; ++k) q[k] = 0.0f;
 #pragma unroll 1
   for (int pol = 0; pol < 2; ++pol) {
-    float2 vg[N2], vf[N2];
+    float2 vg[N2];
     load_col<N2>(g + (arr * 2 + pol) * NP, n1, vg);
     col_inverse<N2>(tw2, n1, vg);
-    load_col<N2>(sf + (arr * 2 + pol) * NP, n1, vf);
-    col_inverse<N2>(tw2, n1, vf);
+    const float2* vs = vt + (arr * 2 + pol) * NP + n1;
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int k = 0; k < N2; ++k) {
-      vf[k] = cscale(vf[k], 1.0f / N2);
-      p[k] = fmaf(vf[k].x, vf[k].x, fmaf(vf[k].y, vf[k].y, p[k]));
-      q[k] = fmaf(vg[k].x, vf[k].y, fmaf(-vg[k].y, vf[k].x, q[k]));
+      if ((k & 7) == 0) __builtin_amdgcn_sched_barrier(0);
+      const float2 vf = vs[kRow * k];
+      q[k] = fmaf(vg[k].x, vf.y, fmaf(-vg[k].y, vf.x, q[k]));
     }
   }
-  float* dp = pb + arr * NP + n1;
   float* dq = tbar + arr * NP + n1;
 #pragma unroll
-  for (int k = 0; k < N2; ++k) {
-    dp[kRow * k] = p[k];
-    dq[kRow * k] = q[k];
-  }
+  for (int k = 0; k < N2; ++k) dq[kRow * k] = q[k];
 }
 
-// Adjoint of the rotation and intensity: with v = v' exp(+j theta) (v' from
-// the stored state as in st_adj_phase_kernel),
-//   g_v = g' exp(+j theta) + 2 p_bar v,
-// then the forward column pass (the adjoint of the inverse column pass that
-// produced v), in place over g.
+// Adjoint of the rotation and intensity: with v = v' exp(+j theta),
+//   g_v = g' exp(+j theta) + 2 p_bar v = exp(+j theta) (g' + 2 p_bar v'),
+// g' the inverse column pass of the adjoint state g, v' as written by
+// st_adj_phase_kernel; g_v (time samples) overwrites v' in vt.
+// st_col_forward_kernel then applies the forward column pass (the adjoint of
+// the inverse column pass that produced v) into g.
 template <int N2>
-__global__ __launch_bounds__(kColThreads) void st_adj_rotate_kernel(float2* __restrict__ g,
-                                                                    const float2* __restrict__ sf,
+__global__ __launch_bounds__(kColThreads) void st_adj_rotate_kernel(const float2* __restrict__ g,
+                                                                    float2* __restrict__ vt,
                                                                     const float* __restrict__ th,
                                                                     const float* __restrict__ pbar,
                                                                     const float2* __restrict__ tw2, int nsb) {
@@ -559,22 +579,38 @@ __global__ __launch_bounds__(kColThreads) void st_adj_rotate_kernel(float2* __re
   }
 #pragma unroll 1
   for (int pol = 0; pol < 2; ++pol) {
-    float2 vg[N2], vf[N2];
+    float2 vg[N2];
     load_col<N2>(g + (arr * 2 + pol) * NP, n1, vg);
     col_inverse<N2>(tw2, n1, vg);
-    load_col<N2>(sf + (arr * 2 + pol) * NP, n1, vf);
-    col_inverse<N2>(tw2, n1, vf);
+    float2* vs = vt + (arr * 2 + pol) * NP + n1;
 #pragma unroll
     for (int k = 0; k < N2; ++k) {
       float sn, cs;
       phase_sincos(theta[k], sn, cs);
-      const float2 e = make_float2(cs, sn);
-      const float2 v = cmul(cscale(vf[k], 1.0f / N2), e);
-      const float2 gr = cmul(vg[k], e);
-      vg[k] = make_float2(fmaf(p2[k], v.x, gr.x), fmaf(p2[k], v.y, gr.y));
+      const float2 vf = vs[kRow * k];
+      const float2 u = make_float2(fmaf(p2[k], vf.x, vg[k].x), fmaf(p2[k], vf.y, vg[k].y));
+      vs[kRow * k] = cmul(u, make_float2(cs, sn));
     }
-    col_forward<N2>(tw2, n1, vg);
-    store_col<N2>(g + (arr * 2 + pol) * NP, n1, vg);
+  }
+}
+
+// Forward column pass of every column of src (time samples in the state
+// layout) into dst.
+template <int N2>
+__global__ __launch_bounds__(kColThreads) void st_col_forward_kernel(const float2* __restrict__ src,
+                                                                     float2* __restrict__ dst,
+                                                                     const float2* __restrict__ tw2, int nsb) {
+  constexpr int NP = kRow * N2;
+  constexpr int GROUPS = kRow / kColThreads;
+  const int i = blockIdx.x / GROUPS;
+  const int n1 = (blockIdx.x - i * GROUPS) * kColThreads + threadIdx.x;
+  const size_t arr = (size_t)blockIdx.y * nsb + i;
+#pragma unroll 1
+  for (int pol = 0; pol < 2; ++pol) {
+    float2 v[N2];
+    load_col<N2>(src + (arr * 2 + pol) * NP, n1, v);
+    col_forward<N2>(tw2, n1, v);
+    store_col<N2>(dst + (arr * 2 + pol) * NP, n1, v);
   }
 }
 
@@ -583,8 +619,10 @@ __global__ __launch_bounds__(kColThreads) void st_adj_rotate_kernel(float2* __re
 //   part[i][l][tau] = sum_n theta_bar_i[n] p_l[(n - tau + nc) mod N'].
 // Thread work items are (l, tau) pairs, each over a contiguous share of the
 // samples (pairs x shares <= 256); the shares are added in LDS in a fixed
-// order.  LDS (dynamic): p rows with a halo of nc each side, theta_bar rows,
-// the share partials.
+// order.  Per 4 samples a thread reads theta_bar of every subband as one
+// 128-bit word (the same for all lanes of a share) and 4 intensities.  LDS
+// (dynamic): p rows with a halo of nc each side (row width rounded up to 4
+// floats), theta_bar rows, the share partials.
 constexpr int kCgOut = 512;
 
 __host__ __device__ inline int cg_shares(int npair) {
@@ -592,27 +630,29 @@ __host__ __device__ inline int cg_shares(int npair) {
   while (2 * sh * npair <= 256 && sh < 64) sh *= 2;
   return sh;
 }
+__host__ __device__ inline int cg_pw(int n_taps) { return (kCgOut + n_taps - 1 + 3) & ~3; }
 __host__ inline size_t cg_lds_bytes(int nsb, int n_taps) {
   const int npair = nsb * n_taps;
   const int sh = npair > 256 ? 1 : cg_shares(npair);
-  return sizeof(float) * ((size_t)nsb * (kCgOut + n_taps - 1) + (size_t)nsb * kCgOut +
+  return sizeof(float) * ((size_t)nsb * cg_pw(n_taps) + (size_t)nsb * kCgOut +
                           (npair > 256 ? 0 : (size_t)sh * npair * nsb));
 }
 
 __global__ __launch_bounds__(256) void st_cgrad_kernel(const float* __restrict__ tbar, const float* __restrict__ pb,
                                                        float* __restrict__ part, int nsb, int np, int n_taps) {
-  extern __shared__ float cg_lds[];
+  extern __shared__ __align__(16) float cg_lds[];
   const int nc = n_taps / 2;
-  const int pw = kCgOut + n_taps - 1;  // p row width
+  const int pw = cg_pw(n_taps);
   float* ptile = cg_lds;
-  float* ttile = cg_lds + (size_t)nsb * pw;
+  float* ttile = cg_lds + (size_t)nsb * pw;  // 16-byte aligned: pw is a multiple of 4
   float* red = ttile + (size_t)nsb * kCgOut;
   const int n0 = blockIdx.x * kCgOut;
   const size_t arr0 = (size_t)blockIdx.y * nsb;
   const int t = threadIdx.x;
+  const int span = kCgOut + 2 * nc;
   for (int l = 0; l < nsb; ++l) {
     const float* prow = pb + (arr0 + l) * np;
-    for (int j = t; j < pw; j += 256) {
+    for (int j = t; j < span; j += 256) {
       int q = n0 - nc + j;
       q = q < 0 ? q + np : (q >= np ? q - np : q);
       ptile[l * pw + j] = prow[q];
@@ -624,9 +664,10 @@ __global__ __launch_bounds__(256) void st_cgrad_kernel(const float* __restrict__
   const int npair = nsb * n_taps;
   const bool wide = npair > 256;
   const int sh = wide ? 1 : cg_shares(npair);
-  const int len = kCgOut / sh;
+  const int len = kCgOut / sh;  // a multiple of 8
   const size_t out0 = ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * nsb * npair;
   const int items = wide ? npair : sh * npair;
+  const float4* t4 = reinterpret_cast<const float4*>(ttile);
   for (int wi = t; wi < items; wi += 256) {
     const int pr = wide ? wi : wi % npair;
     const int sp = wide ? 0 : wi / npair;
@@ -636,11 +677,15 @@ __global__ __launch_bounds__(256) void st_cgrad_kernel(const float* __restrict__
     float acc[kMaxSubbands];
 #pragma unroll
     for (int i = 0; i < kMaxSubbands; ++i) acc[i] = 0.0f;
-    for (int n = sp * len; n < (sp + 1) * len; ++n) {
-      const float pv = prow[n];
+    for (int n = sp * len; n < (sp + 1) * len; n += 4) {
+      const float p0 = prow[n], p1 = prow[n + 1], p2 = prow[n + 2], p3 = prow[n + 3];
 #pragma unroll
-      for (int i = 0; i < kMaxSubbands; ++i)
-        if (i < nsb) acc[i] = fmaf(ttile[i * kCgOut + n], pv, acc[i]);
+      for (int i = 0; i < kMaxSubbands; ++i) {
+        if (i < nsb) {
+          const float4 tv = t4[(i * kCgOut + n) >> 2];
+          acc[i] = fmaf(tv.x, p0, fmaf(tv.y, p1, fmaf(tv.z, p2, fmaf(tv.w, p3, acc[i]))));
+        }
+      }
     }
 #pragma unroll
     for (int i = 0; i < kMaxSubbands; ++i) {
@@ -729,25 +774,35 @@ __global__ __launch_bounds__(kRowNT, 2) void st_gvd_adj_kernel(float2* g, const 
   }
 }
 
-// acc[j] += sum over r < n_rows of part[r][j] (FP64, fixed order: thread
-// (jj, g) of a 64 x 16 block sums rows g, g + 16, ...; the 16 sums are added
-// in a fixed tree).
-constexpr int kAccJ = 64, kAccG = 16;
-__global__ __launch_bounds__(kAccJ * kAccG) void st_acc_rows_kernel(const float* __restrict__ part, int n_rows,
-                                                                   int per_row, double* __restrict__ acc) {
+// acc[j] += sum over r < n_rows of part[r][j] (FP64, fixed order), in two
+// launches: st_sum_rows_kernel gives the sum of every chunk of rows
+// (chunk c = rows c, c + kAccC, ...; thread (jj, g) of a 64 x 16 block sums
+// every 16th of them, then a fixed tree), st_add_chunks_kernel adds the
+// kAccC chunk sums in order.
+constexpr int kAccJ = 64, kAccG = 16, kAccC = 32;
+__global__ __launch_bounds__(kAccJ * kAccG) void st_sum_rows_kernel(const float* __restrict__ part, int n_rows,
+                                                                   int per_row, double* __restrict__ csum) {
   __shared__ double buf[kAccG][kAccJ];
   const int jj = threadIdx.x % kAccJ, gg = threadIdx.x / kAccJ;
   const int j = blockIdx.x * kAccJ + jj;
+  const int c = blockIdx.y;
   double s = 0.0;
   if (j < per_row)
-    for (int r = gg; r < n_rows; r += kAccG) s += (double)part[(size_t)r * per_row + j];
+    for (int r = c + kAccC * gg; r < n_rows; r += kAccC * kAccG) s += (double)part[(size_t)r * per_row + j];
   buf[gg][jj] = s;
   __syncthreads();
   for (int w = kAccG / 2; w > 0; w >>= 1) {
     if (gg < w) buf[gg][jj] += buf[gg + w][jj];
     __syncthreads();
   }
-  if (gg == 0 && j < per_row) acc[j] += buf[0][jj];
+  if (gg == 0 && j < per_row) csum[(size_t)c * per_row + j] = buf[0][jj];
+}
+__global__ void st_add_chunks_kernel(const double* __restrict__ csum, int per_row, double* __restrict__ acc) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= per_row) return;
+  double s = 0.0;
+  for (int c = 0; c < kAccC; ++c) s += csum[(size_t)c * per_row + j];
+  acc[j] += s;
 }
 
 // *acc += sum of part[0 .. n) (FP64, fixed order).
@@ -907,11 +962,13 @@ int launch_stream_forward(cbessfm_plan_t* p, const void* in, void* out, long lon
 //   slot   [k] states after the steps of the current segment
 //   work   one state (row-pass output of a forward step)
 //   g      one state (the adjoint state)
+//   v      one state-sized array of time samples (v' of the step being undone)
 //   theta  [k] phase arrays of the segment's steps
 //   tbar   one phase-cotangent array
 //   cpart  coefficient partials of one step, [N' / kCgOut x nb][n_sb][n_sb][n_taps]
 //   rpart  dispersion-derivative partials of one row pass, [n_sb N2 nb]
 //   acc_c  FP64 [steps][n_sb][n_sb][n_taps], acc_t FP64 [steps + 1]
+//   csum   FP64 [kAccC][n_sb][n_sb][n_taps] chunk sums of the partials
 //   gin    [batch nblk][2][N] block input cotangents (only with grad_in)
 // A state is [nb][n_sb][2][N'] complex; p and p_bar use the plan's arrays.
 StreamBwdLayout stream_bwd_layout(const cbessfm_plan_t* p, long long T, int batch, int ck_every, bool gin) {
@@ -929,14 +986,16 @@ StreamBwdLayout stream_bwd_layout(const cbessfm_plan_t* p, long long T, int batc
   L.slot_off = L.ck_off + sbytes * L.n_ck;
   L.work_off = L.slot_off + sbytes * L.k;
   L.g_off = L.work_off + sbytes;
-  L.theta_off = L.g_off + sbytes;
+  L.v_off = L.g_off + sbytes;
+  L.theta_off = L.v_off + sbytes;
   L.tbar_off = L.theta_off + up(sizeof(float) * cells) * L.k;
   L.cpart_off = L.tbar_off + up(sizeof(float) * cells);
   const size_t n_cg = (size_t)(p->Np / kCgOut) * L.nb;
   L.rpart_off = L.cpart_off + up(sizeof(float) * n_cg * nsb * nsb * p->n_taps);
   L.accc_off = L.rpart_off + up(sizeof(double) * nsb * (p->Np / kRow) * L.nb);
   L.acct_off = L.accc_off + up(sizeof(double) * (size_t)p->steps * nsb * nsb * p->n_taps);
-  L.gin_off = L.acct_off + up(sizeof(double) * (size_t)(p->steps + 1));
+  L.csum_off = L.acct_off + up(sizeof(double) * (size_t)(p->steps + 1));
+  L.gin_off = L.csum_off + up(sizeof(double) * kAccC * nsb * nsb * p->n_taps);
   L.bytes = L.gin_off + (gin ? up(sizeof(float2) * (size_t)items * 2 * p->N) : 0);
   return L;
 }
@@ -962,6 +1021,8 @@ struct StreamBwdCall {
   float* TH(int st) const { return reinterpret_cast<float*>(ws + L.theta_off + tbytes() * (st % L.k)); }
   float2* work() const { return reinterpret_cast<float2*>(ws + L.work_off); }
   float2* G() const { return reinterpret_cast<float2*>(ws + L.g_off); }
+  float2* V() const { return reinterpret_cast<float2*>(ws + L.v_off); }
+  double* csum() const { return reinterpret_cast<double*>(ws + L.csum_off); }
   float* tbar() const { return reinterpret_cast<float*>(ws + L.tbar_off); }
   float* cpart() const { return reinterpret_cast<float*>(ws + L.cpart_off); }
   double* rpart() const { return reinterpret_cast<double*>(ws + L.rpart_off); }
@@ -1020,7 +1081,8 @@ int bwd_wave(const StreamBwdCall& c, StreamArgs a) {
       for (int st = s0; st < s1 && ok; ++st)
         ok = wave_step<N2>(a, tb, p->d_cpad, st, n_taps, tap_pad, c.S(st), c.work(), c.TH(st), c.S(st + 1), s);
     for (int st = s1 - 1; st >= s0 && ok; --st) {
-      st_adj_phase_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(c.G(), c.S(st + 1), c.tbar(), a.pb, a.tw2, nsb);
+      st_adj_phase_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(c.G(), c.S(st + 1), c.V(), c.tbar(), a.pb, a.tw2,
+                                                              nsb);
       ok = ok && ok_launch();
       // p_bar = C^T applied to theta_bar (transposed, tap-reversed rows)
       st_fir_kernel<<<dim3(a.np / kFirOut, a.nb), 256, 0, s>>>(
@@ -1028,10 +1090,13 @@ int bwd_wave(const StreamBwdCall& c, StreamArgs a) {
       ok = ok && ok_launch();
       st_cgrad_kernel<<<cg_grid, 256, cg_lds, s>>>(c.tbar(), a.pb, c.cpart(), nsb, a.np, n_taps);
       ok = ok && ok_launch();
-      st_acc_rows_kernel<<<(per_step + kAccJ - 1) / kAccJ, kAccJ * kAccG, 0, s>>>(
-          c.cpart(), (int)(cg_grid.x * cg_grid.y), per_step, c.acc_c() + (size_t)st * per_step);
+      st_sum_rows_kernel<<<dim3((per_step + kAccJ - 1) / kAccJ, kAccC), kAccJ * kAccG, 0, s>>>(
+          c.cpart(), (int)(cg_grid.x * cg_grid.y), per_step, c.csum());
+      st_add_chunks_kernel<<<(per_step + 255) / 256, 256, 0, s>>>(c.csum(), per_step,
+                                                                  c.acc_c() + (size_t)st * per_step);
       ok = ok && ok_launch();
-      st_adj_rotate_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(c.G(), c.S(st + 1), c.TH(st), a.th, a.tw2, nsb);
+      st_adj_rotate_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(c.G(), c.V(), c.TH(st), a.th, a.tw2, nsb);
+      st_col_forward_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(c.V(), c.G(), a.tw2, nsb);
       ok = ok && ok_launch();
       if (st > 0) {
         if (c.want_gvd)
