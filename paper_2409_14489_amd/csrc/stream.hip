@@ -306,15 +306,22 @@ __global__ __launch_bounds__(kColThreads) void st_intensity_kernel(const float2*
 // in LDS once.  Taps go in chunks of 8 over the zero-padded coefficient rows
 // (uniform across the workgroup, so they are scalar loads of 8 words); for
 // each chunk a thread reads a window of kFirQ + 7 intensities and does
-// 8 kFirQ multiply-adds per output subband.
+// 8 kFirQ multiply-adds per output subband.  The LDS rows (dynamic, n_sb of
+// them, fir_lds_bytes) are only as many as the plan has subbands, so more
+// workgroups fit a CU at small n_sb.
 constexpr int kFirQ = 4;
 constexpr int kFirOut = 256 * kFirQ;
+
+__host__ __device__ inline int fir_row_width(int tap_pad) { return kFirOut + tap_pad - 1; }
+__host__ inline size_t fir_lds_bytes(int nsb, int tap_pad) {
+  return sizeof(float) * (size_t)nsb * fir_row_width(tap_pad);
+}
 
 __global__ __launch_bounds__(256) void st_fir_kernel(const float* __restrict__ pb, float* __restrict__ th,
                                                      const float* __restrict__ cs, int nsb, int np, int nc,
                                                      int tap_pad) {
-  constexpr int W = kFirOut + 256;  // >= kFirOut + tap_pad - 1, tap_pad <= 256
-  __shared__ float tile[kMaxSubbands][W];
+  extern __shared__ float fir_lds[];
+  const int W = fir_row_width(tap_pad);
   const int n0 = blockIdx.x * kFirOut;
   const size_t arr0 = (size_t)blockIdx.y * nsb;
   const int hl = tap_pad - 1 - nc;
@@ -324,7 +331,7 @@ __global__ __launch_bounds__(256) void st_fir_kernel(const float* __restrict__ p
     for (int j = threadIdx.x; j < span; j += 256) {
       int q = n0 - hl + j;
       q = q < 0 ? q + np : (q >= np ? q - np : q);
-      tile[l][j] = row[q];
+      fir_lds[l * W + j] = row[q];
     }
   }
   __syncthreads();
@@ -336,7 +343,7 @@ __global__ __launch_bounds__(256) void st_fir_kernel(const float* __restrict__ p
     for (int q = 0; q < kFirQ; ++q) acc[i][q] = 0.0f;
   const int n_chunks = tap_pad / kTapChunk;
   for (int l = 0; l < nsb; ++l) {
-    const float* tl = tile[l] + t * kFirQ + tap_pad - 1 - (kTapChunk - 1);
+    const float* tl = fir_lds + l * W + t * kFirQ + tap_pad - 1 - (kTapChunk - 1);
     for (int ch = 0; ch < n_chunks; ++ch) {
       // taps tau = 8 ch + u use win[q + 7 - u] for output q
       float win[kFirQ + kTapChunk - 1];
@@ -884,7 +891,8 @@ bool wave_step(const StreamArgs& a, const Tables& tb, const float* cpad, int st,
   bool ok = (st == 0 && nsb > 1) ? row<false, true, true>(a, src, work, h, s) : row<true, true, true>(a, src, work, h, s);
   st_intensity_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(work, a.pb, a.tw2, nsb);
   ok = ok && ok_launch();
-  st_fir_kernel<<<dim3(a.np / kFirOut, a.nb), 256, 0, s>>>(a.pb, theta, cpad + (size_t)st * nsb * nsb * tap_pad,
+  st_fir_kernel<<<dim3(a.np / kFirOut, a.nb), 256, fir_lds_bytes(nsb, tap_pad), s>>>(
+      a.pb, theta, cpad + (size_t)st * nsb * nsb * tap_pad,
                                                            nsb, a.np, n_taps / 2, tap_pad);
   ok = ok && ok_launch();
   st_rotate_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(work, dst, theta, a.tw2, nsb);
@@ -1085,7 +1093,7 @@ int bwd_wave(const StreamBwdCall& c, StreamArgs a) {
                                                               nsb);
       ok = ok && ok_launch();
       // p_bar = C^T applied to theta_bar (transposed, tap-reversed rows)
-      st_fir_kernel<<<dim3(a.np / kFirOut, a.nb), 256, 0, s>>>(
+      st_fir_kernel<<<dim3(a.np / kFirOut, a.nb), 256, fir_lds_bytes(nsb, tap_pad), s>>>(
           c.tbar(), a.th, p->d_ctpad + (size_t)st * per_step / n_taps * tap_pad, nsb, a.np, n_taps / 2, tap_pad);
       ok = ok && ok_launch();
       st_cgrad_kernel<<<cg_grid, 256, cg_lds, s>>>(c.tbar(), a.pb, c.cpart(), nsb, a.np, n_taps);
