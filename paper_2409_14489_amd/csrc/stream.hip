@@ -27,6 +27,12 @@
 // Every kernel reads and writes whole coalesced rows or columns-across-lanes;
 // nothing here is resident across steps, so the path is bound by HBM (and the
 // 256 MB last-level cache) rather than by the persistent kernel's LDS.
+//
+// The second half of the file is the reverse-mode derivative of the same
+// chain (dL/dC, dL/drho, dL/d(segment lengths), dL/dfield_in): a forward
+// sweep that keeps the block state at every checkpoint segment start, then
+// per segment (recomputed from its start) the adjoint stages in reverse
+// order, built from the same column/row passes.
 #include <hip/hip_runtime.h>
 
 #include "fft_lds.hpp"
