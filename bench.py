@@ -127,6 +127,31 @@ def oracle_plan(d, rate, step_km, coeffs, beta2_ps2_km):
                              d["n_sb"] * d["n_sub"], d["n_overlap"], np.asarray(coeffs, np.float64))
 
 
+def oracle_all_cores(x, oplan, n2d, workers=None):
+    """The oracle with the blocks of the field split over worker processes
+    (oracle.timing, started as a child program: no process is forked from
+    this one, which holds the GPU).  None if the child fails."""
+    import subprocess
+    import tempfile
+    import numpy as np
+    workers = workers or max(1, min(16, os.cpu_count() or 1))
+    with tempfile.TemporaryDirectory(prefix="cbessfm_oracle_") as tmp:
+        case = os.path.join(tmp, "case.npz")
+        np.savez(case, x=np.asarray(x, np.complex128), coeffs=np.asarray(oplan.coeffs, np.float64),
+                 beta2_s2_km=oplan.beta2_s2_km, sample_rate=oplan.sample_rate, step_km=oplan.step_km,
+                 n_steps=oplan.n_steps, rho=oplan.rho, n_sb=oplan.n_sb, n_block=oplan.n_block,
+                 n_overlap=oplan.n_overlap)
+        res = subprocess.run([sys.executable, "-m", "oracle.timing", case, str(workers)], cwd=ROOT,
+                             capture_output=True, text=True, timeout=600)
+    if res.returncode != 0 or not res.stdout.strip():
+        return None
+    t = json.loads(res.stdout.strip().splitlines()[-1])
+    return {"value": n2d / t["wall_s"], "unit": "2D-symbols/s", "cores": max(1, round(t["cpu_s"] / t["wall_s"])),
+            "workers": t["workers"], "kind": "oracle",
+            "sample": f"the whole workload, one pass, {t['blocks']} blocks split over {t['workers']} processes, "
+                      f"{t['wall_s']:.1f} s"}
+
+
 def timed_events(stream, fn, reps):
     """Average seconds per call of fn() on `stream`, HIP events around the loop."""
     import torch
@@ -275,6 +300,9 @@ def leg_forward(args):
                                   "cores": max(1, round(proc_s / cpu_s)), "kind": "oracle",
                                   "sample": f"the whole workload ({nblk} blocks), {passes} passes of the FP64 "
                                             f"numpy oracle, {cpu_s:.1f} s"}
+        all_cores = oracle_all_cores(x, oplan, n2d)
+        if all_cores is not None:
+            result["cpu_baseline_all_cores"] = all_cores
     if args.copy_mib:
         n = args.copy_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
