@@ -584,26 +584,37 @@ __global__ __launch_bounds__(kColThreads) void st_adj_rotate_kernel(const float2
   const int i = blockIdx.x / GROUPS;
   const int n1 = (blockIdx.x - i * GROUPS) * kColThreads + threadIdx.x;
   const size_t arr = (size_t)blockIdx.y * nsb + i;
-  float theta[N2], p2[N2];
-#pragma unroll
-  for (int k = 0; k < N2; ++k) {
-    theta[k] = th[arr * NP + n1 + kRow * k];
-    p2[k] = 2.0f * pbar[arr * NP + n1 + kRow * k];
-  }
+  const float* ths = th + arr * NP + n1;
+  const float* pbs = pbar + arr * NP + n1;
 #pragma unroll 1
   for (int pol = 0; pol < 2; ++pol) {
     float2 vg[N2];
     load_col<N2>(g + (arr * 2 + pol) * NP, n1, vg);
     col_inverse<N2>(tw2, n1, vg);
     float2* vs = vt + (arr * 2 + pol) * NP + n1;
+    // the inputs of 8 samples at a time are loaded together and every store
+    // waits until the column is done: stores count in the same in-order
+    // memory counter as loads, so a store between two loads would make the
+    // second one wait for it
 #pragma unroll
-    for (int k = 0; k < N2; ++k) {
-      float sn, cs;
-      phase_sincos(theta[k], sn, cs);
-      const float2 vf = vs[kRow * k];
-      const float2 u = make_float2(fmaf(p2[k], vf.x, vg[k].x), fmaf(p2[k], vf.y, vg[k].y));
-      vs[kRow * k] = cmul(u, make_float2(cs, sn));
+    for (int k0 = 0; k0 < N2; k0 += 8) {
+      float t8[8], q8[8];
+      float2 f8[8];
+#pragma unroll
+      for (int j = 0; j < 8 && k0 + j < N2; ++j) {
+        t8[j] = ths[kRow * (k0 + j)];
+        q8[j] = 2.0f * pbs[kRow * (k0 + j)];
+        f8[j] = vs[kRow * (k0 + j)];
+      }
+#pragma unroll
+      for (int j = 0; j < 8 && k0 + j < N2; ++j) {
+        float sn, cs;
+        phase_sincos(t8[j], sn, cs);
+        const float2 u = make_float2(fmaf(q8[j], f8[j].x, vg[k0 + j].x), fmaf(q8[j], f8[j].y, vg[k0 + j].y));
+        vg[k0 + j] = cmul(u, make_float2(cs, sn));
+      }
     }
+    store_col<N2>(vt + (arr * 2 + pol) * NP, n1, vg);
   }
 }
 
