@@ -36,7 +36,8 @@ Options:
                 (default all; the primary forward always runs)
   --no-cpu      skip the oracle timing (and the full-size parity check)
   --copy-mib M  after timing, one plain device copy of M MiB (counter calibration)
-  --fit-iters F Adam iterations per step count of the long-link fit (default 20)
+  --fit-iters F Adam iterations per step count of the long-link fit (default 20;
+                8 / steps times as many below 8 steps)
 """
 from __future__ import annotations
 
@@ -582,7 +583,7 @@ def leg_longlink(args):
     scaled by the best of a few factors (one forward pass each; the analytic
     taps of a very long step overshoot) and takes ``--fit-iters`` Adam
     iterations of forward + streaming adjoint with recomputation every 8
-    steps."""
+    steps (8 / steps times as many below 8 steps, where they are cheap)."""
     import numpy as np
     import torch
     from paper_2409_14489_amd import Plan, analytic_coeffs
@@ -654,21 +655,22 @@ def leg_longlink(args):
             rho_t = torch.tensor(d["rho"], dtype=torch.float32, device="cuda")
             with torch.no_grad():
                 trial = {a: float(receiver_mse(cbessfm(x_tr, (a * c_an).contiguous(), rho_t, plan), rxs, sym_tr))
-                         for a in (0.125, 0.25, 0.5, 1.0)}
+                         for a in (1 / 32, 1 / 16, 0.125, 0.25, 0.5, 1.0)}
             alpha = min(trial, key=trial.get)
+            iters = max(args.fit_iters, (8 * args.fit_iters) // st)   # short runs are cheap: more iterations
             ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             ev0.record(stream)
-            c_fit, rho_fit, losses = fit(plan, x_tr, sym_tr, rxs, alpha * c_an, d["rho"], iters=args.fit_iters,
+            c_fit, rho_fit, losses = fit(plan, x_tr, sym_tr, rxs, alpha * c_an, d["rho"], iters=iters,
                                          lr=1e-2, checkpoint_every=fit_ck)
             ev1.record(stream)
             torch.cuda.synchronize()
-            fit_ms = ev0.elapsed_time(ev1) / args.fit_iters
+            fit_ms = ev0.elapsed_time(ev1) / iters
             with torch.no_grad():
                 y_fit = cbessfm(xin, c_fit.contiguous(), rho_fit.reshape(()), plan)
             snr_fit = snr_per_channel(y_fit)
             del y_fit
             ls = losses.cpu().numpy()
-            row["fit"] = {"iters": args.fit_iters, "lr": 1e-2, "checkpoint_every": fit_ck, "alpha": alpha,
+            row["fit"] = {"iters": iters, "lr": 1e-2, "checkpoint_every": fit_ck, "alpha": alpha,
                           "alpha_trial_mse": trial, "mse_first": float(ls[0]), "mse_last": float(ls[-1]),
                           "rho": float(rho_fit), "ms_per_iter": fit_ms,
                           "grad_steps_per_s": 1e3 / fit_ms,

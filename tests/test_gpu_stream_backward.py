@@ -129,3 +129,68 @@ def test_stream_backward_graph_replay():
         _ = (xs[k] * 2).sum().item()   # eager work between replays
     del graph
     g.close()
+
+
+def test_stream_backward_rejects_a_short_workspace():
+    """cbessfm_backward on a streaming plan returns CBESSFM_EWORKSPACE, and
+    launches nothing, when the workspace is too small (here half of what
+    cbessfm_backward_workspace() asks for, which also covers the optional
+    input cotangents)."""
+    import ctypes
+    from paper_2409_14489_amd._lib import EWORKSPACE, lib
+    c = rand_coeffs(2, 2, 5, 0.5, 4e-3, 9)
+    g, _ = plans(2, 2 ** 14, 4096, 2, 0.4, c, rate=128e9)
+    x = torch.from_numpy(random_field((2, 40000), 95, power_w=4e-3).astype(np.complex64)).cuda()
+    need = g.backward_workspace(40000, 1, 1)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    gc = torch.empty((2, 2, 2, 5), dtype=torch.float32, device="cuda")
+    gr = torch.empty(1, dtype=torch.float32, device="cuda")
+    rc = lib.cbessfm_backward(g._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(x.data_ptr()), None,
+                              ctypes.c_void_p(gc.data_ptr()), ctypes.c_void_p(gr.data_ptr()), 40000, 1, 1,
+                              ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(need // 2), None)
+    torch.cuda.synchronize()
+    assert rc == EWORKSPACE
+    assert g.status() == 0
+    g.close()
+
+
+def test_stream_gradients_full_long_link_record():
+    """The whole long-link record (5 subbands of N' = 2^17, N_ov = 196608,
+    T = 5 x 2^21: 23 blocks in one wave), 10 steps over 40 x 80 km: checkpoints
+    every 8 steps give the bits of storing every step, and the coefficient
+    gradient along a random direction matches a central difference of the
+    forward map (L = Re sum conj(G) y summed in FP64; step 1e-2 of the
+    coefficients' scale, FP32 rounding of 2.1e7 output samples bounds the
+    agreement to about 1e-3)."""
+    from paper_2409_14489_amd import LinkSpec, Plan, analytic_coeffs
+    steps = 10
+    link = LinkSpec(beta2_ps2_km=-21.7, n_spans=40, span_km=80.0, sample_rate_hz=640e9)
+    c = analytic_coeffs(link, 5, steps, 0.3, 21).astype(np.float32)
+    plan = Plan(link, 5, 2 ** 17, 196608, steps, 0.3, coeffs=c)
+    t_len = 5 * 2 ** 21
+    assert plan.n_blocks(t_len) == 23
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    x = (torch.randn((2, t_len), dtype=torch.complex64, device="cuda", generator=gen) * 0.05).contiguous()
+    go = torch.randn((2, t_len), dtype=torch.complex64, device="cuda", generator=gen).contiguous()
+    _, gc8, gr8 = plan.backward(x, go, need_grad_in=False, checkpoint_every=8)
+    _, gc1, gr1 = plan.backward(x, go, need_grad_in=False, checkpoint_every=1)
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    assert torch.equal(gc8, gc1) and torch.equal(gr8, gr1)
+    d = torch.randn(gc8.shape, dtype=torch.float32, device="cuda", generator=gen)
+    c0 = torch.from_numpy(c).cuda()
+    h = 1e-2 * float(c0.abs().max())
+
+    def loss(cc):
+        plan.set_coeffs(cc.contiguous())
+        y = plan.run(x)
+        return float((torch.conj(go.to(torch.complex128)) * y.to(torch.complex128)).real.sum())
+
+    fd = (loss(c0 + h * d) - loss(c0 - h * d)) / (2 * h)
+    plan.set_coeffs(c0)
+    an = float((gc8.double() * d.double()).sum())
+    err = abs(fd - an) / abs(an)
+    print(f"full record: directional derivative {an:.6e}, central difference {fd:.6e}, rel err {err:.2e}")
+    assert err < 1e-2
+    plan.close()
