@@ -137,19 +137,41 @@ __device__ __forceinline__ void store_col(float2* __restrict__ a, int n1, const 
   for (int k = 0; k < N2; ++k) a[n1 + kRow * k] = v[k];
 }
 
+// Column twiddle exp(-j 2 pi n1 k / N') for k < N2: read directly for
+// k < 8 and k multiple of 8, else as the product of the k mod 8 and the
+// 8 floor(k / 8) entries (10 reads instead of 31 at N2 = 32).
+template <int N2>
+__device__ __forceinline__ void col_twiddles(const float2* __restrict__ tw2, int n1, float2 (&a)[8],
+                                             float2 (&b)[(N2 + 7) / 8]) {
+#pragma unroll
+  for (int j = 1; j < 8 && j < N2; ++j) a[j] = tw2[kRow * j + n1];
+#pragma unroll
+  for (int m = 1; m < (N2 + 7) / 8; ++m) b[m] = tw2[kRow * 8 * m + n1];
+}
+template <int N2>
+__device__ __forceinline__ float2 col_tw(const float2 (&a)[8], const float2 (&b)[(N2 + 7) / 8], int k) {
+  const int j = k & 7, m = k >> 3;
+  if (m == 0) return a[j];
+  if (j == 0) return b[m];
+  return cmul(a[j], b[m]);
+}
 // Inverse column pass of column n1: undo the twiddle, size-N2 inverse DFT.
 template <int N2>
 __device__ __forceinline__ void col_inverse(const float2* __restrict__ tw2, int n1, float2 (&v)[N2]) {
+  float2 a[8], b[(N2 + 7) / 8];
+  col_twiddles<N2>(tw2, n1, a, b);
 #pragma unroll
-  for (int k = 1; k < N2; ++k) v[k] = cmulc(v[k], tw2[kRow * k + n1]);
+  for (int k = 1; k < N2; ++k) v[k] = cmulc(v[k], col_tw<N2>(a, b, k));
   col_dft<N2, true>(v);
 }
 // Forward column pass: size-N2 DFT, then the twiddle exp(-j 2 pi n1 k2 / N').
 template <int N2>
 __device__ __forceinline__ void col_forward(const float2* __restrict__ tw2, int n1, float2 (&v)[N2]) {
   col_dft<N2, false>(v);
+  float2 a[8], b[(N2 + 7) / 8];
+  col_twiddles<N2>(tw2, n1, a, b);
 #pragma unroll
-  for (int k = 1; k < N2; ++k) v[k] = cmul(v[k], tw2[kRow * k + n1]);
+  for (int k = 1; k < N2; ++k) v[k] = cmul(v[k], col_tw<N2>(a, b, k));
 }
 
 }  // namespace
