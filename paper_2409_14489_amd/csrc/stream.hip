@@ -534,10 +534,11 @@ __global__ __launch_bounds__(kColThreads) void st_adj_head_kernel(StreamArgs a, 
 // forward column pass) and v' = inverse column pass of the stored forward
 // state sf / N2 (the unnormalised pair multiplies by N2); also
 // p_i[n] = sum_pol |v'[n]|^2 (the rotation keeps |v|).  v' is written to vt
-// (time samples n = n1 + N1 k2 at position n1 + N1 k2, the state layout) for
-// st_adj_rotate_kernel, so only one column of 32 samples is live at a time.
+// (time samples n = n1 + N1 k2 at position n1 + N1 k2, the state layout) and
+// g' over g (same layout) for st_adj_rotate_kernel; only one column of 32
+// samples is live at a time.
 template <int N2>
-__global__ __launch_bounds__(kColThreads) void st_adj_phase_kernel(const float2* __restrict__ g,
+__global__ __launch_bounds__(kColThreads) void st_adj_phase_kernel(float2* __restrict__ g,
                                                                    const float2* __restrict__ sf,
                                                                    float2* __restrict__ vt,
                                                                    float* __restrict__ tbar, float* __restrict__ pb,
@@ -583,61 +584,35 @@ __global__ __launch_bounds__(kColThreads) void st_adj_phase_kernel(const float2*
       const float2 vf = vs[kRow * k];
       q[k] = fmaf(vg[k].x, vf.y, fmaf(-vg[k].y, vf.x, q[k]));
     }
+    store_col<N2>(g + (arr * 2 + pol) * NP, n1, vg);  // g' in place of g
   }
   float* dq = tbar + arr * NP + n1;
 #pragma unroll
   for (int k = 0; k < N2; ++k) dq[kRow * k] = q[k];
 }
 
-// Adjoint of the rotation and intensity: with v = v' exp(+j theta),
+// Adjoint of the rotation and intensity, pointwise over time samples: with
+// v = v' exp(+j theta),
 //   g_v = g' exp(+j theta) + 2 p_bar v = exp(+j theta) (g' + 2 p_bar v'),
-// g' the inverse column pass of the adjoint state g, v' as written by
-// st_adj_phase_kernel; g_v (time samples) overwrites v' in vt.
-// st_col_forward_kernel then applies the forward column pass (the adjoint of
-// the inverse column pass that produced v) into g.
-template <int N2>
-__global__ __launch_bounds__(kColThreads) void st_adj_rotate_kernel(const float2* __restrict__ g,
-                                                                    float2* __restrict__ vt,
-                                                                    const float* __restrict__ th,
-                                                                    const float* __restrict__ pbar,
-                                                                    const float2* __restrict__ tw2, int nsb) {
-  constexpr int NP = kRow * N2;
-  constexpr int GROUPS = kRow / kColThreads;
-  const int i = blockIdx.x / GROUPS;
-  const int n1 = (blockIdx.x - i * GROUPS) * kColThreads + threadIdx.x;
-  const size_t arr = (size_t)blockIdx.y * nsb + i;
-  const float* ths = th + arr * NP + n1;
-  const float* pbs = pbar + arr * NP + n1;
-#pragma unroll 1
-  for (int pol = 0; pol < 2; ++pol) {
-    float2 vg[N2];
-    load_col<N2>(g + (arr * 2 + pol) * NP, n1, vg);
-    col_inverse<N2>(tw2, n1, vg);
-    float2* vs = vt + (arr * 2 + pol) * NP + n1;
-    // the inputs of 8 samples at a time are loaded together and every store
-    // waits until the column is done: stores count in the same in-order
-    // memory counter as loads, so a store between two loads would make the
-    // second one wait for it
-#pragma unroll
-    for (int k0 = 0; k0 < N2; k0 += 8) {
-      float t8[8], q8[8];
-      float2 f8[8];
-#pragma unroll
-      for (int j = 0; j < 8 && k0 + j < N2; ++j) {
-        t8[j] = ths[kRow * (k0 + j)];
-        q8[j] = 2.0f * pbs[kRow * (k0 + j)];
-        f8[j] = vs[kRow * (k0 + j)];
-      }
-#pragma unroll
-      for (int j = 0; j < 8 && k0 + j < N2; ++j) {
-        float sn, cs;
-        phase_sincos(t8[j], sn, cs);
-        const float2 u = make_float2(fmaf(q8[j], f8[j].x, vg[k0 + j].x), fmaf(q8[j], f8[j].y, vg[k0 + j].y));
-        vg[k0 + j] = cmul(u, make_float2(cs, sn));
-      }
-    }
-    store_col<N2>(vt + (arr * 2 + pol) * NP, n1, vg);
-  }
+// g' and v' as written by st_adj_phase_kernel (gt and vt); g_v overwrites v'
+// in vt.  st_col_forward_kernel then applies the forward column pass (the
+// adjoint of the inverse column pass that produced v).  Thread = one sample n
+// of one array (block, subband), both polarisations.
+__global__ __launch_bounds__(256) void st_adj_rotate_kernel(const float2* __restrict__ gt, float2* __restrict__ vt,
+                                                            const float* __restrict__ th,
+                                                            const float* __restrict__ pbar, int np,
+                                                            long long cells) {
+  const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (c >= cells) return;
+  const long long arr = c / np, n = c - arr * np;
+  float sn, cs;
+  phase_sincos(th[c], sn, cs);
+  const float p2 = 2.0f * pbar[c];
+  const size_t ox = (size_t)(arr * 2) * np + n, oy = ox + np;
+  const float2 gx = gt[ox], gy = gt[oy], vx = vt[ox], vy = vt[oy];
+  const float2 e = make_float2(cs, sn);
+  vt[ox] = cmul(make_float2(fmaf(p2, vx.x, gx.x), fmaf(p2, vx.y, gx.y)), e);
+  vt[oy] = cmul(make_float2(fmaf(p2, vy.x, gy.x), fmaf(p2, vy.y, gy.y)), e);
 }
 
 // Forward column pass of every column of src (time samples in the state
@@ -1101,6 +1076,7 @@ int bwd_wave(const StreamBwdCall& c, StreamArgs a) {
   const dim3 sb_grid(nsb * (kRow / kColThreads), a.nb);
   const dim3 cg_grid(a.np / kCgOut, a.nb);
   const size_t cg_lds = cg_lds_bytes(nsb, n_taps);
+  const long long cells = (long long)a.nb * nsb * a.np;
   StreamWsb wsb;
   for (int j = 0; j < kMaxSubbands; ++j) wsb.w[j] = tb.wsb[j];
   hipStream_t s = c.s;
@@ -1142,7 +1118,8 @@ int bwd_wave(const StreamBwdCall& c, StreamArgs a) {
       st_add_chunks_kernel<<<(per_step + 255) / 256, 256, 0, s>>>(c.csum(), per_step,
                                                                   c.acc_c() + (size_t)st * per_step);
       ok = ok && ok_launch();
-      st_adj_rotate_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(c.G(), c.V(), c.TH(st), a.th, a.tw2, nsb);
+      st_adj_rotate_kernel<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(c.G(), c.V(), c.TH(st), a.th, a.np,
+                                                                         cells);
       st_col_forward_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(c.V(), c.G(), a.tw2, nsb);
       ok = ok && ok_launch();
       if (st > 0) {
