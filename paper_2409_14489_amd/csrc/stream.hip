@@ -345,9 +345,10 @@ __host__ inline size_t fir_lds_bytes(int nsb, int tap_pad) {
   return sizeof(float) * (size_t)nsb * fir_row_width(tap_pad);
 }
 
+template <int NSB>
 __global__ __launch_bounds__(256) void st_fir_kernel(const float* __restrict__ pb, float* __restrict__ th,
-                                                     const float* __restrict__ cs, int nsb, int np, int nc,
-                                                     int tap_pad) {
+                                                     const float* __restrict__ cs, int np, int nc, int tap_pad) {
+  constexpr int nsb = NSB;
   extern __shared__ float fir_lds[];
   const int W = fir_row_width(tap_pad);
   const int n0 = blockIdx.x * kFirOut;
@@ -659,8 +660,10 @@ __host__ inline size_t cg_lds_bytes(int nsb, int n_taps) {
                           (npair > 256 ? 0 : (size_t)sh * npair * nsb));
 }
 
+template <int NSB>
 __global__ __launch_bounds__(256) void st_cgrad_kernel(const float* __restrict__ tbar, const float* __restrict__ pb,
-                                                       float* __restrict__ part, int nsb, int np, int n_taps) {
+                                                       float* __restrict__ part, int np, int n_taps) {
+  constexpr int nsb = NSB;
   extern __shared__ __align__(16) float cg_lds[];
   const int nc = n_taps / 2;
   const int pw = cg_pw(n_taps);
@@ -864,6 +867,51 @@ namespace {
 
 bool ok_launch() { return hipGetLastError() == hipSuccess; }
 
+// The coupled-filter kernels take the subband count as a template argument,
+// so their per-subband loops have no branches and their loads batch.
+template <int NSB>
+void fir_t(dim3 grid, size_t lds, hipStream_t s, const float* pb, float* th, const float* cs, int np, int nc,
+           int tap_pad) {
+  st_fir_kernel<NSB><<<grid, 256, lds, s>>>(pb, th, cs, np, nc, tap_pad);
+}
+bool launch_fir(int nsb, dim3 grid, hipStream_t s, const float* pb, float* th, const float* cs, int np, int nc,
+                int tap_pad) {
+  const size_t lds = fir_lds_bytes(nsb, tap_pad);
+  switch (nsb) {
+    case 1: fir_t<1>(grid, lds, s, pb, th, cs, np, nc, tap_pad); break;
+    case 2: fir_t<2>(grid, lds, s, pb, th, cs, np, nc, tap_pad); break;
+    case 3: fir_t<3>(grid, lds, s, pb, th, cs, np, nc, tap_pad); break;
+    case 4: fir_t<4>(grid, lds, s, pb, th, cs, np, nc, tap_pad); break;
+    case 5: fir_t<5>(grid, lds, s, pb, th, cs, np, nc, tap_pad); break;
+    case 6: fir_t<6>(grid, lds, s, pb, th, cs, np, nc, tap_pad); break;
+    case 7: fir_t<7>(grid, lds, s, pb, th, cs, np, nc, tap_pad); break;
+    case 8: fir_t<8>(grid, lds, s, pb, th, cs, np, nc, tap_pad); break;
+    default: return false;
+  }
+  return ok_launch();
+}
+template <int NSB>
+void cgrad_t(dim3 grid, size_t lds, hipStream_t s, const float* tbar, const float* pb, float* part, int np,
+             int n_taps) {
+  st_cgrad_kernel<NSB><<<grid, 256, lds, s>>>(tbar, pb, part, np, n_taps);
+}
+bool launch_cgrad(int nsb, dim3 grid, hipStream_t s, const float* tbar, const float* pb, float* part, int np,
+                  int n_taps) {
+  const size_t lds = cg_lds_bytes(nsb, n_taps);
+  switch (nsb) {
+    case 1: cgrad_t<1>(grid, lds, s, tbar, pb, part, np, n_taps); break;
+    case 2: cgrad_t<2>(grid, lds, s, tbar, pb, part, np, n_taps); break;
+    case 3: cgrad_t<3>(grid, lds, s, tbar, pb, part, np, n_taps); break;
+    case 4: cgrad_t<4>(grid, lds, s, tbar, pb, part, np, n_taps); break;
+    case 5: cgrad_t<5>(grid, lds, s, tbar, pb, part, np, n_taps); break;
+    case 6: cgrad_t<6>(grid, lds, s, tbar, pb, part, np, n_taps); break;
+    case 7: cgrad_t<7>(grid, lds, s, tbar, pb, part, np, n_taps); break;
+    case 8: cgrad_t<8>(grid, lds, s, tbar, pb, part, np, n_taps); break;
+    default: return false;
+  }
+  return ok_launch();
+}
+
 template <bool FWD, bool GVD, bool INV, bool CONJ = false>
 bool row(const StreamArgs& a, const float2* src, float2* dst, const float2* h, hipStream_t s) {
   st_row_kernel<FWD, GVD, INV, CONJ>
@@ -905,9 +953,8 @@ bool wave_step(const StreamArgs& a, const Tables& tb, const float* cpad, int st,
   bool ok = (st == 0 && nsb > 1) ? row<false, true, true>(a, src, work, h, s) : row<true, true, true>(a, src, work, h, s);
   st_intensity_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(work, a.pb, a.tw2, nsb);
   ok = ok && ok_launch();
-  st_fir_kernel<<<dim3(a.np / kFirOut, a.nb), 256, fir_lds_bytes(nsb, tap_pad), s>>>(
-      a.pb, theta, cpad + (size_t)st * nsb * nsb * tap_pad,
-                                                           nsb, a.np, n_taps / 2, tap_pad);
+  ok = ok && launch_fir(nsb, dim3(a.np / kFirOut, a.nb), s, a.pb, theta,
+                        cpad + (size_t)st * nsb * nsb * tap_pad, a.np, n_taps / 2, tap_pad);
   ok = ok && ok_launch();
   st_rotate_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(work, dst, theta, a.tw2, nsb);
   return ok && ok_launch();
@@ -1075,7 +1122,6 @@ int bwd_wave(const StreamBwdCall& c, StreamArgs a) {
   const dim3 col_grid((nsb * kRow + kColThreads - 1) / kColThreads, a.nb);
   const dim3 sb_grid(nsb * (kRow / kColThreads), a.nb);
   const dim3 cg_grid(a.np / kCgOut, a.nb);
-  const size_t cg_lds = cg_lds_bytes(nsb, n_taps);
   const long long cells = (long long)a.nb * nsb * a.np;
   StreamWsb wsb;
   for (int j = 0; j < kMaxSubbands; ++j) wsb.w[j] = tb.wsb[j];
@@ -1108,10 +1154,10 @@ int bwd_wave(const StreamBwdCall& c, StreamArgs a) {
                                                               nsb);
       ok = ok && ok_launch();
       // p_bar = C^T applied to theta_bar (transposed, tap-reversed rows)
-      st_fir_kernel<<<dim3(a.np / kFirOut, a.nb), 256, fir_lds_bytes(nsb, tap_pad), s>>>(
-          c.tbar(), a.th, p->d_ctpad + (size_t)st * per_step / n_taps * tap_pad, nsb, a.np, n_taps / 2, tap_pad);
+      ok = ok && launch_fir(nsb, dim3(a.np / kFirOut, a.nb), s, c.tbar(), a.th,
+                            p->d_ctpad + (size_t)st * per_step / n_taps * tap_pad, a.np, n_taps / 2, tap_pad);
       ok = ok && ok_launch();
-      st_cgrad_kernel<<<cg_grid, 256, cg_lds, s>>>(c.tbar(), a.pb, c.cpart(), nsb, a.np, n_taps);
+      ok = ok && launch_cgrad(nsb, cg_grid, s, c.tbar(), a.pb, c.cpart(), a.np, n_taps);
       ok = ok && ok_launch();
       st_sum_rows_kernel<<<dim3((per_step + kAccJ - 1) / kAccJ, kAccC), kAccJ * kAccG, 0, s>>>(
           c.cpart(), (int)(cg_grid.x * cg_grid.y), per_step, c.csum());
