@@ -55,6 +55,7 @@ sys.path.insert(0, ROOT)
 
 WORKLOAD = "5ch-64GBd-64QAM-2^16sym-15x80km"
 GRAD_WORKLOAD = "1ch-32GBd-16QAM-2^14sym-1x80km-15steps"
+CFG1_WORKLOAD = "1ch-32GBd-16QAM-2^14sym-1x80km"
 METRIC = "DBP 2D-symbols/s (all channels) + % HBM roofline; coeff-gradient steps/s at ≤1e-5 rel err"
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 vector (published)
@@ -164,6 +165,53 @@ def timed_events(stream, fn, reps):
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def host_identity():
+    """nproc and CPU model of the host the oracle is timed on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 1
+    return {"nproc": usable, "cpu_count": os.cpu_count(), "cpu_model": model}
+
+
+def time_oracle(run, min_s=10.0, max_passes=12):
+    """Runs run() until about min_s seconds of wall time have passed (at least
+    once); returns (passes, wall seconds, process seconds, first result)."""
+    passes, wall, proc, first = 0, 0.0, 0.0, None
+    while passes < 1 or (wall < min_s and passes < max_passes):
+        t0, p0 = time.perf_counter(), time.process_time()
+        out = run()
+        wall += time.perf_counter() - t0
+        proc += time.process_time() - p0
+        first = out if first is None else first
+        passes += 1
+    return passes, wall, proc, first
+
+
+def worst_block_err(got, ref, hop, block, n_ov):
+    """Largest relative L2 error over the kept output segments of the
+    overlap-and-save blocks (both polarisations)."""
+    import numpy as np
+    t_len = got.shape[-1]
+    worst = 0.0
+    for s in range(0, t_len, hop):
+        e = min(s + hop, t_len)
+        r = ref[..., s:e]
+        den = float(np.sum(np.abs(r) ** 2))
+        if den > 0:
+            worst = max(worst, (float(np.sum(np.abs(got[..., s:e] - r) ** 2)) / den) ** 0.5)
+    return worst
 
 
 # ------------------------------------------------------------------ primary: 5-channel forward
@@ -287,20 +335,15 @@ def leg_forward(args):
             den += float(np.sum(np.abs(r) ** 2))
         result["dual_pol_nlpr"]["parity_rel_l2_sampled"] = (num / den) ** 0.5
         result["dual_pol_nlpr"]["parity_blocks"] = pick
-        passes, cpu_s, proc_s, ref = 0, 0.0, 0.0, None
-        while passes < 1 or (cpu_s < 10.0 and passes < 12):
-            t0, p0 = time.perf_counter(), time.process_time()
-            out = oracle.run(x, oplan)
-            cpu_s += time.perf_counter() - t0
-            proc_s += time.process_time() - p0
-            ref = out if ref is None else ref
-            passes += 1
+        passes, cpu_s, proc_s, ref = time_oracle(lambda: oracle.run(x, oplan))
         got = yout.cpu().numpy().astype(np.complex128)
         result["parity_rel_l2"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        result["parity_rel_l2_worst_block"] = worst_block_err(got, ref, plan.hop, plan.block, d["n_overlap"])
         result["cpu_baseline"] = {"value": n2d * passes / cpu_s, "unit": "2D-symbols/s",
                                   "cores": max(1, round(proc_s / cpu_s)), "kind": "oracle",
                                   "sample": f"the whole workload ({nblk} blocks), {passes} passes of the FP64 "
-                                            f"numpy oracle, {cpu_s:.1f} s"}
+                                            f"numpy oracle, {cpu_s:.1f} s",
+                                  **host_identity()}
         all_cores = oracle_all_cores(x, oplan, n2d)
         if all_cores is not None:
             result["cpu_baseline_all_cores"] = all_cores
@@ -753,37 +796,204 @@ def leg_streamgrad(args):
     return out
 
 
+def leg_cfg1(args):
+    """The single-channel workload (1 ch 32 GBd DP-16QAM, 2^14 symbols, 1 x 80 km,
+    1 step, 11 taps, N' = 1024, N_ov = 128): forward throughput from graph
+    replays, full-field parity and the oracle timed on the same field."""
+    import numpy as np
+    import torch
+    from paper_2409_14489_amd import Plan, analytic_coeffs
+    from synth import workload
+
+    x, _, w = workload(CFG1_WORKLOAD, 1001)
+    d, wdm, ch = w["dbp"], w["wdm"], w["ch"]
+    link = link_of(ch, wdm.sample_rate)
+    coeffs = analytic_coeffs(link, d["n_sb"], d["n_steps"], d["rho"], d["n_taps"]).astype(np.float32)
+    plan = Plan(link, d["n_sb"], d["n_sub"], d["n_overlap"], d["n_steps"], d["rho"], coeffs=coeffs)
+    xin = torch.from_numpy(x.astype(np.complex64)).cuda()
+    yout = torch.empty_like(xin)
+    for _ in range(5):
+        plan.run(xin, out=yout)
+    per_graph = 20
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for _ in range(per_graph):
+            plan.run(xin, out=yout)
+    graph.replay()
+    stream = torch.cuda.current_stream()
+    run_s = timed_events(stream, graph.replay, 20) / per_graph
+    if plan.status() != 0:
+        raise RuntimeError("device error flag set in the single-channel leg")
+    del graph
+    n2d = wdm.n_channels * 2 * wdm.n_symbols
+    t_len = x.shape[-1]
+    nblk = plan.n_blocks(t_len)
+    flops = algorithmic_flops_per_block(d["n_sb"], d["n_sub"], d["n_steps"], d["n_taps"]) * nblk
+    out = {"workload": CFG1_WORKLOAD, "T": t_len, "blocks": nblk, "value": n2d / run_s, "unit": "2D-symbols/s",
+           "ms_per_run": run_s * 1e3, "flops_per_run": flops, "tflops": flops / run_s / 1e12,
+           "hbm_gbs_algorithmic": 2 * 2 * t_len * 8 / run_s / 1e9,
+           "launch": f"HIP graph replays, {per_graph} launches per replay"}
+    if not args.no_cpu:
+        import oracle
+        oplan = oracle_plan(d, wdm.sample_rate, ch.span_km * ch.n_spans / d["n_steps"], coeffs, ch.beta2_ps2_km)
+        passes, cpu_s, proc_s, ref = time_oracle(lambda: oracle.run(x, oplan), min_s=5.0)
+        got = yout.cpu().numpy().astype(np.complex128)
+        out["parity_rel_l2"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        out["parity_rel_l2_worst_block"] = worst_block_err(got, ref, plan.hop, plan.block, d["n_overlap"])
+        out["cpu_baseline"] = {"value": n2d * passes / cpu_s, "unit": "2D-symbols/s",
+                               "cores": max(1, round(proc_s / cpu_s)), "kind": "oracle",
+                               "sample": f"the whole field, {passes} passes, {cpu_s:.1f} s", **host_identity()}
+    plan.close()
+    return out
+
+
+def leg_cover(args):
+    """The five-channel 15 x 80 km field backpropagated with an overlap that
+    covers the link's group-delay spread 2 pi |beta2| L R^2 (6.7e4 samples at
+    640 GS/s, Sec. III-A): 5 subbands of N' = 2^15 (N = 163840, streaming
+    path), N_ov = 67584, 15 steps, 21 analytic taps.  The primary line keeps
+    the workload's literal N' = 4096 / N_ov = 2560 framing; this leg gives the
+    throughput of a framing that undoes the whole dispersion memory, its SNR
+    beside the literal framing's, and sampled oracle parity."""
+    import numpy as np
+    import torch
+    from paper_2409_14489_amd import Plan, analytic_coeffs
+    from paper_2409_14489_amd.train import SymbolReceiver, receiver_mse
+    from synth import workload
+
+    x, syms, w = workload(WORKLOAD, 2001, steps_per_span=GEN_STEPS_PER_SPAN)
+    d, wdm, ch = w["dbp"], w["wdm"], w["ch"]
+    link = link_of(ch, wdm.sample_rate)
+    spread = 2 * math.pi * abs(ch.beta2_ps2_km) * 1e-24 * ch.span_km * ch.n_spans * wdm.sample_rate ** 2
+    n_sub, n_ov = 2 ** 15, 2 * int(math.ceil(spread / 2 / 512.0)) * 512
+    coeffs = analytic_coeffs(link, d["n_sb"], d["n_steps"], d["rho"], d["n_taps"]).astype(np.float32)
+    xin = torch.from_numpy(x.astype(np.complex64)).cuda()
+    t_len = x.shape[-1]
+    n2d = wdm.n_channels * 2 * wdm.n_symbols
+    p_w = 1e-3 * 10 ** (wdm.power_dbm_per_channel / 10)
+    offsets = (np.arange(wdm.n_channels) - (wdm.n_channels - 1) / 2.0) * wdm.spacing
+    rxs = [SymbolReceiver(t_len, wdm.sample_rate, wdm.baud, wdm.rolloff, p_w, offset_hz=float(off))
+           for off in offsets]
+    sym = [torch.from_numpy(syms[c].astype(np.complex64)).cuda() for c in range(wdm.n_channels)]
+    stream = torch.cuda.current_stream()
+    out = {"workload": WORKLOAD, "group_delay_spread_samples": spread, "unit": "2D-symbols/s"}
+    for name, nsub, nov in (("covering", n_sub, n_ov), ("literal", d["n_sub"], d["n_overlap"])):
+        plan = Plan(link, d["n_sb"], nsub, nov, d["n_steps"], d["rho"], coeffs=coeffs)
+        y = torch.empty_like(xin)
+        for _ in range(2):
+            plan.run(xin, out=y)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            plan.run(xin, out=y)
+        graph.replay()
+        run_s = timed_events(stream, graph.replay, 10)
+        if plan.status() != 0:
+            raise RuntimeError("device error flag set in the covering-overlap leg")
+        del graph
+        snr = [-10 * math.log10(float(receiver_mse(y, rx, s))) for rx, s in zip(rxs, sym)]
+        row = {"block_sb": nsub, "overlap": nov, "blocks": plan.n_blocks(t_len), "ms_per_run": run_s * 1e3,
+               "value": n2d / run_s, "snr_db_central": snr[len(snr) // 2], "snr_db_per_channel": snr}
+        if name == "covering" and not args.no_cpu:
+            import oracle
+            oplan = oracle.OraclePlan(ch.beta2_ps2_km * 1e-24, wdm.sample_rate, ch.span_km * ch.n_spans /
+                                      d["n_steps"], d["n_steps"], d["rho"], d["n_sb"], d["n_sb"] * nsub, nov,
+                                      np.asarray(coeffs, np.float64))
+            pick = [plan.n_blocks(t_len) // 2]
+            ref = oracle.run_blocks(x, oplan, pick)
+            got = y.cpu().numpy().astype(np.complex128)
+            num = den = 0.0
+            for b, r in ref.items():
+                seg = got[:, b * plan.hop:b * plan.hop + r.shape[-1]]
+                r = r[:, :seg.shape[-1]]
+                num += float(np.sum(np.abs(seg - r) ** 2))
+                den += float(np.sum(np.abs(r) ** 2))
+            row["parity_rel_l2_sampled"] = (num / den) ** 0.5
+            row["parity_blocks"] = pick
+        out[name] = row
+        plan.close()
+    out["value"] = out["covering"]["value"]
+    out["ms_per_run"] = out["covering"]["ms_per_run"]
+    return out
+
+
+HEADLINE_KEYS = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+                 "scaling", "vs_baseline", "dtype", "data")
+
+
+def headline(result):
+    """The compact record of the primary workload (the bench's last line)."""
+    line = {k: result[k] for k in HEADLINE_KEYS if k in result}
+    cfg = result["config"]
+    line["config"] = {k: cfg[k] for k in ("workload", "T", "batch", "n_sb", "block_sb", "overlap", "steps",
+                                          "split_ratio", "n_taps", "fir_mode", "blocks", "kernel") if k in cfg}
+    line["config"]["fwd_kernel_source_sha256"] = cfg.get("fwd_kernel_source_sha256", "")[:16]
+    rf = result["roofline"]
+    line["roofline"] = {k: rf.get(k) for k in ("bound", "achieved", "peak", "unit", "frac", "traffic",
+                                               "flops_per_launch", "kernel_ms")}
+    line["hbm_roofline"] = {k: result["hbm_roofline"][k] for k in ("achieved", "peak", "unit", "frac")}
+    if "cpu_baseline" in result:
+        line["cpu_baseline"] = result["cpu_baseline"]
+    for k in ("parity_rel_l2", "parity_rel_l2_worst_block"):
+        if k in result:
+            line[k] = result[k]
+    g = result.get("grad")
+    if g:
+        line["grad"] = {"steps_per_s": g.get("value"), "unit": "steps/s", "workload": g.get("workload"),
+                        "parity_rel_l2": g.get("parity_rel_l2")}
+    c1 = result.get("cfg1")
+    if c1:
+        line["cfg1"] = {"value": c1["value"], "ms_per_run": c1["ms_per_run"],
+                        "parity_rel_l2": c1.get("parity_rel_l2"),
+                        "cpu_baseline": (c1.get("cpu_baseline") or {}).get("value")}
+    b = result.get("batched")
+    if b:
+        line["batched"] = {"value": b["value"], "speedup_vs_separate": b["speedup_vs_separate"],
+                           "launches_per_run": b["launches_per_run"],
+                           "instances_overlap_covers_memory": b["instances_overlap_covers_memory"]}
+    line["legs_file"] = result.get("legs_file")
+    return line
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--legs", default="fwd,grad,batched,protocol,longlink,streamgrad")
+    ap.add_argument("--legs", default="cfg1,grad,cover,batched,protocol,longlink,streamgrad")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0)
     ap.add_argument("--proto-iters", type=int, default=60)
     ap.add_argument("--fit-iters", type=int, default=20)
+    ap.add_argument("--out", default=os.path.join("gpurun_out", "bench_legs.json"),
+                    help="file that receives every leg's full record")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
               "(the path would shard over blocks and batch instances, one process per GPU)", file=sys.stderr)
         sys.exit(2)
-    legs = set(args.legs.split(","))
+    legs = [leg for leg in args.legs.split(",") if leg]
 
     import torch
     torch.cuda.set_device(0)
     result = leg_forward(args)
-    if "grad" in legs:
-        result["grad"] = leg_grad(args)
-    if "batched" in legs:
-        result["batched"] = leg_batched(args)
-    if "protocol" in legs:
-        result["protocol"] = leg_protocol(args)
-    if "longlink" in legs:
-        result["longlink"] = leg_longlink(args)
-    if "streamgrad" in legs:
-        result["streamgrad"] = leg_streamgrad(args)
-    print(json.dumps(result), flush=True)
+    print(json.dumps({"leg": "fwd", "value": result["value"], "ms_per_step": result["ms_per_step"],
+                      "roofline_frac": result["roofline"]["frac"]}), flush=True)
+    runners = {"cfg1": leg_cfg1, "grad": leg_grad, "batched": leg_batched, "protocol": leg_protocol,
+               "longlink": leg_longlink, "streamgrad": leg_streamgrad, "cover": leg_cover}
+    for leg in legs:
+        if leg not in runners:
+            raise SystemExit(f"unknown leg {leg!r}")
+        result[leg] = runners[leg](args)
+        # one short line per leg as it ends (the full record goes to --out)
+        rec = result[leg]
+        brief = {"leg": leg, **{k: rec[k] for k in ("value", "unit", "ms_per_run", "parity_rel_l2") if k in rec}}
+        print(json.dumps(brief)[:1500], flush=True)
+    if args.out:
+        os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+        with open(args.out, "w") as fh:
+            json.dump(result, fh, indent=1)
+        result["legs_file"] = args.out
+    print(json.dumps(headline(result)), flush=True)
 
 
 if __name__ == "__main__":
