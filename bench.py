@@ -434,14 +434,33 @@ def leg_grad(args):
     if not args.no_cpu:
         from oracle.grad import vjp
         oplan = oracle_plan(d, wdm.sample_rate, ch.span_km * ch.n_spans / d["n_steps"], c0, ch.beta2_ps2_km)
+        # the gradient the fit uses: cotangent of the phase-aligned symbol MSE
+        # (matched filter, symbol sampling) at the analytic coefficients, all
+        # 16 realisations
+        y = plan.run(x).detach().requires_grad_(True)
+        gmse, = torch.autograd.grad(phase_aligned_mse(rx(y), s), y)
+        gmse = gmse.contiguous()
+        gi, gc, gr = plan.backward(x, gmse)
+        torch.cuda.synchronize()
+        xs64 = np.stack(fields).astype(np.complex64).astype(np.complex128)
+        ogi, ogc, ogr = vjp(xs64, oplan, gmse.cpu().numpy().astype(np.complex128))
+        out["parity_rel_l2"] = {
+            "grad_c": float(np.linalg.norm(gc.cpu().numpy() - ogc) / np.linalg.norm(ogc)),
+            "grad_in": float(np.linalg.norm(gi.cpu().numpy() - ogi) / np.linalg.norm(ogi)),
+            "grad_rho_vs_oracle": float(abs(float(gr) - ogr) / abs(ogr)),
+            "cotangent": "phase-aligned symbol MSE, 16 realisations",
+        }
+        # stress case: a white random cotangent on one realisation, whose
+        # out-of-band part the FP32 state resolves least well
         gi, gc, gr = plan.backward(x[:1], g[:1])
         torch.cuda.synchronize()
         ogi, ogc, ogr = vjp(fields[0].astype(np.complex64).astype(np.complex128), oplan,
                             g[0].cpu().numpy().astype(np.complex128))
-        out["parity_rel_l2"] = {
+        out["parity_rel_l2_white_cotangent"] = {
             "grad_c": float(np.linalg.norm(gc.cpu().numpy() - ogc) / np.linalg.norm(ogc)),
             "grad_in": float(np.linalg.norm(gi[0].cpu().numpy() - ogi) / np.linalg.norm(ogi)),
             "grad_rho_vs_oracle": float(abs(float(gr) - ogr) / abs(ogr)),
+            "cotangent": "white Gaussian, std 1e-2, realisation 0",
         }
     out["value"] = out["store_every_step"]["steps_per_s"]
     plan.close()

@@ -13,19 +13,34 @@
 //   g_w = IDFT(g_S),  theta_bar = sum_pol Im(conj(g_w) w),
 //   p_bar_l = sum_i C_s[i][l] (x) theta_bar_i   (correlation: taps reversed),
 //   g_v = g_w exp(+j theta) + 2 p_bar v,  g_A = DFT(g_v),  g_{S_{s-1}} = conj(h_s) g_A,
-//   dL/dC_s[i][l][tau] = sum_k theta_bar_i[k] p_l[(k - tau + Nc) mod N'],
-//   dL/drho = L sum_q phi_q [Im(conj(g_A1) A1) - Im(conj(g_B) B)],
-// with phi_q = 2 pi^2 beta2 f_q^2, A1 the first post-GVD spectrum and B the
-// spectrum after the last GVD.  With free dispersion segments (lengths d_j,
-// j = 0 .. N_st), dL/dd_j = -sum_q phi_q Im(conj(g_{A_j}) A_j), A_j the
-// spectrum after segment j (A_{N_st} = B); A_j for 0 < j < N_st is the DFT of
-// the stored v of step j + 1.  The block's output stage (MUX, inverse size-N
-// DFT) is adjoint to its input stage and vice versa, so both are reused.
+//   dL/dC_s[i][l][tau] = sum_k theta_bar_i[k] p_l[(k - tau + Nc) mod N'].
+// Dispersion segment j (lengths d_0 = (1 - rho) L, d_1 .. d_{N_st-1} = L,
+// d_{N_st} = rho L, Sec. III-C) contributes dL/dd_j = -G_j with
+// G_j = sum_q phi_q Im(conj(g_{A_j}) A_j), phi_q = 2 pi^2 beta2 f_q^2 per km and
+// A_j the spectrum after segment j.  The split ratio moves length from the
+// first segment to the last, dL/drho = L (G_0 - G_{N_st}); G_0 and G_{N_st}
+// are each up to hundreds of times larger than their difference, which FP32
+// state cannot resolve.  Telescoping over the steps instead, with
+// e = exp(-j theta) - 1 (formed as (-2 sin^2(theta/2), -sin theta)),
+// D = DFT(e v) and E = DFT(dg), dg = conj(e) g_w + 2 p_bar v:
+//   G_s - G_{s-1} = sum_q phi'_q [Im(conj(g_S) D) - Im(conj(E) A)],
+// over both polarisations and the subbands, phi'_q = phi_q - phi(f_i) (a
+// constant per subband changes nothing: the rotation commutes with it).  This
+// is the commutator of the dispersion operator with the step's rotation, in
+// the frequency domain (Parseval); D and E are transforms of the small
+// differences w - v = e v and g_v - g_w = dg, so both terms scale with the
+// nonlinear phase and vanish with C, and
+//   dL/drho = -L sum_s (G_s - G_{s-1})
+// keeps the relative accuracy of the FP32 state.  The reverse step then needs
+// no extra transform: g_A = DFT(g_w + dg) = N' g_S + E.  With free dispersion
+// segments dL/dd_j is written as well: A_j for 0 < j < N_st is the DFT of the
+// stored v of step j + 1.  The block's output stage (MUX, inverse size-N DFT)
+// is adjoint to its input stage and vice versa, so both are reused.
 //
-// The reverse step needs v and theta of its forward step.  The forward sweep
-// stores the spectrum S_s at the start of every segment of `ck_every` steps,
-// and (v, theta) of every step of the last segment; the reverse sweep
-// recomputes each earlier segment once from its spectrum, storing (v, theta)
+// The reverse step needs v, theta, A and D of its forward step.  The forward
+// sweep stores the spectrum S_s at the start of every segment of `ck_every`
+// steps, and (v, theta, A, D) of every step of the last segment; the reverse
+// sweep recomputes each earlier segment once from its spectrum, storing them
 // per step, and then runs that segment's reverse steps on them (one level of
 // Griewank-style checkpointing; with a single segment nothing is recomputed).
 // Coefficient and split-ratio partials are written per block and reduced over
@@ -61,7 +76,10 @@ __device__ __forceinline__ void load_state(const float2* st, float2 (&x)[FftShap
   }
 }
 
-// (v, theta) of one step: v_x, v_y (N' complex each) then theta (N' floats).
+// Stored record of one step: v_x, v_y (N' complex each), theta (N' floats),
+// then the spectra A_x, A_y, D_x, D_y (N' complex each): kVtFloats N' floats.
+constexpr int kVtFloats = 13;
+
 template <int N>
 __device__ __forceinline__ void store_vtheta(float* st, const float2 (&x)[FftShape<N>::RR],
                                              const float2 (&y)[FftShape<N>::RR], const float (&th)[FftShape<N>::RR],
@@ -226,6 +244,23 @@ __device__ __forceinline__ double rho_term(const double* __restrict__ phase_km, 
   return acc;
 }
 
+// exp(-j theta) - 1 with both parts accurate for small theta:
+// cos theta - 1 = -2 sin^2(theta / 2), sin theta = 2 sin(theta / 2) cos(theta / 2).
+__device__ __forceinline__ float2 rot_minus_one(float th) {
+  float sh, ch;
+  phase_sincos(0.5f * th, sh, ch);
+  return make_float2(-2.0f * sh * sh, -2.0f * sh * ch);
+}
+
+// phi'_q = phi_q - phi(f_i) of owned bin t + NT o: the member's phase table
+// relative to its centre bin N'/2.
+template <int N>
+__device__ __forceinline__ float phase_rel(const double* __restrict__ phase_km, int t, int o) {
+  return (float)(phase_km[t + FftShape<N>::NT * o] - phase_km[N / 2]);
+}
+
+__device__ __forceinline__ float im_conj_mul(float2 a, float2 b) { return fmaf(a.x, b.y, -a.y * b.x); }
+
 template <int LOGN>
 __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdArgs a) {
   constexpr int N = 1 << LOGN;  // N'
@@ -252,11 +287,12 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdAr
   const int tap_pad = kTapChunk * a.n_chunks;
   const int k = a.ck_every;
   const size_t spec_sz = (size_t)2 * N;  // one member's spectra, two polarisations (float2)
-  const size_t vt_sz = (size_t)5 * N;    // one member's (v, theta), floats
+  const size_t vt_sz = (size_t)kVtFloats * N;  // one member's (v, theta, K v), floats
   float2* team_spec = a.spec + (size_t)c.team * a.n_ck * nsb * spec_sz;
   float* team_vt = a.vtheta + (size_t)c.team * k * nsb * vt_sz;
   auto sp = [&](int slot) { return team_spec + ((size_t)slot * nsb + me) * spec_sz; };
   auto vt = [&](int slot) { return team_vt + ((size_t)slot * nsb + me) * vt_sz; };
+  float2* gsv = a.gsave + ((size_t)c.team * nsb + me) * 2 * N;  // reused by every reverse step
   const int last0 = (a.n_ck - 1) * k;  // first step of the last segment
   uint64_t* xs_a = a.xspec + ((size_t)c.team * 2 + 0) * nsb * 4 * N;
   uint64_t* xs_b = a.xspec + ((size_t)c.team * 2 + 1) * nsb * 4 * N;
@@ -278,6 +314,14 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdAr
     auto forward_step = [&](int s, float* dst, bool tail) {
       t = opaque_tid();
       apply_diag<N, false>(x, y, step_gvd(a.tab, s) + (size_t)me * N, t);
+      float2* rec = dst != nullptr ? reinterpret_cast<float2*>(dst + 5 * N) : nullptr;  // A, then D
+      if (dst != nullptr) {
+#pragma unroll
+        for (int o = 0; o < RR; ++o) {
+          rec[t + NT * o] = x[o];
+          rec[N + t + NT * o] = y[o];
+        }
+      }
       fft<N, true>(x, y, lxy, tw, t);
       float p[RR], theta[RR];
       intensity<N>(x, y, p);
@@ -285,7 +329,24 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdAr
       coupled_fir<N>(c, a.tab.cpad + ((size_t)(s * nsb + me) * nsb) * tap_pad, xrow, rnd, p, theta, lf);
       ++rnd;
       ++np;
-      if (dst != nullptr) store_vtheta<N>(dst, x, y, theta, opaque_tid());
+      if (dst != nullptr) {
+        t = opaque_tid();
+        store_vtheta<N>(dst, x, y, theta, t);
+        // D = DFT(e v), the transform of w - v
+        float2 dx[RR], dy[RR];
+#pragma unroll
+        for (int o = 0; o < RR; ++o) {
+          const float2 e = rot_minus_one(theta[o]);
+          dx[o] = cmul(e, x[o]);
+          dy[o] = cmul(e, y[o]);
+        }
+        fft<N, false>(dx, dy, lxy, tw, t);
+#pragma unroll
+        for (int o = 0; o < RR; ++o) {
+          rec[2 * N + t + NT * o] = dx[o];
+          rec[3 * N + t + NT * o] = dy[o];
+        }
+      }
       if (tail) {
         rotate<N, -1>(x, y, theta);
         fft<N, false>(x, y, lxy, tw, t);
@@ -309,14 +370,11 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdAr
     gather_block<N, true>(go_x, go_x + T, blk, a.hop, a.n_ov, T, a.boundary, nsb, me, t, gx, gy);
     fft<N, false>(gx, gy, lxy, tw, t);
     polyphase_to_subband<N>(c, xs_b, rnd++, t, gx, gy);  // g_B
-    {
-      const double tb = rho_term<N>(phase_km, 1.0, t, gx, gy, x, y);
-      rho_acc -= a.L * tb;
+    if (a.lpart != nullptr) {
       // dL/d(length of the last dispersion segment) = -sum phi Im(conj(g_B) B)
-      if (a.lpart != nullptr) {
-        const double tot = block_sum<NW>(-tb, rho_red, t);
-        if (t == 0) a.lpart[((size_t)item * nsb + me) * (a.steps + 1) + a.steps] = tot;
-      }
+      const double tb = rho_term<N>(phase_km, 1.0, t, gx, gy, x, y);
+      const double tot = block_sum<NW>(-tb, rho_red, t);
+      if (t == 0) a.lpart[((size_t)item * nsb + me) * (a.steps + 1) + a.steps] = tot;
     }
     apply_diag<N, true>(gx, gy, a.tab.h_last + (size_t)me * N, t);  // g_{S_Nst}
 
@@ -332,6 +390,13 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdAr
         t = opaque_tid();
         const float2* hs = step_gvd(a.tab, s - 1) + (size_t)me * N;
         float p[RR], theta[RR], tbar[RR];
+        const float2* rec = reinterpret_cast<const float2*>(vt(s - 1 - s0) + 5 * N);  // A, D of step s
+        // keep g_S for g_A = N' g_S + E and the split-ratio terms
+#pragma unroll
+        for (int o = 0; o < RR; ++o) {
+          gsv[t + NT * o] = gx[o];
+          gsv[N + t + NT * o] = gy[o];
+        }
         load_vtheta<N>(vt(s - 1 - s0), x, y, theta, t);  // v, theta of step s
         intensity<N>(x, y, p);
         // republish p for the coefficient gradient of the other members
@@ -359,27 +424,36 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdAr
         uint64_t* qrow = a.xq + ((size_t)c.team * 2 + (nq & 1u)) * nsb * N;
         ++nq;
         coupled_fir<N>(c, a.ctpad + ((size_t)((s - 1) * nsb + me) * nsb) * tap_pad, qrow, rnd++, tbar, pbar, lf);
-        // g_v = g_w exp(+j theta) + 2 p_bar v
-        rotate<N, +1>(gx, gy, theta);
+        // g_v = g_w exp(+j theta) + 2 p_bar v = g_w + dg, dg = conj(e) g_w + 2 p_bar v
 #pragma unroll
         for (int o = 0; o < RR; ++o) {
-          gx[o] = make_float2(fmaf(2.0f * pbar[o], x[o].x, gx[o].x), fmaf(2.0f * pbar[o], x[o].y, gx[o].y));
-          gy[o] = make_float2(fmaf(2.0f * pbar[o], y[o].x, gy[o].x), fmaf(2.0f * pbar[o], y[o].y, gy[o].y));
+          const float2 e = rot_minus_one(theta[o]);
+          const float p2 = 2.0f * pbar[o];
+          gx[o] = make_float2(fmaf(p2, x[o].x, fmaf(e.x, gx[o].x, e.y * gx[o].y)),
+                              fmaf(p2, x[o].y, fmaf(e.x, gx[o].y, -e.y * gx[o].x)));
+          gy[o] = make_float2(fmaf(p2, y[o].x, fmaf(e.x, gy[o].x, e.y * gy[o].y)),
+                              fmaf(p2, y[o].y, fmaf(e.x, gy[o].y, -e.y * gy[o].x)));
         }
-        fft<N, false>(gx, gy, lxy, tw, t);  // g_A
-        if (s == 1) {                          // first GVD depends on rho
-          load_state<N>(sp(0), x, y, t);
-          apply_diag<N, false>(x, y, hs, t);  // A1
-          const double ta = rho_term<N>(phase_km, 1.0, t, gx, gy, x, y);
-          rho_acc += a.L * ta;
-          if (a.lpart != nullptr) {
-            const double tot = block_sum<NW>(-ta, rho_red, t);
-            if (t == 0) a.lpart[((size_t)item * nsb + me) * (a.steps + 1)] = tot;
+        fft<N, false>(gx, gy, lxy, tw, t);  // E = DFT(dg)
+        // split-ratio terms sum phi' [Im(conj(g_S) D) - Im(conj(E) A)]; g_A = N' g_S + E
+#pragma unroll
+        for (int o = 0; o < RR; ++o) {
+          const float w = phase_rel<N>(phase_km, t, o);
+          const float2 sx = gsv[t + NT * o], sy = gsv[N + t + NT * o];
+          const float im = im_conj_mul(sx, rec[2 * N + t + NT * o]) + im_conj_mul(sy, rec[3 * N + t + NT * o]) -
+                           im_conj_mul(gx[o], rec[t + NT * o]) - im_conj_mul(gy[o], rec[N + t + NT * o]);
+          rho_acc -= a.L * (double)(w * im);
+          gx[o] = make_float2(fmaf((float)N, sx.x, gx[o].x), fmaf((float)N, sx.y, gx[o].y));
+          gy[o] = make_float2(fmaf((float)N, sy.x, gy[o].x), fmaf((float)N, sy.y, gy[o].y));
+        }
+        if (a.lpart != nullptr) {  // dL/d(length of segment s - 1) = -sum phi Im(conj(g_A) A)
+          float2 ax[RR], ay[RR];
+#pragma unroll
+          for (int o = 0; o < RR; ++o) {
+            ax[o] = rec[t + NT * o];
+            ay[o] = rec[N + t + NT * o];
           }
-        } else if (a.lpart != nullptr) {
-          // A_s = DFT(v_s) / N' (v_s is the unscaled inverse DFT of A_s)
-          fft<N, false>(x, y, lxy, tw, t);
-          const double ta = rho_term<N>(phase_km, 1.0 / (double)N, t, gx, gy, x, y);
+          const double ta = rho_term<N>(phase_km, 1.0, t, gx, gy, ax, ay);
           const double tot = block_sum<NW>(-ta, rho_red, t);
           if (t == 0) a.lpart[((size_t)item * nsb + me) * (a.steps + 1) + (s - 1)] = tot;
         }
@@ -562,7 +636,8 @@ BwdLayout bwd_layout(const cbessfm_plan_t* p, long long T, int batch, int ck_eve
   const size_t nsb = p->sb.n_sb;
   L.spec_off = 0;
   L.vtheta_off = up(L.spec_off + sizeof(float2) * (size_t)L.n_teams * L.n_ck * nsb * 2 * p->Np);
-  L.cpart_off = up(L.vtheta_off + sizeof(float) * (size_t)L.n_teams * L.k * nsb * 5 * p->Np);
+  L.gsave_off = up(L.vtheta_off + sizeof(float) * (size_t)L.n_teams * L.k * nsb * kVtFloats * p->Np);
+  L.cpart_off = up(L.gsave_off + sizeof(float2) * (size_t)L.n_teams * nsb * 2 * p->Np);
   L.rpart_off = up(L.cpart_off + sizeof(float) * (size_t)L.n_items * p->steps * nsb * nsb * p->n_taps);
   L.lpart_off = up(L.rpart_off + sizeof(double) * (size_t)L.n_items * nsb);
   L.gin_off = up(L.lpart_off + sizeof(double) * (size_t)L.n_items * nsb * (p->steps + 1));
@@ -602,6 +677,7 @@ int launch_backward(cbessfm_plan_t* p, const void* field_in, const void* grad_ou
   a.xq = p->d_xq;
   a.spec = reinterpret_cast<float2*>(ws + L.spec_off);
   a.vtheta = reinterpret_cast<float*>(ws + L.vtheta_off);
+  a.gsave = reinterpret_cast<float2*>(ws + L.gsave_off);
   a.cpart = reinterpret_cast<float*>(ws + L.cpart_off);
   a.rpart = reinterpret_cast<double*>(ws + L.rpart_off);
   a.lpart = grad_gvd ? reinterpret_cast<double*>(ws + L.lpart_off) : nullptr;

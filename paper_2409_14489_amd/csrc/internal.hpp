@@ -118,7 +118,7 @@ struct StreamArgs {
 struct StreamBwdLayout {
   int k, n_ck, nblk, nb;
   size_t state;
-  size_t ck_off, slot_off, work_off, g_off, v_off, theta_off, tbar_off, cpart_off, rpart_off, accc_off, acct_off,
+  size_t ck_off, slot_off, work_off, g_off, v_off, kg_off, theta_off, tbar_off, cpart_off, rpart_off, accc_off, acct_off,
       csum_off, gin_off, bytes;
 };
 
@@ -140,7 +140,8 @@ struct BwdArgs {
   uint64_t* xp;         // tagged intensity rows
   uint64_t* xq;         // tagged theta_bar rows, [team_capacity][2][n_sb][N']
   float2* spec;         // [n_teams][n_ck][n_sb][2][N'] spectrum at each segment start
-  float* vtheta;        // [n_teams][ck_every][n_sb][5 N'] (v_x, v_y, theta) of a segment's steps
+  float* vtheta;        // [n_teams][ck_every][n_sb][13 N'] (v_x, v_y, theta, A, D) of a segment's steps
+  float2* gsave;        // [n_teams][n_sb][2 N'] the incoming g_S of the reverse step
   float* cpart;         // [n_items][steps][n_sb][n_sb][n_taps]
   double* rpart;        // [n_items][n_sb]
   double* lpart;        // [n_items][n_sb][steps + 1] dispersion-segment partials, or null
@@ -151,7 +152,7 @@ struct BwdArgs {
 // Workspace layout of one adjoint call.
 struct BwdLayout {
   int k, n_ck, nblk, n_items, n_teams;
-  size_t spec_off, vtheta_off, cpart_off, rpart_off, lpart_off, gin_off, bytes;
+  size_t spec_off, vtheta_off, gsave_off, cpart_off, rpart_off, lpart_off, gin_off, bytes;
 };
 
 }  // namespace cbessfm

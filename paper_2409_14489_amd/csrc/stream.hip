@@ -35,6 +35,8 @@
 // order, built from the same column/row passes.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "fft_lds.hpp"
 #include "internal.hpp"
 #include "sincos.hpp"
@@ -536,7 +538,7 @@ __global__ __launch_bounds__(kColThreads) void st_adj_head_kernel(StreamArgs a, 
 // state sf / N2 (the unnormalised pair multiplies by N2); also
 // p_i[n] = sum_pol |v'[n]|^2 (the rotation keeps |v|).  v' is written to vt
 // (time samples n = n1 + N1 k2 at position n1 + N1 k2, the state layout) and
-// g' over g (same layout) for st_adj_rotate_kernel; only one column of 32
+// g' over g (same layout) for st_adj_comm_kernel; only one column of 32
 // samples is live at a time.
 template <int N2>
 __global__ __launch_bounds__(kColThreads) void st_adj_phase_kernel(float2* __restrict__ g,
@@ -592,30 +594,6 @@ __global__ __launch_bounds__(kColThreads) void st_adj_phase_kernel(float2* __res
   for (int k = 0; k < N2; ++k) dq[kRow * k] = q[k];
 }
 
-// Adjoint of the rotation and intensity, pointwise over time samples: with
-// v = v' exp(+j theta),
-//   g_v = g' exp(+j theta) + 2 p_bar v = exp(+j theta) (g' + 2 p_bar v'),
-// g' and v' as written by st_adj_phase_kernel (gt and vt); g_v overwrites v'
-// in vt.  st_col_forward_kernel then applies the forward column pass (the
-// adjoint of the inverse column pass that produced v).  Thread = one sample n
-// of one array (block, subband), both polarisations.
-__global__ __launch_bounds__(256) void st_adj_rotate_kernel(const float2* __restrict__ gt, float2* __restrict__ vt,
-                                                            const float* __restrict__ th,
-                                                            const float* __restrict__ pbar, int np,
-                                                            long long cells) {
-  const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (c >= cells) return;
-  const long long arr = c / np, n = c - arr * np;
-  float sn, cs;
-  phase_sincos(th[c], sn, cs);
-  const float p2 = 2.0f * pbar[c];
-  const size_t ox = (size_t)(arr * 2) * np + n, oy = ox + np;
-  const float2 gx = gt[ox], gy = gt[oy], vx = vt[ox], vy = vt[oy];
-  const float2 e = make_float2(cs, sn);
-  vt[ox] = cmul(make_float2(fmaf(p2, vx.x, gx.x), fmaf(p2, vx.y, gx.y)), e);
-  vt[oy] = cmul(make_float2(fmaf(p2, vy.x, gy.x), fmaf(p2, vy.y, gy.y)), e);
-}
-
 // Forward column pass of every column of src (time samples in the state
 // layout) into dst.
 template <int N2>
@@ -633,6 +611,121 @@ __global__ __launch_bounds__(kColThreads) void st_col_forward_kernel(const float
     load_col<N2>(src + (arr * 2 + pol) * NP, n1, v);
     col_forward<N2>(tw2, n1, v);
     store_col<N2>(dst + (arr * 2 + pol) * NP, n1, v);
+  }
+}
+
+// Split-ratio derivative (the telescoped form of the persistent adjoint):
+// with v the time samples before step st's rotation, w after it, g' the
+// cotangent of w, p_bar the intensity cotangent, e = exp(-j theta) - 1 and K
+// the filter phi'_q = phi_q - phi(f_i) (phi_q = 2 pi^2 beta2 f_q^2 per km,
+// phi(f_i) at the subband centre) applied to a time signal,
+//   G_{st+1} - G_{st} = sum_n Im(conj(K g') e v) - Im(conj(e* g' + 2 p_bar v) K v)
+// over both polarisations and the subbands, where G_j = sum_q phi_q
+// Im(conj(g_{A_j}) A_j) over the spectrum after dispersion segment j; then
+// dL/drho = L (G_0 - G_{N_st}) = -L sum over steps.  Both terms scale with the
+// nonlinear phase, where G_0 and G_{N_st} are each many times their
+// difference.
+//
+// st_kweight_kernel: row pass [optional forward size-N1 DFT, times
+// scale phi' (and h when GVD), inverse size-N1 DFT] of row k2 of array
+// (block w, subband i).  Its inverse column pass is K applied to the time
+// samples of the state (K v from S(st) with h the step's filter, K g' from G
+// with scale 1 / N1, the gain of the unnormalised row pair).
+template <bool FWD, bool GVD>
+__global__ __launch_bounds__(kRowNT, 4) void st_kweight_kernel(const float2* __restrict__ src,
+                                                              float2* __restrict__ dst,
+                                                              const float2* __restrict__ h,
+                                                              const double* __restrict__ phase, float scale,
+                                                              const float2* __restrict__ twr, int nsb, int n2,
+                                                              int np) {
+  __shared__ __align__(16) float4 lxy[FftShape<kRow>::LDS_C];
+  const int i = blockIdx.x / n2, k2 = blockIdx.x - (blockIdx.x / n2) * n2;
+  const size_t off = ((size_t)blockIdx.y * nsb + i) * 2 * np + (size_t)k2 * kRow;
+  const int t = threadIdx.x;
+  float2 x[kRowRR], y[kRowRR];
+#pragma unroll
+  for (int o = 0; o < kRowRR; ++o) {
+    x[o] = src[off + t + kRowNT * o];
+    y[o] = src[off + np + t + kRowNT * o];
+  }
+  if constexpr (FWD) fft<kRow, false>(x, y, lxy, twr, t);
+  const size_t hoff = (size_t)i * np + (size_t)k2 * kRow;
+  const double centre = phase[(size_t)i * np + kRow / 2];  // bin N'/2 sits at position N1/2
+#pragma unroll
+  for (int o = 0; o < kRowRR; ++o) {
+    float2 w = make_float2((float)(phase[hoff + t + kRowNT * o] - centre) * scale, 0.0f);
+    if constexpr (GVD) w = cscale(h[hoff + t + kRowNT * o], w.x);
+    x[o] = GVD ? cmul(x[o], w) : cscale(x[o], w.x);
+    y[o] = GVD ? cmul(y[o], w) : cscale(y[o], w.x);
+  }
+  fft<kRow, true>(x, y, lxy, twr, t);
+#pragma unroll
+  for (int o = 0; o < kRowRR; ++o) {
+    dst[off + t + kRowNT * o] = x[o];
+    dst[off + np + t + kRowNT * o] = y[o];
+  }
+}
+
+// Adjoint of the rotation and intensity with the split-ratio sum: per column
+// n1, K g' and K v are the inverse column passes of kg and kv; g', w (as
+// written by st_adj_phase_kernel in gt and vt), theta and p_bar are read per
+// sample.  g_v = g' + e* g' + 2 p_bar v (= g' exp(+j theta) + 2 p_bar v, v =
+// w exp(+j theta)) overwrites w in vt, for st_col_forward_kernel.  Each
+// workgroup writes its FP64 share of the sum above to part.
+template <int N2>
+__global__ __launch_bounds__(kColThreads) void st_adj_comm_kernel(const float2* __restrict__ gt,
+                                                                  float2* __restrict__ vt,
+                                                                  const float2* __restrict__ kg,
+                                                                  const float2* __restrict__ kv,
+                                                                  const float* __restrict__ th,
+                                                                  const float* __restrict__ pbar,
+                                                                  const float2* __restrict__ tw2, int nsb,
+                                                                  double* __restrict__ part) {
+  constexpr int NP = kRow * N2;
+  constexpr int GROUPS = kRow / kColThreads;
+  __shared__ double red[kColThreads / 64];
+  const int i = blockIdx.x / GROUPS;
+  const int n1 = (blockIdx.x - i * GROUPS) * kColThreads + threadIdx.x;
+  const size_t arr = (size_t)blockIdx.y * nsb + i;
+  const float* tc = th + arr * NP + n1;
+  const float* pc = pbar + arr * NP + n1;
+  double acc = 0.0;
+#pragma unroll 1
+  for (int pol = 0; pol < 2; ++pol) {
+    const size_t base = (arr * 2 + pol) * NP;
+    float2 a[N2], b[N2];
+    load_col<N2>(kg + base, n1, a);
+    col_inverse<N2>(tw2, n1, a);
+    load_col<N2>(kv + base, n1, b);
+    col_inverse<N2>(tw2, n1, b);
+    const float2* gc = gt + base + n1;
+    float2* vc = vt + base + n1;
+#pragma unroll
+    for (int k = 0; k < N2; ++k) {
+      float sh, ch;
+      phase_sincos(0.5f * tc[kRow * k], sh, ch);
+      const float2 e = make_float2(-2.0f * sh * sh, -2.0f * sh * ch);  // exp(-j theta) - 1
+      const float2 w = vc[kRow * k], g = gc[kRow * k];
+      const float2 ew = cmulc(w, e);                                   // conj(e) w = v - w
+      const float2 v = cadd(w, ew);
+      const float2 ge = cmulc(g, e);                                   // conj(e) g'
+      const float p2 = 2.0f * pc[kRow * k];
+      const float2 dg = make_float2(fmaf(p2, v.x, ge.x), fmaf(p2, v.y, ge.y));
+      // Im(conj(K g') e v) with e v = w - v = -conj(e) w; Im(conj(dg) K v)
+      const float t1 = -fmaf(a[k].x, ew.y, -a[k].y * ew.x);
+      const float t2 = fmaf(dg.x, b[k].y, -dg.y * b[k].x);
+      acc += (double)t1 - (double)t2;
+      vc[kRow * k] = cadd(g, dg);
+    }
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sum = 0.0;
+    for (int wv = 0; wv < kColThreads / 64; ++wv) sum += red[wv];
+    part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = sum;
   }
 }
 
@@ -850,15 +943,16 @@ __global__ void st_zero_kernel(double* __restrict__ p, int n) {
 }
 
 // Final gradients: dL/dC from the FP64 sums; acc_t[j] = sum phi Im(conj(Gy) Y)
-// over dispersion segment j, so dL/d(length j) = -acc_t[j] and, with the
-// first and last segments (1 - rho) L and rho L,
-// dL/drho = L (acc_t[0] - acc_t[steps]).
+// over dispersion segment j, so dL/d(length j) = -acc_t[j]; acc_t[steps + 1]
+// is the sum over steps of G_{st+1} - G_{st} (st_adj_comm_kernel), so with
+// the first and last segments (1 - rho) L and rho L,
+// dL/drho = L (G_0 - G_{N_st}) = -L acc_t[steps + 1].
 __global__ void st_bwd_finish_kernel(const double* __restrict__ acc_c, int n_c, const double* __restrict__ acc_t,
                                      int steps, double L, float* __restrict__ grad_c, float* __restrict__ grad_rho,
                                      double* __restrict__ grad_gvd) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n_c) grad_c[k] = (float)acc_c[k];
-  if (k == 0) *grad_rho = (float)(L * (acc_t[0] - acc_t[steps]));
+  if (k == 0) *grad_rho = (float)(-L * acc_t[steps + 1]);
   if (grad_gvd != nullptr && k <= steps) grad_gvd[k] = -acc_t[k];
 }
 
@@ -1033,10 +1127,13 @@ int launch_stream_forward(cbessfm_plan_t* p, const void* in, void* out, long lon
 //   g      one state (the adjoint state)
 //   v      one state-sized array of time samples (v' of the step being undone)
 //   theta  [k] phase arrays of the segment's steps
+//   kg     one state (K g' of the step being undone, before its column pass;
+//          K v goes to work)
 //   tbar   one phase-cotangent array
 //   cpart  coefficient partials of one step, [N' / kCgOut x nb][n_sb][n_sb][n_taps]
-//   rpart  dispersion-derivative partials of one row pass, [n_sb N2 nb]
-//   acc_c  FP64 [steps][n_sb][n_sb][n_taps], acc_t FP64 [steps + 1]
+//   rpart  dispersion and split-ratio partials of one pass, [n_sb max(N2, N1 / 256) nb]
+//   acc_c  FP64 [steps][n_sb][n_sb][n_taps], acc_t FP64 [steps + 2] (segment
+//          derivatives, then the split-ratio sum)
 //   csum   FP64 [kAccC][n_sb][n_sb][n_taps] chunk sums of the partials
 //   gin    [batch nblk][2][N] block input cotangents (only with grad_in)
 // A state is [nb][n_sb][2][N'] complex; p and p_bar use the plan's arrays.
@@ -1056,14 +1153,16 @@ StreamBwdLayout stream_bwd_layout(const cbessfm_plan_t* p, long long T, int batc
   L.work_off = L.slot_off + sbytes * L.k;
   L.g_off = L.work_off + sbytes;
   L.v_off = L.g_off + sbytes;
-  L.theta_off = L.v_off + sbytes;
+  L.kg_off = L.v_off + sbytes;
+  L.theta_off = L.kg_off + sbytes;
   L.tbar_off = L.theta_off + up(sizeof(float) * cells) * L.k;
   L.cpart_off = L.tbar_off + up(sizeof(float) * cells);
   const size_t n_cg = (size_t)(p->Np / kCgOut) * L.nb;
   L.rpart_off = L.cpart_off + up(sizeof(float) * n_cg * nsb * nsb * p->n_taps);
-  L.accc_off = L.rpart_off + up(sizeof(double) * nsb * (p->Np / kRow) * L.nb);
+  const size_t rows = (size_t)std::max(p->Np / kRow, kRow / kColThreads);
+  L.accc_off = L.rpart_off + up(sizeof(double) * nsb * rows * L.nb);
   L.acct_off = L.accc_off + up(sizeof(double) * (size_t)p->steps * nsb * nsb * p->n_taps);
-  L.csum_off = L.acct_off + up(sizeof(double) * (size_t)(p->steps + 1));
+  L.csum_off = L.acct_off + up(sizeof(double) * (size_t)(p->steps + 2));
   L.gin_off = L.csum_off + up(sizeof(double) * kAccC * nsb * nsb * p->n_taps);
   L.bytes = L.gin_off + (gin ? up(sizeof(float2) * (size_t)items * 2 * p->N) : 0);
   return L;
@@ -1091,6 +1190,7 @@ struct StreamBwdCall {
   float2* work() const { return reinterpret_cast<float2*>(ws + L.work_off); }
   float2* G() const { return reinterpret_cast<float2*>(ws + L.g_off); }
   float2* V() const { return reinterpret_cast<float2*>(ws + L.v_off); }
+  float2* KG() const { return reinterpret_cast<float2*>(ws + L.kg_off); }
   double* csum() const { return reinterpret_cast<double*>(ws + L.csum_off); }
   float* tbar() const { return reinterpret_cast<float*>(ws + L.tbar_off); }
   float* cpart() const { return reinterpret_cast<float*>(ws + L.cpart_off); }
@@ -1122,7 +1222,6 @@ int bwd_wave(const StreamBwdCall& c, StreamArgs a) {
   const dim3 col_grid((nsb * kRow + kColThreads - 1) / kColThreads, a.nb);
   const dim3 sb_grid(nsb * (kRow / kColThreads), a.nb);
   const dim3 cg_grid(a.np / kCgOut, a.nb);
-  const long long cells = (long long)a.nb * nsb * a.np;
   StreamWsb wsb;
   for (int j = 0; j < kMaxSubbands; ++j) wsb.w[j] = tb.wsb[j];
   hipStream_t s = c.s;
@@ -1150,6 +1249,17 @@ int bwd_wave(const StreamBwdCall& c, StreamArgs a) {
       for (int st = s0; st < s1 && ok; ++st)
         ok = wave_step<N2>(a, tb, p->d_cpad, st, n_taps, tap_pad, c.S(st), c.work(), c.TH(st), c.S(st + 1), s);
     for (int st = s1 - 1; st >= s0 && ok; --st) {
+      // K g' (row domain, from G) and K v (from the state before the step)
+      const dim3 row_grid(nsb * a.n2, a.nb);
+      st_kweight_kernel<true, false><<<row_grid, kRowNT, 0, s>>>(c.G(), c.KG(), nullptr, p->d_phase,
+                                                                 1.0f / (float)kRow, a.twr, nsb, a.n2, a.np);
+      if (st == 0 && nsb > 1)
+        st_kweight_kernel<false, true><<<row_grid, kRowNT, 0, s>>>(c.S(st), c.work(), step_filter(tb, st),
+                                                                   p->d_phase, 1.0f, a.twr, nsb, a.n2, a.np);
+      else
+        st_kweight_kernel<true, true><<<row_grid, kRowNT, 0, s>>>(c.S(st), c.work(), step_filter(tb, st),
+                                                                  p->d_phase, 1.0f, a.twr, nsb, a.n2, a.np);
+      ok = ok && ok_launch();
       st_adj_phase_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(c.G(), c.S(st + 1), c.V(), c.tbar(), a.pb, a.tw2,
                                                               nsb);
       ok = ok && ok_launch();
@@ -1164,8 +1274,9 @@ int bwd_wave(const StreamBwdCall& c, StreamArgs a) {
       st_add_chunks_kernel<<<(per_step + 255) / 256, 256, 0, s>>>(c.csum(), per_step,
                                                                   c.acc_c() + (size_t)st * per_step);
       ok = ok && ok_launch();
-      st_adj_rotate_kernel<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(c.G(), c.V(), c.TH(st), a.th, a.np,
-                                                                         cells);
+      st_adj_comm_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(c.G(), c.V(), c.KG(), c.work(), c.TH(st), a.th,
+                                                             a.tw2, nsb, c.rpart());
+      st_acc_sum_kernel<<<1, 256, 0, s>>>(c.rpart(), (int)(sb_grid.x * sb_grid.y), c.acc_t() + steps + 1);
       st_col_forward_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(c.V(), c.G(), a.tw2, nsb);
       ok = ok && ok_launch();
       if (st > 0) {
@@ -1210,7 +1321,7 @@ int launch_stream_backward(cbessfm_plan_t* p, const void* field_in, const void* 
   c.s = s;
   const int n_c = p->steps * p->sb.n_sb * p->sb.n_sb * p->n_taps;
   st_zero_kernel<<<(n_c + 255) / 256, 256, 0, s>>>(c.acc_c(), n_c);
-  st_zero_kernel<<<(p->steps + 1 + 255) / 256, 256, 0, s>>>(c.acc_t(), p->steps + 1);
+  st_zero_kernel<<<(p->steps + 2 + 255) / 256, 256, 0, s>>>(c.acc_t(), p->steps + 2);
   if (!ok_launch()) return CBESSFM_EHIP;
   StreamArgs a;
   fill_stream_args(p, field_in, nullptr, T, a);

@@ -2,13 +2,13 @@
 
 The oracle differentiates a plain PyTorch complex128 CPU rewrite of the
 forward map (itself pinned to the numpy oracle and to finite differences on
-the CPU).  Bar: relative L2 error <= 1e-5 for dL/dC and dL/dfield_in.
+the CPU).  Bar: relative L2 error <= 1e-5 for dL/dC and dL/dfield_in, and
+relative error <= 1e-5 for dL/drho.
 
-dL/drho is the difference of two terms, the derivative through the first and
-through the last GVD (Sec. III-C), which nearly cancel (their sizes exceed
-|dL/drho| up to a few hundred times under strong nonlinearity).  Its bar is
-that both terms are resolved to 1e-5 of their own size:
-|error| <= 1e-5 (|d_first| + |d_last|), summed per realisation.
+dL/drho is the difference of the derivatives through the first and the last
+GVD (Sec. III-C), each up to hundreds of times larger than the result; the
+adjoint forms it step by step from terms that scale with the nonlinear phase
+(a dispersion/rotation commutator), so it reaches the same relative bar.
 Finite differences of the FP64 oracle are checked as a second reference.
 """
 import copy
@@ -57,17 +57,6 @@ def gpu_grads(g, x, gout, need_in=True, ck=1):
     return (gi.cpu().numpy() if gi is not None else None), gc.cpu().numpy(), float(gr.cpu().numpy()[0])
 
 
-def rho_scale(x, o, gout):
-    """sum over realisations of |d_first| + |d_last| (oracle)."""
-    xs = x if x.ndim == 3 else x[None]
-    gs = gout if gout.ndim == 3 else gout[None]
-    total = 0.0
-    for xi, gi in zip(xs, gs):
-        _, _, (rf, rl) = vjp(xi, o, gi, rho_parts=True)
-        total += abs(rf) + abs(rl)
-    return total
-
-
 def check_case(n_sb, block_sb, overlap, steps, rho, taps, t_len, batch=1, ck=1, boundary="circular", seed=0,
                rate=None, need_in=True, phase=0.5):
     power = 4e-3
@@ -79,7 +68,7 @@ def check_case(n_sb, block_sb, overlap, steps, rho, taps, t_len, batch=1, ck=1, 
     g, o = plans(n_sb, block_sb, overlap, steps, rho, c, rate=rate, boundary=boundary)
     gi, gc, gr = gpu_grads(g, x, gout, need_in=need_in, ck=ck)
     ogi, ogc, ogr = vjp(x, o, gout)
-    errs = dict(c=rel(gc, ogc), rho=abs(gr - ogr) / rho_scale(x, o, gout))
+    errs = dict(c=rel(gc, ogc), rho=abs(gr - ogr) / abs(ogr))
     if need_in:
         errs["in"] = rel(gi, ogi)
     print(n_sb, block_sb, steps, taps, ck, errs)
@@ -110,7 +99,7 @@ def test_checkpointing_and_determinism(ck):
     assert np.array_equal(got[0], again[0]) and np.array_equal(got[1], again[1]) and got[2] == again[2]
     ogi, ogc, ogr = vjp(x, o, gout)
     assert rel(got[0], ogi) < TOL and rel(got[1], ogc) < TOL
-    assert abs(got[2] - ogr) < TOL * rho_scale(x, o, gout)
+    assert abs(got[2] - ogr) < TOL * abs(ogr)
     if 1 < ck < 5:
         assert g.backward_workspace(2500, 1, ck) < g.backward_workspace(2500, 1, 1)
 
@@ -138,11 +127,10 @@ def test_gradient_workload_sixteen_realisations_and_finite_differences():
     c = analytic_coeffs(LinkSpec(beta2_ps2_km=BETA2_PS2, sample_rate_hz=64e9), 1, 15, 0.5, 11)
     g, o = plans(1, 1024, 128, 15, 0.5, c)
     ogi, ogc, ogr = vjp(xs, o, gout)
-    scale = rho_scale(xs, o, gout)
     for ck in (1, 8):
         gi, gc, gr = gpu_grads(g, xs, gout, ck=ck)
-        errs = dict(c=rel(gc, ogc), rho=abs(gr - ogr) / scale, inp=rel(gi, ogi))
-        print("16 realisations, checkpoint every", ck, errs, "rho rel", abs(gr - ogr) / abs(ogr))
+        errs = dict(c=rel(gc, ogc), rho=abs(gr - ogr) / abs(ogr), inp=rel(gi, ogi))
+        print("16 realisations, checkpoint every", ck, errs)
         assert max(errs.values()) < TOL, errs
 
     # central differences of the FP64 oracle, h = 1e-3 relative
@@ -161,7 +149,7 @@ def test_gradient_workload_sixteen_realisations_and_finite_differences():
     pa, pb = copy.copy(o), copy.copy(o)
     pa.rho, pb.rho = o.rho + h, o.rho - h
     fd = (loss(pa) - loss(pb)) / (2 * h)
-    assert abs(gr - fd) < 1e-4 * abs(fd) + TOL * scale
+    assert abs(gr - fd) < 1e-4 * abs(fd)
 
 
 def test_autograd_function_and_adam_step():
@@ -180,7 +168,7 @@ def test_autograd_function_and_adam_step():
     xn = x.cpu().numpy().astype(np.complex128)
     _, ogc, ogr = vjp(xn, o, gout)
     assert rel(coeffs.grad.cpu().numpy(), ogc) < TOL
-    assert abs(float(rho.grad) - ogr) < TOL * rho_scale(xn, o, gout)
+    assert abs(float(rho.grad) - ogr) < TOL * abs(ogr)
     opt = torch.optim.Adam([coeffs, rho], lr=1e-3)
     before = float(loss)
     for _ in range(20):

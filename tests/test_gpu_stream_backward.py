@@ -1,10 +1,8 @@
 """Parity of the streaming adjoint (blocks of N' = 2^14 .. 2^17 per subband)
 with the FP64 gradient oracle, through the C ABI.
 
-Same bars as the persistent adjoint: relative L2 error <= 1e-5 for dL/dC and
-dL/dfield_in; dL/drho resolved to 1e-5 of the sum of its two terms (the
-derivative through the first and through the last dispersion segment, which
-nearly cancel); dL/d(segment lengths) to relative L2 1e-5.
+Same bars as the persistent adjoint: relative L2 error <= 1e-5 for dL/dC,
+dL/dfield_in and dL/d(segment lengths), relative error <= 1e-5 for dL/drho.
 """
 import numpy as np
 import pytest
@@ -13,7 +11,7 @@ import torch
 from oracle.grad import vjp, vjp_lengths
 from synth import random_field
 
-from test_gpu_backward import TOL, check_case, gpu_grads, plans, rand_coeffs, rel, rho_scale
+from test_gpu_backward import TOL, check_case, gpu_grads, plans, rand_coeffs, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -63,7 +61,7 @@ def test_stream_checkpointing_is_exact_and_deterministic(ck):
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]) and got[2] == ref[2]
     ogi, ogc, ogr = vjp(x, o, gout)
     assert rel(got[0], ogi) < TOL and rel(got[1], ogc) < TOL
-    assert abs(got[2] - ogr) < TOL * rho_scale(x, o, gout)
+    assert abs(got[2] - ogr) < TOL * abs(ogr)
     if 1 < ck < 5:
         assert g.backward_workspace(45000, 1, ck) < g.backward_workspace(45000, 1, 1)
     g.close()
