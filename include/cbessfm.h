@@ -173,6 +173,24 @@ int cbessfm_backward(cbessfm_plan_t* plan, const void* field_in, const void* gra
                      int32_t checkpoint_every, void* workspace, size_t workspace_bytes,
                      void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): cbessfm_backward
+ * with the library's own fixed device scratch as its workspace.  The scratch
+ * is one array of CBESSFM_STATIC_SCRATCH_BYTES per device, held until the
+ * process ends and shared by every call on that device: calls that overlap in
+ * time on one device race on it.  It calls no allocating routine; the plan
+ * (created beforehand) still owns its tables and exchange buffers.  Same
+ * arguments, results and errors as cbessfm_backward without the workspace;
+ * also CBESSFM_EWORKSPACE when the call would need more than
+ * CBESSFM_STATIC_SCRATCH_BYTES (cbessfm_backward_workspace gives the need;
+ * a checkpoint spacing between 1 and steps, or a smaller T or batch, lowers
+ * it), CBESSFM_EINVAL when the current device is not the plan's.
+ * Asynchronous on stream. */
+#define CBESSFM_STATIC_SCRATCH_BYTES (64u << 20)
+int cbessfm_backward_static(cbessfm_plan_t* plan, const void* field_in, const void* grad_out, void* grad_in,
+                            float* grad_c, float* grad_rho, int64_t T, int32_t batch, int32_t checkpoint_every,
+                            void* stream);
+
 /* Complexity model of Sec. III-D (host): real multiplications *rm and real
  * additions *ra per 2D symbol of a method processing blocks of N samples with
  * overlap N_ov at n_sps samples per symbol.

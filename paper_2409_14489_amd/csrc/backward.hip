@@ -47,6 +47,8 @@
 // blocks in FP64 by a second kernel, in a fixed order.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "fft_lds.hpp"
 #include "internal.hpp"
 #include "stages.hpp"
@@ -718,6 +720,35 @@ int launch_gather_gin(const float2* blk_g, float2* gin, long long T, int N, int 
   gather_gin_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(blk_g, gin, (int)T, N, hop, n_ov, nblk, batch,
                                                                      boundary);
   return hipGetLastError() == hipSuccess ? CBESSFM_OK : CBESSFM_EHIP;
+}
+
+// ------------------------------------------------------------------ fixed scratch
+// Device memory of cbessfm_backward_static: one array per device, held until
+// the process ends, shared by every such call on that device (calls that
+// overlap in time on one device race on it).  The kernels write every part
+// of the workspace they later read (the FP64 accumulators of the streaming
+// path are cleared by a kernel at the start of each call), so nothing is
+// cleared here.  In host code `scratch` is only a stand-in for the symbol:
+// its device address comes from hipGetSymbolAddress, taken once per device
+// with that device current, and only that address is passed to kernels.
+static __device__ __align__(256) unsigned char scratch[CBESSFM_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
+int static_scratch(int device, void** ptr) {
+  if (device < 0 || device >= kMaxScratchDevices) return CBESSFM_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device] == nullptr) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return CBESSFM_EHIP;
+    g_scratch_ptr[device] = p;
+  }
+  *ptr = g_scratch_ptr[device];
+  return CBESSFM_OK;
 }
 
 }  // namespace cbessfm

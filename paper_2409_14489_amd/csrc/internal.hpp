@@ -225,6 +225,9 @@ StreamBwdLayout stream_bwd_layout(const cbessfm_plan_t* p, long long T, int batc
 int launch_stream_backward(cbessfm_plan_t* p, const void* field_in, const void* grad_out, void* grad_in,
                            float* grad_c, float* grad_rho, double* grad_gvd, long long T, int batch, int ck_every,
                            void* workspace, size_t ws_bytes, hipStream_t s);
+// backward.hip: device address of the fixed scratch array on `device` (which
+// must be current), looked up once per device and kept.
+int static_scratch(int device, void** ptr);
 // backward.hip: grad_in[inst][pol][pos] = sum of the block input cotangents
 // blk_g[inst nblk + b][pol][n] of every block position that reads pos.
 int launch_gather_gin(const float2* blk_g, float2* gin, long long T, int N, int hop, int n_ov, int nblk, int batch,

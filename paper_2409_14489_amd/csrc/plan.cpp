@@ -602,4 +602,23 @@ int cbessfm_backward_gvd(cbessfm_plan_t* p, const void* field_in, const void* gr
                                   checkpoint_every, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
 }
 
+int cbessfm_backward_static(cbessfm_plan_t* p, const void* field_in, const void* grad_out, void* grad_in,
+                            float* grad_c, float* grad_rho, int64_t T, int32_t batch, int32_t checkpoint_every,
+                            void* stream) {
+  if (!p || !field_in || !grad_out || !grad_c || !grad_rho || T < 1 || batch < 1 || T >= (1LL << 31))
+    return CBESSFM_EINVAL;
+  if (p->nlpr != CBESSFM_NLPR_AVERAGED) return CBESSFM_EUNSUPPORTED;
+  const size_t need = p->stream ? cbessfm::stream_bwd_layout(p, T, batch, checkpoint_every, grad_in != nullptr).bytes
+                                : cbessfm::bwd_layout(p, T, batch, checkpoint_every).bytes;
+  if (need > (size_t)CBESSFM_STATIC_SCRATCH_BYTES) return CBESSFM_EWORKSPACE;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return CBESSFM_EHIP;
+  if (dev != p->device) return CBESSFM_EINVAL;
+  void* ws = nullptr;
+  const int rc = cbessfm::static_scratch(dev, &ws);
+  if (rc) return rc;
+  return cbessfm_backward_gvd(p, field_in, grad_out, grad_in, grad_c, grad_rho, nullptr, T, batch, checkpoint_every,
+                              ws, (size_t)CBESSFM_STATIC_SCRATCH_BYTES, stream);
+}
+
 }  // extern "C"
