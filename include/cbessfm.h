@@ -276,6 +276,16 @@ int cbessfm_plan_info(const cbessfm_plan_t* plan, cbessfm_info* out);
  * plan's exchange state is then reset as well). */
 int cbessfm_status(cbessfm_plan_t* plan);
 
+/* Bound of the device-side exchange waits of the plan's persistent kernels
+ * (cbessfm_run, cbessfm_backward): a wait polls at most `polls` times, about
+ * 64 cycles apart, then gives up: it sets the plan's sticky error
+ * (CBESSFM_ESYNC from cbessfm_status) and every later wait of the launch
+ * falls through, so the launch still ends, with invalid results.  A healthy
+ * launch never comes near the default of 2^22 polls (about 0.1 s); 0 restores
+ * it.  Lowering it exercises the give-up path (tests).  Host only; takes
+ * effect at the next run or backward.  CBESSFM_EINVAL for a NULL plan. */
+int cbessfm_set_wait_limit(cbessfm_plan_t* plan, uint32_t polls);
+
 /* Releases the plan and all its device memory (NULL is a no-op). */
 void cbessfm_destroy(cbessfm_plan_t* plan);
 

@@ -22,7 +22,7 @@ EXPORTED = (
     "cbessfm_batch_destroy", "cbessfm_schedule", "cbessfm_autotune",
     "cbessfm_tie_expand", "cbessfm_tie_reduce", "cbessfm_step_weights", "cbessfm_tied_half_taps",
     "cbessfm_complexity", "cbessfm_set_nlpr", "cbessfm_set_gvd_lengths", "cbessfm_backward_gvd",
-    "cbessfm_backward_static",
+    "cbessfm_backward_static", "cbessfm_set_wait_limit",
 )
 
 STATIC_SCRATCH_BYTES = 64 << 20   # CBESSFM_STATIC_SCRATCH_BYTES
@@ -123,6 +123,7 @@ def _load() -> ctypes.CDLL:
         "cbessfm_set_gvd_lengths": ([P, P, P], ctypes.c_int),
         "cbessfm_backward_gvd": ([P, P, P, P, P, P, P, i64, i32, i32, P, sz, P], ctypes.c_int),
         "cbessfm_backward_static": ([P, P, P, P, P, P, i64, i32, i32, P], ctypes.c_int),
+        "cbessfm_set_wait_limit": ([P, ctypes.c_uint32], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

@@ -686,7 +686,7 @@ int launch_backward(cbessfm_plan_t* p, const void* field_in, const void* grad_ou
   a.gin_blk = grad_in ? reinterpret_cast<float2*>(ws + L.gin_off) : nullptr;
   a.ctl.abort = p->d_abort;
   a.ctl.err = p->d_err;
-  a.ctl.spin_limit = 1u << 22;
+  a.ctl.spin_limit = p->wait_limit;
   a.rounds_per_item = 4u * (unsigned)p->steps + 4u;
   a.epoch = p->d_epoch;
   const int groups = (a.n_teams + kXcds - 1) / kXcds;

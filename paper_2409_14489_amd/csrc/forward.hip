@@ -348,7 +348,7 @@ int launch_forward(cbessfm_plan_t* p, const void* in, void* out, long long T, in
   a.xp = p->d_xp;
   a.ctl.abort = p->d_abort;
   a.ctl.err = p->d_err;
-  a.ctl.spin_limit = 1u << 22;
+  a.ctl.spin_limit = p->wait_limit;
   const int groups = (a.n_teams + kXcds - 1) / kXcds;
   const int grid = groups * kXcds * a.inst.n_sb;
   switch (p->log_np) {

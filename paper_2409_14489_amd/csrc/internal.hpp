@@ -157,6 +157,10 @@ struct BwdLayout {
 
 }  // namespace cbessfm
 
+// Default bound of an exchange wait: 2^22 polls about 64 cycles apart
+// (about 0.1 s), far beyond any wait of a healthy launch.
+constexpr unsigned kDefaultWaitLimit = 1u << 22;
+
 struct cbessfm_plan {
   cbessfm_link link;
   cbessfm_subbands sb;
@@ -173,6 +177,7 @@ struct cbessfm_plan {
   int gvd_explicit;       // 1: dispersion segment lengths from d_len, else (1 - rho) L, L, ..., rho L
   int bwd_team_capacity;  // the same for the adjoint kernel
   int xchg_teams;         // teams the exchange buffers are sized for
+  unsigned wait_limit;    // polls before an exchange wait gives up (cbessfm_set_wait_limit)
   // device memory
   double* d_phase;    // [N] 2 pi^2 beta2 f^2 per km, subband order (FP64); streaming plans keep
                       // each subband's N' entries in the permuted order of stream.hip

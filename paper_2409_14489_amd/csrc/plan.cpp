@@ -363,6 +363,7 @@ int cbessfm_plan(cbessfm_plan_t** out, const cbessfm_link* link, const cbessfm_s
   p->xchg_teams = std::max(std::max(p->team_capacity, p->team_capacity_dual), p->bwd_team_capacity);
   }
   p->nlpr = CBESSFM_NLPR_AVERAGED;
+  p->wait_limit = kDefaultWaitLimit;
 
   const int N = p->N, Np = p->Np, nsb = sb->n_sb;
   const size_t crows = (size_t)steps * nsb * nsb;
@@ -560,6 +561,12 @@ int cbessfm_status(cbessfm_plan_t* p) {
       return CBESSFM_EHIP;
   }
   return err;
+}
+
+int cbessfm_set_wait_limit(cbessfm_plan_t* p, uint32_t polls) {
+  if (!p) return CBESSFM_EINVAL;
+  p->wait_limit = polls ? polls : kDefaultWaitLimit;
+  return CBESSFM_OK;
 }
 
 int cbessfm_set_nlpr(cbessfm_plan_t* p, int32_t mode) {

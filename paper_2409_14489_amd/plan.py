@@ -237,6 +237,11 @@ class Plan:
     def status(self) -> int:
         return lib.cbessfm_status(self._h)
 
+    def set_wait_limit(self, polls: int) -> None:
+        """Polls before a device-side exchange wait gives up (0: the default);
+        a launch that gives up ends normally and cbessfm_status reports it."""
+        check(lib.cbessfm_set_wait_limit(self._h, int(polls)), "cbessfm_set_wait_limit")
+
     def close(self):
         if getattr(self, "_h", None):
             lib.cbessfm_destroy(self._h)

@@ -30,7 +30,7 @@ import torch
 from ._lib import check, lib
 from .autograd import cbessfm
 from .plan import LinkSpec, Plan, _stream_ptr, analytic_coeffs
-from .train import SymbolReceiver, adam_loop, phase_aligned_mse, snr_db
+from .train import SymbolReceiver, adam_loop, phase_aligned_mse, plan_check_fn, snr_db
 
 def step_weights(link: LinkSpec, steps: int):
     """(w [steps] float64 with mean 1, mean effective step length in km)."""
@@ -176,7 +176,8 @@ def fit_tied(plan: Plan, link: LinkSpec, fields: torch.Tensor, symbols: torch.Te
             c = tie(rows_t, weights, half)
             return phase_aligned_mse(receiver(cbessfm(fields, c, rho_t, plan, checkpoint_every)), symbols)
 
-        losses[h] = adam_loop([u], loss_fn, iters_per_row, lr, graph=graph, warmup=warmup, device=dev)
+        losses[h] = adam_loop([u], loss_fn, iters_per_row, lr, graph=graph, warmup=warmup, device=dev,
+                              check=plan_check_fn(plan))
         with torch.no_grad():
             fitted[h] = u.detach() * scale
     return fitted, losses

@@ -14,6 +14,7 @@ import math
 
 import torch
 
+from ._lib import CbessfmError
 from .autograd import cbessfm, cbessfm_steps
 
 
@@ -75,12 +76,14 @@ def phase_aligned_mse(z: torch.Tensor, s: torch.Tensor) -> torch.Tensor:
 
 
 def adam_loop(params, loss_fn, iters: int, lr: float, graph: bool = False, warmup: int = 3,
-              after_step=None, device=None):
+              after_step=None, device=None, check=None):
     """Adam on ``params`` for ``iters`` iterations of ``loss_fn()`` (which
     returns a scalar tensor).  With ``graph`` the iteration (forward, loss,
     backward, update) is recorded in a HIP graph after ``warmup`` eager
     iterations on a side stream and replayed for the rest; ``iters`` counts
     all of them.  ``after_step`` runs under no_grad after every update.
+    ``check`` (if given) runs after the eager iterations and at the end,
+    outside any capture: it raises if the device reported an error.
     Returns the losses as a tensor."""
     opt = torch.optim.Adam(params, lr=lr, capturable=graph)
 
@@ -98,6 +101,8 @@ def adam_loop(params, loss_fn, iters: int, lr: float, graph: bool = False, warmu
     if not graph:
         for _ in range(iters):
             losses.append(step())
+        if check is not None:
+            check()
         return torch.stack(losses)
     side = torch.cuda.Stream(device=device)
     side.wait_stream(torch.cuda.current_stream())
@@ -105,6 +110,8 @@ def adam_loop(params, loss_fn, iters: int, lr: float, graph: bool = False, warmu
         for _ in range(min(warmup, iters)):
             losses.append(step())
     torch.cuda.current_stream().wait_stream(side)
+    if check is not None:
+        check()
     if iters > warmup:
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
@@ -113,7 +120,19 @@ def adam_loop(params, loss_fn, iters: int, lr: float, graph: bool = False, warmu
             g.replay()
             losses.append(static_loss.clone())
         del g
+        if check is not None:
+            check()
     return torch.stack(losses)
+
+
+def plan_check_fn(plan):
+    """A ``check`` for adam_loop: raises CbessfmError if a device-side
+    exchange wait of the plan gave up (its gradients are then invalid)."""
+    def check():
+        code = plan.status()
+        if code != 0:
+            raise CbessfmError(code, "device error during the fit")
+    return check
 
 
 def fit(plan, fields: torch.Tensor, symbols: torch.Tensor, receiver: SymbolReceiver, coeffs0, rho0: float,
@@ -142,7 +161,7 @@ def fit(plan, fields: torch.Tensor, symbols: torch.Tensor, receiver: SymbolRecei
         return receiver_mse(y, receiver, symbols)
 
     losses = adam_loop(params, loss_fn, iters, lr, graph=graph, warmup=warmup,
-                       after_step=lambda: rho.clamp_(0.0, 1.0), device=fields.device)
+                       after_step=lambda: rho.clamp_(0.0, 1.0), device=fields.device, check=plan_check_fn(plan))
     return (u * scale).detach(), rho.detach(), losses
 
 
@@ -193,7 +212,8 @@ def fit_steps(plan, fields: torch.Tensor, symbols: torch.Tensor, receiver: Symbo
     groups = [{"params": [u], "lr": lr}]
     if fit_lengths:
         groups.append({"params": [z], "lr": lr if lr_lengths is None else lr_lengths})
-    losses = adam_loop(groups, loss_fn, iters, lr, graph=graph, warmup=warmup, device=dev)
+    losses = adam_loop(groups, loss_fn, iters, lr, graph=graph, warmup=warmup, device=dev,
+                       check=plan_check_fn(plan))
     c_fit, l_fit = (u * scale).detach(), (total * torch.softmax(z, 0)).detach()
     with torch.no_grad():
         start = phase_aligned_mse(receiver(cbessfm_steps(fields, c0.contiguous(), l0.contiguous(), plan)), symbols)

@@ -57,3 +57,38 @@ def test_asymmetric_split_helps_one_step_per_span(link_case):
     e = {rho: dbp_error(rx, tx, link, dbp_coefficients(link, 4, 2, rho, 61), rho)
          for rho in (0.2, 0.5)}
     assert e[0.2] < e[0.5]
+
+
+@pytest.fixture(scope="module")
+def one_span_case():
+    """One channel, 32 GBd DP-16QAM at 9 dBm over a single 80 km span (fine
+    steps, no noise): the signal power falls by 16 dB along the span, so
+    fractional DBP steps of the same length carry very different nonlinear
+    phases."""
+    spec = WdmSpec(n_symbols=2 ** 12, n_channels=1, baud=32e9, spacing=40e9, rolloff=0.1,
+                   qam_order=16, sample_rate=64e9, power_dbm_per_channel=9.0)
+    ch = ChannelSpec(n_spans=1, steps_per_span=400, ase=False)
+    rx, _ = received_field(spec, ch, 11)
+    tx, _ = wdm_transmit(spec, rng_for(11))
+    return rx, tx, Link(n_spans=1, sample_rate=64e9)
+
+
+@pytest.mark.parametrize("n_steps", [3, 4, 5])
+@pytest.mark.parametrize("rho", [0.5, 0.2])
+def test_fractional_step_order(one_span_case, n_steps, rho):
+    """DBP step s undoes physical step N_st - s + 1 (the link is traversed
+    backwards, Sec. I; per-step kernels of fractional steps, Sec. II-D): with
+    the analytic coefficients in that order the link is undone better than
+    with the same steps in the reverse order (the reading DBP step s <->
+    physical step s) or with their mean in every step."""
+    rx, tx, link = one_span_case
+
+    def err(C):
+        p = oracle.OraclePlan(link.beta2, link.sample_rate, 80.0 / n_steps, n_steps, rho, 1, rx.shape[-1], 0, C)
+        return np.linalg.norm(oracle.run(rx, p) - tx) / np.linalg.norm(tx)
+
+    C = dbp_coefficients(link, 1, n_steps, rho, 21)
+    e = err(C)
+    assert e < 0.25 * err(0 * C)
+    assert 1.3 * e < err(C[::-1].copy())
+    assert e < err(np.repeat(C.mean(axis=0, keepdims=True), n_steps, axis=0))
