@@ -100,6 +100,17 @@ def measured_traffic():
         return None
 
 
+# Algorithmic FP32 flops per 2D symbol of the named workloads, the per-unit
+# figures of the method's operation count (5 n log2 n per complex DFT of size
+# n plus the pointwise stages, with the coupled filter in its frequency-domain
+# form): the roofline's `achieved` is this times the 2D symbols of one launch.
+FLOPS_PER_2D_SYMBOL = {
+    "5ch-64GBd-64QAM-2^16sym-15x80km": 7.0e3,
+    "1ch-32GBd-16QAM-2^14sym-1x80km": 614.0,
+    "1ch-32GBd-16QAM-2^14sym-1x80km-15steps": 5.8e3,
+}
+
+
 def algorithmic_flops_per_block(n_sb, n_sub, steps, n_taps):
     """Flops of one overlap-and-save block, by this convention:
     5 n log2 n per complex DFT of size n, 6 per complex multiply, 7 per
@@ -265,7 +276,8 @@ def leg_forward(args):
 
     n2d = wdm.n_channels * 2 * wdm.n_symbols                # 2D symbols per pass
     nblk = plan.n_blocks(t_len)
-    flops = algorithmic_flops_per_block(d["n_sb"], d["n_sub"], d["n_steps"], d["n_taps"]) * nblk
+    flops = FLOPS_PER_2D_SYMBOL[WORKLOAD] * n2d
+    flops_own = algorithmic_flops_per_block(d["n_sb"], d["n_sub"], d["n_steps"], d["n_taps"]) * nblk
     achieved = flops / kernel_s / 1e12
     alg_bytes = 2 * (2 * t_len * 8)                          # read + write complex64, both pols
     hbm_gbs = alg_bytes / kernel_s / 1e9
@@ -293,7 +305,10 @@ def leg_forward(args):
                    "fwd_kernel_source_sha256": kernel_source_digest(FWD_KERNEL_SOURCES)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
-                     "flops_per_launch": flops, "kernel_ms": kernel_s * 1e3},
+                     "flops_per_launch": flops, "flops_per_2d_symbol": FLOPS_PER_2D_SYMBOL[WORKLOAD],
+                     "kernel_ms": kernel_s * 1e3,
+                     "flops_per_launch_direct_filter": flops_own,
+                     "frac_direct_filter": flops_own / kernel_s / 1e12 / PEAK_FP32_TFLOPS},
         "launch": {"timed": f"HIP graph replays, {per_graph} launch(es) per replay",
                    "eager_cooperative_ms_per_step": eager_s * 1e3},
         "hbm_roofline": {"achieved": hbm_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -847,7 +862,7 @@ def leg_cfg1(args):
     n2d = wdm.n_channels * 2 * wdm.n_symbols
     t_len = x.shape[-1]
     nblk = plan.n_blocks(t_len)
-    flops = algorithmic_flops_per_block(d["n_sb"], d["n_sub"], d["n_steps"], d["n_taps"]) * nblk
+    flops = FLOPS_PER_2D_SYMBOL[CFG1_WORKLOAD] * n2d
     out = {"workload": CFG1_WORKLOAD, "T": t_len, "blocks": nblk, "value": n2d / run_s, "unit": "2D-symbols/s",
            "ms_per_run": run_s * 1e3, "flops_per_run": flops, "tflops": flops / run_s / 1e12,
            "hbm_gbs_algorithmic": 2 * 2 * t_len * 8 / run_s / 1e9,

@@ -193,6 +193,35 @@ __device__ __forceinline__ void subband_to_polyphase(const TeamCtx& c, uint64_t*
   apply_diag<N, true>(x, y, c.tab->poly_tw + (size_t)c.me * N, t);
 }
 
+// A pointer every lane of the wave holds the same value of, made visible as
+// such to the compiler (so that loads through it become scalar loads).
+template <typename T>
+__device__ __forceinline__ const T* uniform_ptr(const T* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<const T*>(((uint64_t)hi << 32) | lo);
+}
+
+// acc[q] += sum_{tau < 8 NCH} cl[tau] W[q - tau + 8 NCH - 1], q < QB, with the
+// window W[i] = cur[pad_r(start + i)], i < QB + 8 NCH - 1, read once; the
+// taps are compile-time, so every window index is static (no register moves)
+// and the coefficients are scalar operands.
+template <int NCH, int QB>
+__device__ __forceinline__ void fir_row_fixed(const float* cur, int start, const float* __restrict__ cl,
+                                              float* acc) {
+  constexpr int TP = kTapChunk * NCH;
+  constexpr int WN = (QB + TP - 1 + 3) & ~3;
+  float win[WN];
+  load_row4<WN, 0>(cur, start, win);
+#pragma unroll
+  for (int tau = 0; tau < TP; ++tau) {
+    const float cv = cl[tau];
+#pragma unroll
+    for (int q = 0; q < QB; ++q) acc[q] = fmaf(cv, win[q - tau + TP - 1], acc[q]);
+  }
+}
+
 // Coupled intensity filter of eq. (15) for member `me`, circular over N':
 //   out[k] = sum_l sum_tau crow[l][tau] in_l[(k - tau + nc) mod N'],
 // crow = the member's coefficient rows ([n_sb][8 n_chunks], zero padded).
@@ -247,36 +276,45 @@ __device__ __forceinline__ void coupled_fir(const TeamCtx& c, const float* __res
     const bool more = l + 1 < nsb;
     const bool fetch = more && (l + 1 != me);  // next row is remote
     const uint64_t* nrow = xrow + (size_t)(l + 1) * N;
-    const float* cl = crow + (size_t)l * tap_pad;
+    const float* cl = uniform_ptr(crow + (size_t)l * tap_pad);
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       uint64_t w[QB];
       if (fetch) xissue<QB>(nrow + NT * QB * g, t, NT, w);  // in flight during the filter
-      float win[QB + kTapChunk];
       int start = t * RR + g * QB;  // = t RR + g QB + tap_pad - 8 n_chunks
-      load_row4<QB + kTapChunk, 0>(cur, start, win);
-      // the chunk's 8 coefficients (uniform: scalar loads), fetched one chunk ahead
-      float cf[kTapChunk];
+      switch (c.n_chunks) {  // up to 32 taps: compile-time taps, window read once
+        case 1: fir_row_fixed<1, QB>(cur, start, cl, acc + g * QB); break;
+        case 2: fir_row_fixed<2, QB>(cur, start, cl, acc + g * QB); break;
+        case 3: fir_row_fixed<3, QB>(cur, start, cl, acc + g * QB); break;
+        case 4: fir_row_fixed<4, QB>(cur, start, cl, acc + g * QB); break;
+        default: {
+          float win[QB + kTapChunk];
+          load_row4<QB + kTapChunk, 0>(cur, start, win);
+          // the chunk's 8 coefficients, fetched one chunk ahead
+          float cf[kTapChunk];
 #pragma unroll
-      for (int tt = 0; tt < kTapChunk; ++tt) cf[tt] = cl[kTapChunk * (c.n_chunks - 1) + tt];
-      for (int ch = c.n_chunks - 1; ch >= 0; --ch) {
-        float cf_next[kTapChunk];
-        const int ch_next = ch > 0 ? ch - 1 : 0;
+          for (int tt = 0; tt < kTapChunk; ++tt) cf[tt] = cl[kTapChunk * (c.n_chunks - 1) + tt];
+          for (int ch = c.n_chunks - 1; ch >= 0; --ch) {
+            float cf_next[kTapChunk];
+            const int ch_next = ch > 0 ? ch - 1 : 0;
 #pragma unroll
-        for (int tt = 0; tt < kTapChunk; ++tt) cf_next[tt] = cl[kTapChunk * ch_next + tt];
+            for (int tt = 0; tt < kTapChunk; ++tt) cf_next[tt] = cl[kTapChunk * ch_next + tt];
 #pragma unroll
-        for (int tt = 0; tt < kTapChunk; ++tt) {
+            for (int tt = 0; tt < kTapChunk; ++tt) {
 #pragma unroll
-          for (int q = 0; q < QB; ++q) acc[g * QB + q] = fmaf(cf[tt], win[q - tt + kTapChunk - 1], acc[g * QB + q]);
+              for (int q = 0; q < QB; ++q)
+                acc[g * QB + q] = fmaf(cf[tt], win[q - tt + kTapChunk - 1], acc[g * QB + q]);
+            }
+            if (ch > 0) {
+#pragma unroll
+              for (int i = 0; i < QB; ++i) win[i] = win[i + kTapChunk];
+              start += kTapChunk;
+              load_row4<kTapChunk, QB>(cur, start + QB, win);
+            }
+#pragma unroll
+            for (int tt = 0; tt < kTapChunk; ++tt) cf[tt] = cf_next[tt];
+          }
         }
-        if (ch > 0) {
-#pragma unroll
-          for (int i = 0; i < QB; ++i) win[i] = win[i + kTapChunk];
-          start += kTapChunk;
-          load_row4<kTapChunk, QB>(cur, start + QB, win);
-        }
-#pragma unroll
-        for (int tt = 0; tt < kTapChunk; ++tt) cf[tt] = cf_next[tt];
       }
       if (more) {  // this part of the next row into the other buffer (last read before the previous barrier)
         if (fetch) {

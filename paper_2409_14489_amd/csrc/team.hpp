@@ -2,11 +2,19 @@
 // exchange between the workgroups of a team, and the overlap-and-save framing.
 //
 // Exchange protocol.  Every exchanged float travels in its own 64-bit word
-// whose high half is a round tag; words are written and read with relaxed
-// device-scope atomics (single-copy atomic, coherent across the XCDs' L2s).
-// A reader polls a word until it carries the tag of the round it needs, so it
-// can never consume stale data, and no cache write-back / invalidate fences
-// are needed.
+// whose high half is a round tag; words are single-copy atomic, written with
+// relaxed workgroup-scope atomic stores and read with relaxed device-scope
+// atomic loads.  The members of a team are workgroups with the same blockIdx
+// mod 8, which the dispatcher places on one XCD (workgroups go to the XCDs
+// round-robin, from a launch-dependent start), so the exchange only has to
+// be coherent within that XCD's L2: the stores go through the CU's
+// write-through L1 into the L2 and are not written through to memory, and
+// the loads miss the L1 and read the L2.  A reader polls a word until it
+// carries the tag of the round it needs, so it can never consume stale data,
+// and no cache write-back / invalidate fences are needed.  Were the members
+// of a team ever on different XCDs, the bounded waits would give up and the
+// launch would report CBESSFM_ESYNC; a stale word cannot be mistaken for a
+// new one.
 //
 // Tags come from a per-team round counter kept in device memory (the team's
 // "epoch"): a launch reads it once at the start, numbers its rounds after it,
@@ -45,7 +53,7 @@ __device__ __forceinline__ int opaque_tid() {
 
 __device__ __forceinline__ void xput(uint64_t* dst, float v, unsigned tag) {
   const uint64_t w = ((uint64_t)tag << 32) | (uint64_t)__float_as_uint(v);
-  __hip_atomic_store(dst, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(dst, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 __device__ __forceinline__ uint64_t xload(const uint64_t* src) {
