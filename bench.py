@@ -548,7 +548,8 @@ def leg_batched(args):
            "unit": "2D-symbols/s", "value": n2d / t_batch, "ms_per_run": t_batch * 1e3,
            "separate_launches": {"value": n2d / t_sep, "ms_per_run": t_sep * 1e3, "launches": len(specs)},
            "speedup_vs_separate": t_sep / t_batch, "graph_replayed": True,
-           "launches_per_run": info["launches"], "teams": info["teams"], "workgroups": info["workgroups"],
+           "launches_per_run": info["launches"], "streamed_instances": info["streamed"],
+           "streamed_blocks": info["streamed_items"], "teams": info["teams"], "workgroups": info["workgroups"],
            "blocks": info["items"], "predicted_ms": info["makespan_s"] * 1e3,
            "lower_bound_ms": info["lower_bound_s"] * 1e3,
            "block_sb_chosen": sorted({t["block_sb"] for t in tuned}),
@@ -982,7 +983,7 @@ def headline(result):
     b = result.get("batched")
     if b:
         line["batched"] = {"value": b["value"], "speedup_vs_separate": b["speedup_vs_separate"],
-                           "launches_per_run": b["launches_per_run"],
+                           "launches_per_run": b["launches_per_run"], "streamed": b.get("streamed_instances"),
                            "instances_overlap_covers_memory": b["instances_overlap_covers_memory"]}
     line["legs_file"] = result.get("legs_file")
     return line

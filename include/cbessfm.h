@@ -293,8 +293,10 @@ void cbessfm_destroy(cbessfm_plan_t* plan);
 const char* cbessfm_strerror(int code);
 
 /* ------------------------------------------------------------------ batches
- * Many instances in one persistent launch per distinct N' (one launch when
- * all instances share N').  An instance is a plan -- its own link, subband
+ * Many instances in one persistent launch per distinct N' up to 8192 (one
+ * launch when all instances share N'); instances with N' >= 2^14 (streamed
+ * block state) run on the streaming kernels after those launches, on the
+ * same stream.  An instance is a plan -- its own link, subband
  * count, steps, split ratio and coefficients -- with its own fields, length
  * and batch count; the batch computes for every instance exactly what
  * cbessfm_run would (Sec. III-A / III-C).  Workgroups form static teams of the
@@ -315,12 +317,15 @@ typedef struct {
 typedef struct cbessfm_batch cbessfm_batch_t;
 
 typedef struct {
-  int32_t launches;        /* persistent launches per run (distinct N') */
+  int32_t launches;        /* persistent launches per run (distinct N' <= 8192) */
   int32_t teams;           /* teams over all launches */
   int32_t workgroups;      /* summed grid sizes */
   int64_t items;           /* overlap-and-save blocks over all instances */
-  double makespan_s;       /* predicted run time: summed over launches, max over teams */
+  double makespan_s;       /* predicted run time: summed over launches, max over teams,
+                              plus the streamed instances */
   double lower_bound_s;    /* a lower bound of makespan_s for the same item costs */
+  int32_t streamed;        /* instances with N' >= 2^14, run by the streaming kernels */
+  int64_t streamed_items;  /* their blocks (included in items) */
 } cbessfm_batch_info;
 
 /* Builds the schedule and the device tables of a batch on the current
@@ -380,8 +385,12 @@ int cbessfm_schedule(const cbessfm_sched_job* jobs, int32_t n_jobs, int32_t slot
  * over L; Sec. III-A), rounded up to even.  Among the N' in [256, 8192] whose
  * block N = n_sb N' exceeds it, the one with the least predicted time for the
  * instance (blocks / resident teams, rounded up, times the time of one block)
- * wins.  If no N' covers the memory, N' = 8192 with N_ov = min(memory, N / 2)
- * is returned with covered = 0.  flags: CBESSFM_TUNE_MEASURE times each
+ * wins.  If none of them covers the memory, the smallest streamed block
+ * N' in [2^14, 2^17] that does is returned (its time from an operation-count
+ * model of the streaming kernels); only if even N' = 2^17 does not cover it,
+ * N' = 2^17 with N_ov = min(memory, N / 2) and covered = 0.  A streamed
+ * instance needs its own plan's block-state buffers (cbessfm_plan sizes them,
+ * at most 512 MB).  flags: CBESSFM_TUNE_MEASURE times each
  * candidate block shape on the current device (probe launches of one block
  * per resident team at 1 and 4 steps, linear in the step count; cached per
  * device and shape for the process); 0 uses an operation-count model and

@@ -1,8 +1,9 @@
 """Batched CB-ESSFM execution, its scheduler and the block-length autotuner.
 
 ``Batch`` binds many instances -- each a :class:`Plan` with its own fields --
-to one persistent launch per distinct N' (``cbessfm_batch_*`` in
-``include/cbessfm.h``).  ``schedule`` exposes the host-only team scheduler and
+to one persistent launch per distinct N' up to 8192, and runs instances of
+streamed blocks (N' >= 2^14) on the streaming kernels in the same run
+(``cbessfm_batch_*`` in ``include/cbessfm.h``).  ``schedule`` exposes the host-only team scheduler and
 ``autotune`` the N' / N_ov choice.  Argument marshalling only.
 """
 from __future__ import annotations

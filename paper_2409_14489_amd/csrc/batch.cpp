@@ -3,7 +3,9 @@
 //
 // A batch runs many instances (plans with their own link, subband count,
 // steps, coefficients, fields and length) in one persistent launch per
-// distinct N'.  Its workgroups form static teams; a team has the width
+// distinct N' up to 8192; instances whose blocks exceed one CU (N' = 2^14 ..
+// 2^17, streamed block state) run on the streaming kernels after those
+// launches, in the same stream (so the whole run is graph-capturable).  Its workgroups form static teams; a team has the width
 // (n_sb) of the instances it runs and keeps that width for the whole launch,
 // so the exchange protocol of the single-plan kernel carries over unchanged:
 // a team owns its exchange slots and round counter and runs its items one
@@ -278,6 +280,15 @@ int item_cost(const cbessfm_link* link, int log_np, int nsb, int n_taps, int ste
   return CBESSFM_OK;
 }
 
+// Operation-count model of one streamed block (seconds): each step moves the
+// block state through device memory about six times (row pass in and out,
+// intensity, filter, rotation in and out) at an assumed 4 TB/s, plus the
+// input and output stages.
+double stream_block_cost(int log_np, int nsb, int steps) {
+  const double state = (double)nsb * (double)(1 << log_np) * 2.0 * sizeof(float2);
+  return (6.0 * steps + 4.0) * state / 4e12 + 20e-6 * steps;
+}
+
 long long dispersion_memory(const cbessfm_link* link) {
   const double beta2 = std::fabs(link->beta2_ps2_km) * 1e-24;  // s^2/km
   const double L = link->span_km * link->n_spans;
@@ -298,6 +309,9 @@ struct cbessfm_batch {
     BatchArgs args{};
   };
   std::vector<Launch> launches;
+  // instances whose plans stream their block state (N' >= 2^14): run by the
+  // streaming kernels after the persistent launches
+  std::vector<cbessfm_instance> streamed;
   cbessfm_batch_info info{};
   std::vector<void*> allocs;
   unsigned* d_abort = nullptr;
@@ -401,6 +415,24 @@ int cbessfm_autotune(const cbessfm_link* link, int32_t n_sb, int32_t steps, int3
       out->predicted_s = pred;
     }
   }
+  if (out->block_sb && out->covered) return CBESSFM_OK;
+  // No block of the persistent kernels covers the memory: the smallest
+  // streamed block that does (N' = 2^14 .. 2^17), else the largest with
+  // N_ov = min(memory, N / 2) and covered = 0.
+  for (int log_np = cbessfm::kStreamMinLog; log_np <= cbessfm::kStreamMaxLog; ++log_np) {
+    const long long N = (long long)n_sb << log_np;
+    const bool covers = mem < N;
+    if (!covers && log_np < cbessfm::kStreamMaxLog) continue;
+    long long ov = covers ? mem : std::min(mem, N / 2);
+    ov &= ~1LL;
+    const long long items = (long long)batch * ((T + (N - ov) - 1) / (N - ov));
+    out->block_sb = 1 << log_np;
+    out->overlap = (int32_t)ov;
+    out->covered = covers ? 1 : 0;
+    out->measured = 0;
+    out->predicted_s = (double)items * stream_block_cost(log_np, n_sb, steps);
+    break;
+  }
   return out->block_sb ? CBESSFM_OK : CBESSFM_EUNSUPPORTED;
 }
 
@@ -428,7 +460,6 @@ int cbessfm_batch_create(cbessfm_batch_t** out, const cbessfm_instance* inst, in
       return CBESSFM_EINVAL;
     if (a.plan->device != dev) return CBESSFM_EINVAL;
     if (a.plan->nlpr != CBESSFM_NLPR_AVERAGED) return CBESSFM_EUNSUPPORTED;  // batches run eq. (15)
-    if (a.plan->stream) return CBESSFM_EUNSUPPORTED;  // batches run the persistent kernels
     const size_t bytes = (size_t)a.batch * 2 * a.T * sizeof(float2);
     if (overlaps(a.field_in, bytes, a.field_out, bytes)) return CBESSFM_EINVAL;
     for (int j = 0; j < i; ++j) {
@@ -442,9 +473,21 @@ int cbessfm_batch_create(cbessfm_batch_t** out, const cbessfm_instance* inst, in
   if (!b) return CBESSFM_ENOMEM;
   b->device = dev;
 
-  // ---- one launch per N'
+  // ---- one launch per N' of the persistent kernels; streamed plans apart
   std::map<int, std::vector<int>> by_np;
-  for (int i = 0; i < n; ++i) by_np[inst[i].plan->log_np].push_back(i);
+  long long stream_items = 0;
+  double stream_time = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const cbessfm_plan_t* p = inst[i].plan;
+    if (p->stream) {
+      b->streamed.push_back(inst[i]);
+      const long long nblk = (inst[i].T + p->hop - 1) / p->hop;
+      stream_items += (long long)inst[i].batch * nblk;
+      stream_time += (double)inst[i].batch * nblk * stream_block_cost(p->log_np, p->sb.n_sb, p->steps);
+    } else {
+      by_np[p->log_np].push_back(i);
+    }
+  }
   struct Built {
     int log_np;
     Schedule s;
@@ -503,9 +546,9 @@ int cbessfm_batch_create(cbessfm_batch_t** out, const cbessfm_instance* inst, in
   b->xspec_words = xspec_words;
   b->xp_words = xp_words;
   b->n_epoch = n_epoch;
-  b->d_xspec = static_cast<uint64_t*>(alloc(xspec_words * sizeof(uint64_t)));
-  b->d_xp = static_cast<uint64_t*>(alloc(xp_words * sizeof(uint64_t)));
-  b->d_epoch = static_cast<unsigned*>(alloc(n_epoch * sizeof(unsigned)));
+  b->d_xspec = static_cast<uint64_t*>(alloc(std::max<size_t>(1, xspec_words) * sizeof(uint64_t)));
+  b->d_xp = static_cast<uint64_t*>(alloc(std::max<size_t>(1, xp_words) * sizeof(uint64_t)));
+  b->d_epoch = static_cast<unsigned*>(alloc(std::max<size_t>(1, n_epoch) * sizeof(unsigned)));
   b->d_abort = static_cast<unsigned*>(alloc(sizeof(unsigned)));
   b->d_err = static_cast<int*>(alloc(sizeof(int)));
   if (!ok || reset_exchange(b)) {
@@ -585,9 +628,11 @@ int cbessfm_batch_create(cbessfm_batch_t** out, const cbessfm_instance* inst, in
   b->info.launches = (int32_t)b->launches.size();
   b->info.teams = total_teams;
   b->info.workgroups = total_wg;
-  b->info.items = total_items;
-  b->info.makespan_s = makespan;
-  b->info.lower_bound_s = bound;
+  b->info.items = total_items + stream_items;
+  b->info.makespan_s = makespan + stream_time;
+  b->info.lower_bound_s = bound + stream_time;
+  b->info.streamed = (int32_t)b->streamed.size();
+  b->info.streamed_items = stream_items;
   *out = b;
   return CBESSFM_OK;
 }
@@ -597,6 +642,10 @@ int cbessfm_batch_run(cbessfm_batch_t* b, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   for (const auto& L : b->launches) {
     const int rc = cbessfm::launch_batch(L.log_np, L.args, L.grid, s);
+    if (rc) return rc;
+  }
+  for (const cbessfm_instance& a : b->streamed) {
+    const int rc = cbessfm::launch_stream_forward(a.plan, a.field_in, a.field_out, a.T, a.batch, s);
     if (rc) return rc;
   }
   return CBESSFM_OK;

@@ -115,18 +115,28 @@ def test_model_autotune_covers_the_dispersion_memory(n_sb, spans, rate):
     t = autotune(link, n_sb, 10, 11, 1 << 18, measure=False)
     assert t["memory"] == memory_samples(-21.7, 80.0 * spans, rate)
     assert t["measured"] == 0
-    assert t["block_sb"] in (256, 512, 1024, 2048, 4096, 8192)
+    assert t["block_sb"] in [1 << k for k in range(8, 18)]
     assert t["overlap"] % 2 == 0
-    if t["covered"]:
-        assert t["memory"] <= t["overlap"] < n_sb * t["block_sb"]
-    else:
-        assert t["block_sb"] == 8192 and t["overlap"] == min(t["memory"], n_sb * 8192 // 2) // 2 * 2
+    assert t["covered"] == 1                        # every link here fits a block of at most 2^17
+    assert t["memory"] <= t["overlap"] < n_sb * t["block_sb"]
+    if t["block_sb"] > 8192:                        # streamed only when no persistent block covers
+        assert t["memory"] >= n_sb * 8192
+        assert t["memory"] < n_sb * t["block_sb"] and t["memory"] >= n_sb * t["block_sb"] // 2
 
 
-def test_model_autotune_uncovered_long_link():
+def test_model_autotune_long_link_streams_a_covering_block():
+    """40 x 80 km at 640 GS/s: memory 1.79e5 samples, beyond 5 x 8192; the
+    smallest covering streamed block is N' = 2^16 (N = 327680)."""
     link = LinkSpec(n_spans=40, sample_rate_hz=640e9)
     t = autotune(link, 5, 40, 21, 1 << 20, measure=False)
-    assert t["covered"] == 0 and t["block_sb"] == 8192 and t["overlap"] == 20480
+    assert t["covered"] == 1 and t["block_sb"] == 1 << 16 and t["overlap"] == t["memory"]
+
+
+def test_model_autotune_beyond_the_largest_block():
+    """A memory beyond n_sb x 2^17 samples: the largest block, half overlap, covered = 0."""
+    link = LinkSpec(n_spans=400, sample_rate_hz=640e9)
+    t = autotune(link, 1, 40, 21, 1 << 22, measure=False)
+    assert t["covered"] == 0 and t["block_sb"] == 1 << 17 and t["overlap"] == (1 << 17) // 2
 
 
 def test_model_autotune_rejects_bad_arguments():

@@ -227,3 +227,51 @@ def test_measured_autotune_gives_a_working_plan():
                           c.astype(np.float64))
     assert rel_l2(y.cpu().numpy().astype(np.complex128), oracle.run(x, o)) < TOL
     plan.close()
+
+
+def test_batch_with_streamed_instances_matches_oracle_block_by_block():
+    """Instances whose blocks are streamed (N' = 2^14 and 2^15) in one batch
+    with persistent ones: every instance equals the FP64 oracle over its whole
+    output and over every block, equals its own cbessfm_run, and a HIP graph
+    of the run replays to the same bytes."""
+    from paper_2409_14489_amd import Batch
+    shapes = [
+        (2, 2 ** 14, 4096, 3, 0.3, 7, 40000, 1, "circular", 2),
+        (1, 1024, 128, 2, 0.5, 11, 9000, 1, "circular", 1),
+        (1, 2 ** 15, 8192, 2, 0.5, 9, 70001, 1, "zero", 3),
+        (3, 512, 192, 2, 0.4, 5, 6000, 2, "circular", 2),
+    ]
+    insts = make_instances(shapes, seed0=2000)
+    b = Batch([(d["plan"], d["xt"], d["yt"]) for d in insts])
+    info = b.info()
+    print(info)
+    assert info["streamed"] == 2 and info["launches"] == 2
+    b.run()
+    torch.cuda.synchronize()
+    assert b.status() == 0
+    eager = [d["yt"].clone() for d in insts]
+    for k, d in enumerate(insts):
+        got = d["yt"].cpu().numpy().astype(np.complex128)
+        ref = oracle.run(d["x"], d["oracle"])
+        e_or, e_blk = rel_l2(got, ref), worst_block_rel_l2(got, ref, d["plan"].hop)
+        single = d["plan"].run(d["xt"])
+        torch.cuda.synchronize()
+        print(k, shapes[k][:4], "vs oracle", e_or, "worst block", e_blk)
+        assert e_or < TOL and e_blk < TOL
+        assert torch.equal(single, eager[k])
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        b.run()
+    for _ in range(2):
+        for d in insts:
+            d["yt"].zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        _ = float(insts[0]["xt"].abs().sum())      # eager work between replays
+        for d, e in zip(insts, eager):
+            assert torch.equal(d["yt"], e)
+    del graph
+    assert b.status() == 0
+    b.close()
+    for d in insts:
+        d["plan"].close()
