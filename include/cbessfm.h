@@ -295,8 +295,9 @@ const char* cbessfm_strerror(int code);
 /* ------------------------------------------------------------------ batches
  * Many instances in one persistent launch per distinct N' up to 8192 (one
  * launch when all instances share N'); instances with N' >= 2^14 (streamed
- * block state) run on the streaming kernels after those launches, on the
- * same stream.  An instance is a plan -- its own link, subband
+ * block state) run on the streaming kernels after those launches,
+ * concurrently on up to four side streams of the batch (default priority)
+ * that fork from and join back to the caller's stream.  An instance is a plan -- its own link, subband
  * count, steps, split ratio and coefficients -- with its own fields, length
  * and batch count; the batch computes for every instance exactly what
  * cbessfm_run would (Sec. III-A / III-C).  Workgroups form static teams of the

@@ -5,7 +5,8 @@
 // steps, coefficients, fields and length) in one persistent launch per
 // distinct N' up to 8192; instances whose blocks exceed one CU (N' = 2^14 ..
 // 2^17, streamed block state) run on the streaming kernels after those
-// launches, in the same stream (so the whole run is graph-capturable).  Its workgroups form static teams; a team has the width
+// launches, concurrently on a few side streams forked from and joined back
+// to the caller's stream (so the whole run stays graph-capturable).  Its workgroups form static teams; a team has the width
 // (n_sb) of the instances it runs and keeps that width for the whole launch,
 // so the exchange protocol of the single-plan kernel carries over unchanged:
 // a team owns its exchange slots and round counter and runs its items one
@@ -312,6 +313,12 @@ struct cbessfm_batch {
   // instances whose plans stream their block state (N' >= 2^14): run by the
   // streaming kernels after the persistent launches
   std::vector<cbessfm_instance> streamed;
+  // their side streams (default priority) and fork / join events: the
+  // streamed instances run concurrently, instances of one plan on one stream
+  std::vector<hipStream_t> side;
+  std::vector<int> side_of;  // per streamed instance
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
   cbessfm_batch_info info{};
   std::vector<void*> allocs;
   unsigned* d_abort = nullptr;
@@ -443,6 +450,9 @@ void cbessfm_batch_destroy(cbessfm_batch_t* b) {
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(b->device);
   for (void* p : b->allocs) (void)hipFree(p);
+  for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  for (hipStream_t st : b->side) (void)hipStreamDestroy(st);
   (void)hipSetDevice(prev);
   delete b;
 }
@@ -625,6 +635,49 @@ int cbessfm_batch_create(cbessfm_batch_t** out, const cbessfm_instance* inst, in
     makespan += s.makespan;
     bound += s.lower_bound;
   }
+  // ---- side streams of the streamed instances: longest first onto the least
+  // loaded stream, instances sharing a plan on the same stream
+  if (!b->streamed.empty()) {
+    constexpr int kSideStreams = 4;
+    const int n_side = std::min<int>(kSideStreams, (int)b->streamed.size());
+    std::vector<double> cost(b->streamed.size()), load(n_side, 0.0);
+    std::vector<int> order(b->streamed.size());
+    for (size_t k = 0; k < b->streamed.size(); ++k) {
+      const cbessfm_instance& a = b->streamed[k];
+      const cbessfm_plan_t* p = a.plan;
+      cost[k] = (double)a.batch * ((a.T + p->hop - 1) / p->hop) * stream_block_cost(p->log_np, p->sb.n_sb, p->steps);
+      order[k] = (int)k;
+    }
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    b->side_of.assign(b->streamed.size(), 0);
+    std::map<const cbessfm_plan_t*, int> plan_side;
+    for (int k : order) {
+      auto it = plan_side.find(b->streamed[k].plan);
+      int sd;
+      if (it != plan_side.end()) {
+        sd = it->second;
+      } else {
+        sd = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        plan_side[b->streamed[k].plan] = sd;
+      }
+      b->side_of[k] = sd;
+      load[sd] += cost[k];
+    }
+    bool sok = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; k < n_side && sok; ++k) {
+      hipStream_t st = nullptr;
+      hipEvent_t ev = nullptr;
+      sok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+      if (sok) b->side.push_back(st);
+      sok = sok && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+      if (sok) b->join.push_back(ev);
+    }
+    if (!sok) {
+      cbessfm_batch_destroy(b);
+      return CBESSFM_EHIP;
+    }
+    stream_time = *std::max_element(load.begin(), load.end());
+  }
   b->info.launches = (int32_t)b->launches.size();
   b->info.teams = total_teams;
   b->info.workgroups = total_wg;
@@ -644,11 +697,23 @@ int cbessfm_batch_run(cbessfm_batch_t* b, void* stream) {
     const int rc = cbessfm::launch_batch(L.log_np, L.args, L.grid, s);
     if (rc) return rc;
   }
-  for (const cbessfm_instance& a : b->streamed) {
-    const int rc = cbessfm::launch_stream_forward(a.plan, a.field_in, a.field_out, a.T, a.batch, s);
-    if (rc) return rc;
+  if (b->streamed.empty()) return CBESSFM_OK;
+  // streamed instances: fork to the side streams after the persistent
+  // launches, join back (under graph capture this records a fork / join of
+  // kernel nodes)
+  if (hipEventRecord(b->fork, s) != hipSuccess) return CBESSFM_EHIP;
+  for (hipStream_t st : b->side)
+    if (hipStreamWaitEvent(st, b->fork, 0) != hipSuccess) return CBESSFM_EHIP;
+  int rc = CBESSFM_OK;
+  for (size_t k = 0; k < b->streamed.size() && !rc; ++k) {
+    const cbessfm_instance& a = b->streamed[k];
+    rc = cbessfm::launch_stream_forward(a.plan, a.field_in, a.field_out, a.T, a.batch, b->side[b->side_of[k]]);
   }
-  return CBESSFM_OK;
+  // join every side stream even after a failed launch
+  for (size_t k = 0; k < b->side.size(); ++k)
+    if (hipEventRecord(b->join[k], b->side[k]) != hipSuccess || hipStreamWaitEvent(s, b->join[k], 0) != hipSuccess)
+      rc = rc ? rc : CBESSFM_EHIP;
+  return rc;
 }
 
 int cbessfm_batch_describe(const cbessfm_batch_t* b, cbessfm_batch_info* out) {
