@@ -77,8 +77,19 @@ typedef struct {
   int32_t block_sb;  /* N' = N / N_sb, power of two in [256, 8192] (one CU per
                         subband block) or [2^14, 2^17] (streamed block state) */
   int32_t overlap;   /* N_ov, full-field samples, even, 0 <= N_ov < N */
+  int32_t fir_mode;  /* how the forward evaluates the coupled filter of eq. (15),
+                        circular over N' (the same map either way):
+                        CBESSFM_FIR_TIME: direct sum over the taps;
+                        CBESSFM_FIR_FREQ: the paper's frequency-domain form
+                        (Sec. III-A, Fig. "scheme_NLPR"): DFT of each subband's
+                        intensity, the N_sb x N_sb matrix of the coefficient
+                        rows' DFTs per bin, inverse DFT (N' <= 8192 only);
+                        CBESSFM_FIR_AUTO: frequency domain above 64 taps.
+                        The adjoint and the dual-polarisation NLPR evaluate the
+                        filter in the time domain. */
   int32_t boundary;  /* 0: circular sequence; 1: zeros outside [0, T) */
 } cbessfm_subbands;
+enum { CBESSFM_FIR_AUTO = 0, CBESSFM_FIR_TIME = 1, CBESSFM_FIR_FREQ = 2 };
 
 /* Coefficients of the coupled intensity filter, eq. (15). */
 typedef struct {
@@ -101,6 +112,7 @@ typedef struct {
 /* Checks every argument of cbessfm_plan on the host, touching no device.
  * Order of checks: link (n_spans >= 1, span_km > 0, sample_rate_hz > 0,
  * finite beta2), n_sb in 1..8, N' supported, overlap even and in [0, N),
+ * fir_mode in {0, 1, 2} (CBESSFM_EUNSUPPORTED for 2 with N' >= 2^14),
  * boundary in {0, 1}, n_taps odd and in range, grid_m, split_ratio in [0, 1],
  * steps >= 1.  Returns CBESSFM_EINVAL or CBESSFM_EUNSUPPORTED on the first
  * failure. */

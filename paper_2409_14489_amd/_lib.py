@@ -39,7 +39,10 @@ class Link(ctypes.Structure):
 
 class Subbands(ctypes.Structure):
     _fields_ = [("n_sb", ctypes.c_int32), ("block_sb", ctypes.c_int32),
-                ("overlap", ctypes.c_int32), ("boundary", ctypes.c_int32)]
+                ("overlap", ctypes.c_int32), ("fir_mode", ctypes.c_int32), ("boundary", ctypes.c_int32)]
+
+
+FIR_MODES = {"auto": 0, "time": 1, "freq": 2}
 
 
 class Coeffs(ctypes.Structure):

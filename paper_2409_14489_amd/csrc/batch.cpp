@@ -203,7 +203,7 @@ int probe_time(const cbessfm_link* link, int log_np, int nsb, int n_taps, int st
   int teams = 0;
   int rc = team_capacity(log_np, nsb, &teams, nullptr);
   if (rc) return rc;
-  cbessfm_subbands sb{nsb, 1 << log_np, 0, 0};
+  cbessfm_subbands sb{nsb, 1 << log_np, 0, CBESSFM_FIR_AUTO, 0};
   std::vector<float> c((size_t)steps * nsb * nsb * n_taps, 0.0f);
   for (int s = 0; s < steps; ++s)
     for (int i = 0; i < nsb; ++i)
@@ -532,7 +532,7 @@ int cbessfm_batch_create(cbessfm_batch_t** out, const cbessfm_instance* inst, in
     const int np = 1 << bt.log_np;
     for (size_t tm = 0; tm < bt.s.team_width.size(); ++tm) {
       xspec_words += (size_t)2 * bt.s.team_width[tm] * 4 * np;
-      xp_words += (size_t)2 * bt.s.team_width[tm] * np;
+      xp_words += (size_t)2 * bt.s.team_width[tm] * 2 * np;
       ++n_epoch;
     }
     built.push_back(std::move(bt));
@@ -590,7 +590,7 @@ int cbessfm_batch_create(cbessfm_batch_t** out, const cbessfm_instance* inst, in
       t.xspec_off = (long long)xs_off;
       t.xp_off = (long long)xp_off;
       xs_off += (size_t)2 * t.width * 4 * np;
-      xp_off += (size_t)2 * t.width * np;
+      xp_off += (size_t)2 * t.width * 2 * np;
       unsigned rounds = 0;
       for (long long id : s.team_items[tm]) {
         const size_t j = std::upper_bound(first_item.begin(), first_item.end(), id) - first_item.begin() - 1;

@@ -312,4 +312,72 @@ __device__ __forceinline__ void fft(float2 (&x)[FftShape<N>::RR], float2 (&y)[Ff
   fft_passes<N, 0, INV>(x, y, lxy, twt, w0, t);
 }
 
+// ------------------------------------------------------------- one array
+// The same Stockham transform of a single owned register set (a real
+// intensity or phase row of the frequency-domain coupled filter): identical
+// radices, twiddles and layout contract, with the exchange buffer holding one
+// float2 per position (the first 2 (N + N/8 + 1) floats of the buffer).
+template <int N, int P, bool INV>
+__device__ __forceinline__ void fft1_pass(float2 (&x)[FftShape<N>::RR], float2* __restrict__ lx,
+                                          const PassTwRegs<N, P>& w, int t) {
+  using S = FftShape<N>;
+  constexpr int R = S::radix(P);
+  constexpr int L = S::stride(P);
+  constexpr int NB = S::RR / R;
+  constexpr bool FIRST = (P == 0);
+  constexpr bool LAST = (P == S::passes() - 1);
+  constexpr int NR = N / R;
+  float2 vx[NB][R];
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      if constexpr (FIRST)
+        vx[a][m] = x[a + m * NB];
+      else
+        vx[a][m] = lx[pad_c(t + S::NT * a + m * NR)];
+    }
+  if constexpr (!FIRST && !LAST) __syncthreads();
+#pragma unroll
+  for (int a = 0; a < NB; ++a) {
+    if constexpr (!FIRST) {
+#pragma unroll
+      for (int m = 1; m < R; ++m) vx[a][m] = twmul<INV>(vx[a][m], w[a * (R - 1) + m - 1]);
+    }
+    dft<R, INV>(vx[a]);
+  }
+#pragma unroll
+  for (int a = 0; a < NB; ++a) {
+    const int j = t + S::NT * a;
+    const int k = j % L;
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      if constexpr (LAST)
+        x[a + m * NB] = vx[a][m];
+      else
+        lx[pad_c((j - k) * R + k + m * L)] = vx[a][m];
+    }
+  }
+  if constexpr (!LAST) __syncthreads();
+}
+
+template <int N, int P, bool INV>
+__device__ __forceinline__ void fft1_passes(float2 (&x)[FftShape<N>::RR], float2* lx, const float2* twt,
+                                            const PassTwRegs<N, P>& w, int t) {
+  if constexpr (P < FftShape<N>::passes()) {
+    PassTwRegs<N, P + 1> w_next;
+    load_pass_tw<N, P + 1>(w_next, twt, t);
+    fft1_pass<N, P, INV>(x, lx, w, t);
+    fft1_passes<N, P + 1, INV>(x, lx, twt, w_next, t);
+  }
+}
+
+// Unnormalised size-N DFT of one owned register set; same conventions as fft.
+template <int N, bool INV>
+__device__ __forceinline__ void fft1(float2 (&x)[FftShape<N>::RR], float2* lx, const float2* twt, int t) {
+  PassTwRegs<N, 0> w0;
+  __syncthreads();
+  fft1_passes<N, 0, INV>(x, lx, twt, w0, t);
+}
+
 }  // namespace cbessfm

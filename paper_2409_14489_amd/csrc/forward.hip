@@ -22,8 +22,11 @@ namespace cbessfm {
 // One overlap-and-save block of one instance, as member c.me of a team.
 // sub = batch entry * nblk + block; the team's exchange rounds for this block
 // are round0 .. round0 + steps + 1.  xs_in / xs_out: the team's two spectrum
-// slots; xp_team: its two intensity-row slots.
-template <int N, bool DUAL>
+// slots; xp_team: its two slots of intensity rows or spectra (n_sb x 2 N'
+// words each).
+// FIR: 0 time-domain coupled filter, 1 frequency domain, 2 as the instance's
+// tables say (batches mixing instances of both kinds).
+template <int N, bool DUAL, int FIR>
 __device__ __forceinline__ void fwd_item(TeamCtx& c, const Inst& d, int sub, unsigned round0, uint64_t* xs_in,
                                          uint64_t* xs_out, uint64_t* xp_team, float* lf) {
   using S = FftShape<N>;
@@ -53,13 +56,16 @@ __device__ __forceinline__ void fwd_item(TeamCtx& c, const Inst& d, int sub, uns
     intensity<N>(x, y, p);
     const size_t crow = ((size_t)(s * nsb + me) * nsb) * tap_pad;
     const unsigned round = round0 + 1u + (unsigned)s * (DUAL ? 2u : 1u);
-    uint64_t* xrow = xp_team + (size_t)(round & 1u) * nsb * N;
-    coupled_fir<N>(c, d.tab.cpad + crow, xrow, round, p, theta, lf);
+    uint64_t* xrow = xp_team + (size_t)(round & 1u) * nsb * 2 * N;
+    if (!DUAL && (FIR == 1 || (FIR == 2 && d.tab.chat != nullptr)))
+      coupled_fir_freq<N>(c, d.tab.chat + ((size_t)(s * nsb + me) * nsb) * N, xrow, round, p, theta, lf);
+    else
+      coupled_fir<N>(c, d.tab.cpad + crow, xrow, round, p, theta, lf);
     if (DUAL) {
       // theta^{x,y} = theta +- phi, phi_i = (1/3) sum_{l != i} C_il (*) (|x_l|^2 - |y_l|^2)
       float phi[RR];
       intensity_diff<N>(x, y, p);
-      uint64_t* drow = xp_team + (size_t)((round + 1u) & 1u) * nsb * N;
+      uint64_t* drow = xp_team + (size_t)((round + 1u) & 1u) * nsb * 2 * N;
       coupled_fir<N>(c, d.tab.cdpad + crow, drow, round + 1u, p, phi, lf);
       rotate_dual<N>(x, y, theta, phi);
     } else {
@@ -80,7 +86,7 @@ __device__ __forceinline__ void fwd_item(TeamCtx& c, const Inst& d, int sub, uns
 // Single plan: team j takes blocks j, j + n_teams, ...  The n_sb members of a
 // team share blockIdx mod 8, i.e. one XCD and its L2 (workgroups are dispatched
 // round-robin over the 8 XCDs).
-template <int LOGN, bool DUAL>
+template <int LOGN, bool DUAL, int FIR>
 __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void fwd_kernel(FwdArgs a) {
   constexpr int N = 1 << LOGN;  // N'
   __shared__ __align__(16) float lf[lds_floats<N>()];
@@ -100,11 +106,11 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void fwd_kernel(FwdArgs 
   const unsigned rounds_per_item = fwd_rounds(a.inst.steps, DUAL);
   uint64_t* xs_in = a.xspec + ((size_t)c.team * 2 + 0) * nsb * 4 * N;
   uint64_t* xs_out = a.xspec + ((size_t)c.team * 2 + 1) * nsb * 4 * N;
-  uint64_t* xp_team = a.xp + (size_t)c.team * 2 * nsb * N;
+  uint64_t* xp_team = a.xp + (size_t)c.team * 2 * nsb * 2 * N;
   const unsigned first = epoch_begin(a.epoch + c.team, &epoch_word);
   unsigned iter = 0;
   for (int item = c.team; item < a.n_items; item += a.n_teams, ++iter)
-    fwd_item<N, DUAL>(c, a.inst, item, first + iter * rounds_per_item, xs_in, xs_out, xp_team, lf);
+    fwd_item<N, DUAL, FIR>(c, a.inst, item, first + iter * rounds_per_item, xs_in, xs_out, xp_team, lf);
   epoch_end(a.epoch + c.team, first, iter * rounds_per_item, c.me);
 }
 
@@ -136,7 +142,7 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void fwd_batch_kernel(Ba
     c.n_chunks = d.n_chunks;
     c.nc = d.nc;
     c.tab = &d.tab;
-    fwd_item<N, false>(c, d, it.sub, first + it.round_off, xs_in, xs_out, xp_team, lf);
+    fwd_item<N, false, 2>(c, d, it.sub, first + it.round_off, xs_in, xs_out, xp_team, lf);
   }
   epoch_end(epoch, first, tm.rounds, c.me);
 }
@@ -208,6 +214,26 @@ __global__ void pad_coeffs_kernel(const float* __restrict__ src, float* __restri
 
 __global__ void copy_rho_kernel(const float* __restrict__ src, double* __restrict__ dst) { *dst = (double)*src; }
 
+// chat[row][k] = sum_t c[row][t] exp(-j 2 pi k (t - Nc) / N'): the DFT of a
+// coefficient row placed circularly (tap t at position t - Nc mod N'), from
+// the plan's twiddle table tw[n] = exp(-j 2 pi n / N'), summed in FP64.
+__global__ void row_dft_kernel(const float* __restrict__ c, const float2* __restrict__ tw, float2* __restrict__ chat,
+                               int rows, int n_taps, int np) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)rows * np) return;
+  const int row = (int)(idx / np), k = (int)(idx - (long long)row * np);
+  const int nc = n_taps / 2;
+  double re = 0.0, im = 0.0;
+  for (int t = 0; t < n_taps; ++t) {
+    const int m = ((t - nc) % np + np) % np;
+    const float2 w = tw[(int)(((long long)k * m) % np)];
+    const double cv = (double)c[(size_t)row * n_taps + t];
+    re += cv * (double)w.x;
+    im += cv * (double)w.y;
+  }
+  chat[idx] = make_float2((float)re, (float)im);
+}
+
 // ------------------------------------------------------------------ launchers
 // True when `s` is recording a graph.  Cooperative launches guarantee that
 // the whole grid is resident; inside a capture an ordinary launch of the same
@@ -234,8 +260,10 @@ static int launch_persistent(K kernel, const A& args, int grid, int threads, hip
 
 template <int LOGN>
 static int launch_fwd_t(const FwdArgs& args, bool dual, int grid, hipStream_t s) {
-  return dual ? launch_persistent(fwd_kernel<LOGN, true>, args, grid, FftShape<(1 << LOGN)>::NT, s)
-              : launch_persistent(fwd_kernel<LOGN, false>, args, grid, FftShape<(1 << LOGN)>::NT, s);
+  constexpr int NT = FftShape<(1 << LOGN)>::NT;
+  if (dual) return launch_persistent(fwd_kernel<LOGN, true, 0>, args, grid, NT, s);
+  return args.inst.tab.chat != nullptr ? launch_persistent(fwd_kernel<LOGN, false, 1>, args, grid, NT, s)
+                                       : launch_persistent(fwd_kernel<LOGN, false, 0>, args, grid, NT, s);
 }
 
 template <int LOGN>
@@ -267,13 +295,21 @@ int threads_for(int log_np) {
   }
 }
 
+// Resident workgroups per CU; for the averaged NLPR the smaller of the time-
+// and frequency-domain filter kernels (the plan's teams fit either).
 template <int LOGN>
 static int occ_t(bool dual, int* blocks) {
-  const hipError_t e =
-      dual ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fwd_kernel<LOGN, true>, FftShape<(1 << LOGN)>::NT, 0)
-           : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fwd_kernel<LOGN, false>, FftShape<(1 << LOGN)>::NT,
-                                                          0);
-  return e == hipSuccess ? CBESSFM_OK : CBESSFM_EHIP;
+  constexpr int NT = FftShape<(1 << LOGN)>::NT;
+  if (dual)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fwd_kernel<LOGN, true, 0>, NT, 0) == hipSuccess
+               ? CBESSFM_OK
+               : CBESSFM_EHIP;
+  int bt = 0, bf = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bt, fwd_kernel<LOGN, false, 0>, NT, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&bf, fwd_kernel<LOGN, false, 1>, NT, 0) != hipSuccess)
+    return CBESSFM_EHIP;
+  *blocks = bt < bf ? bt : bf;
+  return CBESSFM_OK;
 }
 
 template <int LOGN>
@@ -317,6 +353,7 @@ void fill_tables(const cbessfm_plan_t* p, Tables& tb) {
   tb.poly_tw = p->d_poly;
   tb.cpad = p->d_cpad;
   tb.cdpad = p->d_cdpad;
+  tb.chat = p->fir_freq ? p->d_chat : nullptr;
   for (int i = 0; i < kMaxSubbands; ++i) tb.wsb[i] = p->wsb[i];
 }
 
@@ -374,6 +411,11 @@ int launch_pad_coeffs(cbessfm_plan_t* p, const float* src, hipStream_t s) {
   const int total = rows * p->tap_pad;
   pad_coeffs_kernel<<<(total + 255) / 256, 256, 0, s>>>(src, p->d_cpad, p->d_ctpad, p->d_cdpad, p->steps,
                                                        p->sb.n_sb, p->n_taps, p->tap_pad);
+  if (p->fir_freq) {
+    const long long cells = (long long)rows * p->Np;
+    row_dft_kernel<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(src, p->d_tw, p->d_chat, rows, p->n_taps,
+                                                                  p->Np);
+  }
   return hipGetLastError() == hipSuccess ? CBESSFM_OK : CBESSFM_EHIP;
 }
 

@@ -24,6 +24,8 @@ struct Tables {
   const float2* poly_tw;  // [n_sb][N'] exp(-j 2 pi i k / N)
   const float* cpad;      // [steps][n_sb][n_sb][tap_pad] applied coefficients, zero padded
   const float* cdpad;     // the same with a zero diagonal, divided by 3 (dual-polarisation NLPR)
+  const float2* chat;     // [steps][n_sb][n_sb][N'] DFT of each coefficient row placed circularly
+                          // (tap t at position t - Nc mod N'), natural bin order; NULL: time-domain filter
   float2 wsb[kMaxSubbands];  // exp(-j 2 pi a / n_sb)
 };
 
@@ -55,7 +57,8 @@ struct FwdArgs {
   int n_teams;        // persistent teams of n_sb workgroups
   unsigned* epoch;    // [teams] exchange rounds completed so far by each team (device)
   uint64_t* xspec;    // [team_capacity][2 slots][n_sb][4 comps][N']  tagged spectra
-  uint64_t* xp;       // [team_capacity][2 slots][n_sb][N']           tagged intensities
+  uint64_t* xp;       // [team_capacity][2 slots][n_sb][2 N']         tagged intensities (N' words) or
+                      // intensity spectra (re then im, 2 N' words) per member
   XchgCtl ctl;
 };
 
@@ -176,6 +179,7 @@ struct cbessfm_plan {
   int nlpr;               // CBESSFM_NLPR_AVERAGED or CBESSFM_NLPR_DUAL_POL
   int gvd_explicit;       // 1: dispersion segment lengths from d_len, else (1 - rho) L, L, ..., rho L
   int bwd_team_capacity;  // the same for the adjoint kernel
+  int fir_freq;           // 1: the forward evaluates the coupled filter in the frequency domain
   int xchg_teams;         // teams the exchange buffers are sized for
   unsigned wait_limit;    // polls before an exchange wait gives up (cbessfm_set_wait_limit)
   // device memory
@@ -188,6 +192,7 @@ struct cbessfm_plan {
   float* d_cpad;      // padded copy used by the kernels
   float* d_ctpad;     // transposed, tap-reversed padded copy (adjoint)
   float* d_cdpad;     // padded copy with zero diagonal, / 3 (dual-polarisation NLPR)
+  float2* d_chat;     // [steps][n_sb][n_sb][N'] row DFTs (frequency-domain filter only)
   double* d_rho;      // current split ratio
   double* d_len;      // [steps + 1] explicit dispersion segment lengths, km
   uint64_t* d_xspec;  // tagged exchange words

@@ -48,6 +48,8 @@ int check_layout(const cbessfm_subbands* sb) {
   if (sb->block_sb > 8192 && sb->block_sb < (1 << cbessfm::kStreamMinLog)) return CBESSFM_EUNSUPPORTED;
   const long long n = (long long)sb->n_sb * sb->block_sb;
   if (sb->overlap < 0 || sb->overlap >= n || (sb->overlap & 1)) return CBESSFM_EINVAL;
+  if (sb->fir_mode < CBESSFM_FIR_AUTO || sb->fir_mode > CBESSFM_FIR_FREQ) return CBESSFM_EINVAL;
+  if (sb->fir_mode == CBESSFM_FIR_FREQ && sb->block_sb > 8192) return CBESSFM_EUNSUPPORTED;
   if (sb->boundary != 0 && sb->boundary != 1) return CBESSFM_EINVAL;
   return CBESSFM_OK;
 }
@@ -118,8 +120,8 @@ namespace {
 size_t xspec_bytes(const cbessfm_plan_t* p) {
   return sizeof(uint64_t) * (size_t)p->xchg_teams * 2 * p->sb.n_sb * 4 * p->Np;
 }
-size_t xp_bytes(const cbessfm_plan_t* p) {
-  return sizeof(uint64_t) * (size_t)p->xchg_teams * 2 * p->sb.n_sb * p->Np;
+size_t xp_bytes(const cbessfm_plan_t* p) {  // room for the spectra of the frequency-domain filter
+  return sizeof(uint64_t) * (size_t)p->xchg_teams * 2 * p->sb.n_sb * 2 * p->Np;
 }
 
 }  // namespace
@@ -291,8 +293,8 @@ void cbessfm_destroy(cbessfm_plan_t* p) {
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(p->device);
   void* bufs[] = {p->d_phase, p->d_h,     p->d_tw,    p->d_poly, p->d_c,     p->d_cpad,  p->d_ctpad,
-                  p->d_cdpad, p->d_rho,   p->d_len,   p->d_xspec, p->d_xp,  p->d_xq,    p->d_epoch,
-                  p->d_abort, p->d_err,   p->d_st,    p->d_pb,    p->d_th};
+                  p->d_cdpad, p->d_chat,  p->d_rho,   p->d_len,   p->d_xspec, p->d_xp,  p->d_xq,
+                  p->d_epoch, p->d_abort, p->d_err,   p->d_st,    p->d_pb,    p->d_th};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   (void)hipSetDevice(prev);
@@ -364,6 +366,11 @@ int cbessfm_plan(cbessfm_plan_t** out, const cbessfm_link* link, const cbessfm_s
   }
   p->nlpr = CBESSFM_NLPR_AVERAGED;
   p->wait_limit = kDefaultWaitLimit;
+  // auto: the frequency-domain filter costs about two single-array transforms
+  // per step whatever the tap count; the direct sum grows with n_sb x n_taps
+  // and is cheaper up to 64 taps (measured crossover 45..100 taps)
+  p->fir_freq = !p->stream && (sb->fir_mode == CBESSFM_FIR_FREQ ||
+                               (sb->fir_mode == CBESSFM_FIR_AUTO && coeffs->n_taps > 8 * kTapChunk));
 
   const int N = p->N, Np = p->Np, nsb = sb->n_sb;
   const size_t crows = (size_t)steps * nsb * nsb;
@@ -434,6 +441,7 @@ int cbessfm_plan(cbessfm_plan_t** out, const cbessfm_link* link, const cbessfm_s
   alloc((void**)&p->d_cpad, sizeof(float) * crows * p->tap_pad);
   alloc((void**)&p->d_ctpad, sizeof(float) * crows * p->tap_pad);
   alloc((void**)&p->d_cdpad, sizeof(float) * crows * p->tap_pad);
+  if (p->fir_freq) alloc((void**)&p->d_chat, sizeof(float2) * crows * Np);
   alloc((void**)&p->d_rho, sizeof(double));
   alloc((void**)&p->d_len, sizeof(double) * (size_t)(steps + 1));
   if (p->stream) {

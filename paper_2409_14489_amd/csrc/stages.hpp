@@ -342,6 +342,62 @@ __device__ __forceinline__ void coupled_fir(const TeamCtx& c, const float* __res
   for (int o = 0; o < RR; ++o) out[o] = th[pad_r(t + NT * o)];
 }
 
+// The coupled filter of eq. (15) in the frequency domain (the paper's form,
+// Sec. III-A and Fig. "scheme_NLPR"): the member's intensity row is
+// transformed (P_me = DFT(p), a complex transform of the real row), the
+// spectra are exchanged, and
+//   theta_me = (1/N') IDFT( sum_l chat[me][l] P_l ),
+// chat[me][l] = DFT of coefficient row (me, l) placed circularly.  The same
+// circular map as coupled_fir.  xrow: the team's exchange slot, member l's
+// spectrum at xrow + 2 N' l (real parts, then imaginary parts); chat_me: the
+// member's N_sb rows of N' bins for this step.  Result at t + NT o.
+template <int N>
+__device__ __forceinline__ void coupled_fir_freq(const TeamCtx& c, const float2* __restrict__ chat_me,
+                                                uint64_t* xrow, unsigned tag, const float (&own)[FftShape<N>::RR],
+                                                float (&out)[FftShape<N>::RR], float* lf) {
+  constexpr int RR = FftShape<N>::RR, NT = FftShape<N>::NT;
+  const int nsb = c.nsb, me = c.me;
+  const float2* tw = c.tab->tw;
+  float2* lx = reinterpret_cast<float2*>(lf);
+  int t = opaque_tid();
+  float2 z[RR];
+#pragma unroll
+  for (int o = 0; o < RR; ++o) z[o] = make_float2(own[o], 0.0f);
+  fft1<N, false>(z, lx, tw, t);  // P_me at bins t + NT o
+  t = opaque_tid();
+  if (nsb > 1) {
+    uint64_t* row = xrow + (size_t)me * 2 * N;
+#pragma unroll
+    for (int o = 0; o < RR; ++o) {
+      xput(row + t + NT * o, z[o].x, tag);
+      xput(row + N + t + NT * o, z[o].y, tag);
+    }
+  }
+  float2 acc[RR];
+  {
+    const float2* cm = chat_me + (size_t)me * N;
+#pragma unroll
+    for (int o = 0; o < RR; ++o) acc[o] = cmul(cm[t + NT * o], z[o]);
+  }
+  for (int l = 0; l < nsb; ++l) {
+    if (l == me) continue;
+    const uint64_t* row = xrow + (size_t)l * 2 * N;
+    uint64_t wr[RR], wi[RR];
+    xissue<RR>(row, t, NT, wr);
+    xissue<RR>(row + N, t, NT, wi);
+    float re[RR], im[RR];
+    xcomplete<RR>(row, t, NT, tag, c.ctl, wr, re);
+    xcomplete<RR>(row + N, t, NT, tag, c.ctl, wi, im);
+    const float2* cl = chat_me + (size_t)l * N;
+#pragma unroll
+    for (int o = 0; o < RR; ++o) acc[o] = cadd(acc[o], cmul(cl[t + NT * o], make_float2(re[o], im[o])));
+  }
+  fft1<N, true>(acc, lx, tw, t);
+  constexpr float inv_n = 1.0f / (float)N;
+#pragma unroll
+  for (int o = 0; o < RR; ++o) out[o] = acc[o].x * inv_n;
+}
+
 // x / y *= exp(-+ j theta): '-' (SIGN = -1) is the rotation of eq. (3).
 template <int N, int SIGN>
 __device__ __forceinline__ void rotate(float2 (&x)[FftShape<N>::RR], float2 (&y)[FftShape<N>::RR],

@@ -13,7 +13,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import Coeffs, Info, Link, Subbands, check, lib
+from ._lib import FIR_MODES, Coeffs, Info, Link, Subbands, check, lib
 
 
 @dataclass
@@ -39,10 +39,12 @@ class LinkSpec:
 _BOUNDARY = {"circular": 0, "zero": 1}
 
 
-def _subbands(n_sb: int, block_sb: int, overlap: int, boundary: str) -> Subbands:
+def _subbands(n_sb: int, block_sb: int, overlap: int, boundary: str, fir_mode: str = "auto") -> Subbands:
     if boundary not in _BOUNDARY:
         raise ValueError("boundary must be 'circular' or 'zero'")
-    return Subbands(int(n_sb), int(block_sb), int(overlap), _BOUNDARY[boundary])
+    if fir_mode not in FIR_MODES:
+        raise ValueError("fir_mode must be 'auto', 'time' or 'freq'")
+    return Subbands(int(n_sb), int(block_sb), int(overlap), FIR_MODES[fir_mode], _BOUNDARY[boundary])
 
 
 def _coeff_struct(coeffs, n_taps, grid_m):
@@ -54,9 +56,9 @@ def _coeff_struct(coeffs, n_taps, grid_m):
 
 
 def plan_check(link: LinkSpec, n_sb: int, block_sb: int, overlap: int, steps: int, split_ratio: float,
-               n_taps: int, boundary: str = "circular", grid_m: int = 0) -> int:
+               n_taps: int, boundary: str = "circular", grid_m: int = 0, fir_mode: str = "auto") -> int:
     """Host-only validation (``cbessfm_plan_check``); returns the C error code."""
-    lk, sb = link.c(), _subbands(n_sb, block_sb, overlap, boundary)
+    lk, sb = link.c(), _subbands(n_sb, block_sb, overlap, boundary, fir_mode)
     co = Coeffs(int(n_taps), None, int(grid_m))
     return lib.cbessfm_plan_check(ctypes.byref(lk), ctypes.byref(sb), int(steps), float(split_ratio),
                                   ctypes.byref(co))
@@ -67,7 +69,7 @@ def analytic_coeffs(link: LinkSpec, n_sb: int, steps: int, split_ratio: float, n
     """Applied analytic coefficients [steps][n_sb][n_sb][n_taps] in FP64 (host)."""
     out = np.empty((steps, n_sb, n_sb, n_taps), dtype=np.float64)
     lk = link.c()
-    sb = Subbands(int(n_sb), 256, 0, 0)
+    sb = Subbands(int(n_sb), 256, 0, 0, 0)
     check(lib.cbessfm_analytic_coeffs(ctypes.byref(lk), ctypes.byref(sb), int(steps), float(split_ratio),
                                       int(n_taps), int(grid_m),
                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
@@ -85,18 +87,20 @@ class Plan:
 
     coeffs: applied coefficients [steps][n_sb][n_sb][n_taps] (rad/W, 3/2 and
     DBP sign included), or None for the analytic ones (then ``n_taps`` is
-    required).
+    required).  fir_mode: "auto", "time" or "freq", how the forward evaluates
+    the coupled filter (``cbessfm_subbands.fir_mode``).
     """
 
     def __init__(self, link: LinkSpec, n_sb: int, block_sb: int, overlap: int, steps: int,
                  split_ratio: float, coeffs=None, n_taps: int | None = None, grid_m: int = 0,
-                 boundary: str = "circular"):
+                 boundary: str = "circular", fir_mode: str = "auto"):
         if coeffs is None and n_taps is None:
             raise ValueError("give coeffs or n_taps")
         self.link = link
         self.n_sb, self.block_sb, self.overlap, self.steps = int(n_sb), int(block_sb), int(overlap), int(steps)
         self.boundary = boundary
-        lk, sb = link.c(), _subbands(n_sb, block_sb, overlap, boundary)
+        self.fir_mode = fir_mode
+        lk, sb = link.c(), _subbands(n_sb, block_sb, overlap, boundary, fir_mode)
         co, keep = _coeff_struct(coeffs, n_taps, grid_m)
         self.n_taps = co.n_taps
         self.nlpr = "averaged"

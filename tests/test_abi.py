@@ -99,3 +99,16 @@ def test_manakov_flag_scales_gamma():
     a = analytic_coeffs(LinkSpec(), 1, 1, 0.5, 5)
     b = analytic_coeffs(LinkSpec(manakov_8_9=True), 1, 1, 0.5, 5)
     assert np.allclose(b, a * 8 / 9, rtol=1e-13)
+
+
+def test_fir_mode_validation():
+    from paper_2409_14489_amd._lib import EINVAL, EUNSUPPORTED, OK
+    assert plan_check(LINK, 5, 4096, 2560, 15, 0.3, 21, fir_mode="freq") == OK
+    assert plan_check(LINK, 5, 4096, 2560, 15, 0.3, 21, fir_mode="time") == OK
+    assert plan_check(LINK, 5, 2 ** 15, 2560, 15, 0.3, 21, fir_mode="freq") == EUNSUPPORTED
+    assert plan_check(LINK, 5, 2 ** 15, 2560, 15, 0.3, 21, fir_mode="auto") == OK
+    import ctypes
+    from paper_2409_14489_amd._lib import Coeffs, Subbands, lib
+    sb = Subbands(2, 1024, 0, 3, 0)
+    co = Coeffs(11, None, 0)
+    assert lib.cbessfm_plan_check(ctypes.byref(LINK.c()), ctypes.byref(sb), 2, 0.5, ctypes.byref(co)) == EINVAL

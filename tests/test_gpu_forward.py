@@ -257,3 +257,43 @@ def test_exchange_wait_give_up_is_reported_and_recovers(wdm5):
     assert g.status() == 0
     assert torch.equal(again[1], ref[1]) and torch.equal(again[2], ref[2])
     g.close()
+
+
+@pytest.mark.parametrize("n_sb,block_sb,taps", [(1, 1024, 1), (2, 512, 21), (5, 1024, 45), (3, 256, 101),
+                                                (2, 4096, 255), (8, 256, 33), (2, 8192, 65)])
+def test_frequency_domain_filter_matches_oracle(n_sb, block_sb, taps):
+    """fir_mode 'freq' (the paper's RFFT / MIMO / IRFFT form of eq. (15),
+    Sec. III-A) against the oracle's literal double sum, whole output and every
+    block, and against the time-domain mode of the same plan shape."""
+    power = 4e-3
+    n = n_sb * block_sb
+    x = random_field((2, 3 * n + 33), 700 + taps, power_w=power)
+    c = rand_coeffs(3, n_sb, taps, 0.5, power, taps)
+    from paper_2409_14489_amd import LinkSpec, Plan
+    link = LinkSpec(beta2_ps2_km=BETA2_PS2, n_spans=2, sample_rate_hz=n_sb * 64e9)
+    outs = {}
+    for mode in ("freq", "time"):
+        g = Plan(link, n_sb, block_sb, n // 8, 3, 0.3, coeffs=c.astype(np.float32), fir_mode=mode)
+        outs[mode] = run_gpu(g, x)
+        hop = g.hop
+        g.close()
+    ref = oracle.run(x, oracle_plan(n_sb, block_sb, n // 8, 3, 0.3, c, spans=2, rate=n_sb * 64e9))
+    assert_parity(outs["freq"], ref, hop)
+    assert rel_l2(outs["freq"], outs["time"]) < 2e-6
+
+
+def test_auto_filter_mode_and_set_coeffs_in_frequency_mode():
+    """Above 64 taps 'auto' takes the frequency domain; a coefficient update on
+    the device re-derives the row DFTs."""
+    from paper_2409_14489_amd import LinkSpec, Plan
+    power = 4e-3
+    x = random_field((2, 9000), 71, power_w=power)
+    c1 = rand_coeffs(2, 2, 81, 0.5, power, 1)
+    c2 = rand_coeffs(2, 2, 81, 0.5, power, 2)
+    link = LinkSpec(beta2_ps2_km=BETA2_PS2, n_spans=1, sample_rate_hz=128e9)
+    g = Plan(link, 2, 1024, 256, 2, 0.4, coeffs=c1.astype(np.float32))
+    g.set_coeffs(torch.from_numpy(c2.astype(np.float32)).cuda())
+    y = run_gpu(g, x)
+    ref = oracle.run(x, oracle_plan(2, 1024, 256, 2, 0.4, c2, rate=128e9))
+    assert_parity(y, ref, g.hop)
+    g.close()
