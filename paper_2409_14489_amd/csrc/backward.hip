@@ -296,8 +296,7 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdAr
   auto vt = [&](int slot) { return team_vt + ((size_t)slot * nsb + me) * vt_sz; };
   float2* gsv = a.gsave + ((size_t)c.team * nsb + me) * 2 * N;  // reused by every reverse step
   const int last0 = (a.n_ck - 1) * k;  // first step of the last segment
-  uint64_t* xs_a = a.xspec + ((size_t)c.team * 2 + 0) * nsb * 4 * N;
-  uint64_t* xs_b = a.xspec + ((size_t)c.team * 2 + 1) * nsb * 4 * N;
+  uint64_t* xs_team = a.xspec + (size_t)c.team * 2 * nsb * 4 * N;
   const double* phase_km = a.phase + (size_t)me * N;
   const unsigned first = epoch_begin(a.epoch + c.team, &epoch_word);
 
@@ -306,6 +305,10 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdAr
     int t = opaque_tid();
     unsigned rnd = first + iter * a.rounds_per_item;
     unsigned np = 0, nq = 0;  // p- and theta_bar-rounds so far (slot parity)
+    // one spectrum slot for the three spectrum rounds of this block (the step
+    // rounds between them keep the exchange's reuse rule); the next block
+    // takes the other slot
+    uint64_t* xs = xs_team + (size_t)(iter & 1u) * nsb * 4 * N;
     const int inst = item / a.nblk;
     const int blk = item - inst * a.nblk;
     float2 x[RR], y[RR], gx[RR], gy[RR];
@@ -359,7 +362,7 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdAr
     const float2* in_x = a.in + (size_t)inst * 2 * T;
     gather_block<N, false>(in_x, in_x + T, blk, a.hop, a.n_ov, T, a.boundary, nsb, me, t, x, y);
     fft<N, false>(x, y, lxy, tw, t);
-    polyphase_to_subband<N>(c, xs_a, rnd++, t, x, y);
+    polyphase_to_subband<N>(c, xs, rnd++, t, x, y);
     for (int s = 0; s < a.steps; ++s) {
       if (s % k == 0) store_state<N>(sp(s / k), x, y, opaque_tid());
       forward_step(s, s >= last0 ? vt(s - last0) : nullptr, true);
@@ -371,7 +374,7 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdAr
     const float2* go_x = a.gout + (size_t)inst * 2 * T;
     gather_block<N, true>(go_x, go_x + T, blk, a.hop, a.n_ov, T, a.boundary, nsb, me, t, gx, gy);
     fft<N, false>(gx, gy, lxy, tw, t);
-    polyphase_to_subband<N>(c, xs_b, rnd++, t, gx, gy);  // g_B
+    polyphase_to_subband<N>(c, xs, rnd++, t, gx, gy);  // g_B
     if (a.lpart != nullptr) {
       // dL/d(length of the last dispersion segment) = -sum phi Im(conj(g_B) B)
       const double tb = rho_term<N>(phase_km, 1.0, t, gx, gy, x, y);
@@ -466,7 +469,7 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdAr
     // ---- D: adjoint of the input stage (optional)
     if (a.gin_blk != nullptr) {
       t = opaque_tid();
-      subband_to_polyphase<N>(c, xs_b, rnd++, t, gx, gy);
+      subband_to_polyphase<N>(c, xs, rnd++, t, gx, gy);
       fft<N, true>(gx, gy, lxy, tw, t);
       float2* dst = a.gin_blk + (size_t)item * 2 * nsb * N;
 #pragma unroll

@@ -21,14 +21,18 @@ namespace cbessfm {
 
 // One overlap-and-save block of one instance, as member c.me of a team.
 // sub = batch entry * nblk + block; the team's exchange rounds for this block
-// are round0 .. round0 + steps + 1.  xs_in / xs_out: the team's two spectrum
-// slots; xp_team: its two slots of intensity rows or spectra (n_sb x 2 N'
+// are round0 .. round0 + steps + 1.  xs: one of the team's two spectrum slots
+// (n_sb x 4 N' words), used by both the input and the output exchange of this
+// block: the step rounds between them keep the reuse rule of the exchange, and
+// the team's next block takes the other slot.  Keeping to one slot per block
+// halves the exchange memory a block touches, so more of it stays in the L2.
+// xp_team: the team's two slots of intensity rows or spectra (n_sb x 2 N'
 // words each).
 // FIR: 0 time-domain coupled filter, 1 frequency domain, 2 as the instance's
 // tables say (batches mixing instances of both kinds).
 template <int N, bool DUAL, int FIR>
-__device__ __forceinline__ void fwd_item(TeamCtx& c, const Inst& d, int sub, unsigned round0, uint64_t* xs_in,
-                                         uint64_t* xs_out, uint64_t* xp_team, float* lf) {
+__device__ __forceinline__ void fwd_item(TeamCtx& c, const Inst& d, int sub, unsigned round0, uint64_t* xs,
+                                         uint64_t* xp_team, float* lf) {
   using S = FftShape<N>;
   constexpr int RR = S::RR;
   float4* lxy = reinterpret_cast<float4*>(lf);
@@ -45,7 +49,7 @@ __device__ __forceinline__ void fwd_item(TeamCtx& c, const Inst& d, int sub, uns
   // ---- block input: size-N DFT as N_sb polyphase FFTs + N_sb-point DFT
   gather_block<N, false>(in_x, in_x + T, blk, d.hop, d.n_ov, T, d.boundary, nsb, me, t, x, y);
   fft<N, false>(x, y, lxy, tw, t);
-  polyphase_to_subband<N>(c, xs_in, round0, t, x, y);
+  polyphase_to_subband<N>(c, xs, round0, t, x, y);
 
   // ---- step loop (Fig. "scheme_CB-ESSFM"), spectra in subband order
   for (int s = 0; s < d.steps; ++s) {
@@ -77,7 +81,7 @@ __device__ __forceinline__ void fwd_item(TeamCtx& c, const Inst& d, int sub, uns
   // ---- final GVD, recombination, inverse size-N DFT, kept samples
   t = opaque_tid();
   apply_diag<N, false>(x, y, d.tab.h_last + (size_t)me * N, t);
-  subband_to_polyphase<N>(c, xs_out, round0 + fwd_rounds(d.steps, DUAL) - 1u, t, x, y);
+  subband_to_polyphase<N>(c, xs, round0 + fwd_rounds(d.steps, DUAL) - 1u, t, x, y);
   fft<N, true>(x, y, lxy, tw, t);
   float2* out_x = d.out + (size_t)inst * 2 * T;
   scatter_block<N>(out_x, out_x + T, blk, d.hop, d.n_ov, T, nsb, me, t, x, y);
@@ -104,13 +108,13 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void fwd_kernel(FwdArgs 
   c.tab = &a.inst.tab;
   const int nsb = c.nsb;
   const unsigned rounds_per_item = fwd_rounds(a.inst.steps, DUAL);
-  uint64_t* xs_in = a.xspec + ((size_t)c.team * 2 + 0) * nsb * 4 * N;
-  uint64_t* xs_out = a.xspec + ((size_t)c.team * 2 + 1) * nsb * 4 * N;
+  uint64_t* xs_team = a.xspec + (size_t)c.team * 2 * nsb * 4 * N;
   uint64_t* xp_team = a.xp + (size_t)c.team * 2 * nsb * 2 * N;
   const unsigned first = epoch_begin(a.epoch + c.team, &epoch_word);
   unsigned iter = 0;
   for (int item = c.team; item < a.n_items; item += a.n_teams, ++iter)
-    fwd_item<N, DUAL, FIR>(c, a.inst, item, first + iter * rounds_per_item, xs_in, xs_out, xp_team, lf);
+    fwd_item<N, DUAL, FIR>(c, a.inst, item, first + iter * rounds_per_item,
+                           xs_team + (size_t)(iter & 1u) * nsb * 4 * N, xp_team, lf);
   epoch_end(a.epoch + c.team, first, iter * rounds_per_item, c.me);
 }
 
@@ -131,8 +135,7 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void fwd_batch_kernel(Ba
   c.me = wg.y;
   c.team = wg.x;
   c.ctl = a.ctl;
-  uint64_t* xs_in = a.xspec + tm.xspec_off;
-  uint64_t* xs_out = xs_in + (size_t)c.nsb * 4 * N;
+  uint64_t* xs_team = a.xspec + tm.xspec_off;
   uint64_t* xp_team = a.xp + tm.xp_off;
   unsigned* epoch = a.epoch + tm.epoch_slot;
   const unsigned first = epoch_begin(epoch, &epoch_word);
@@ -142,7 +145,8 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void fwd_batch_kernel(Ba
     c.n_chunks = d.n_chunks;
     c.nc = d.nc;
     c.tab = &d.tab;
-    fwd_item<N, false, 2>(c, d, it.sub, first + it.round_off, xs_in, xs_out, xp_team, lf);
+    fwd_item<N, false, 2>(c, d, it.sub, first + it.round_off, xs_team + (size_t)(k & 1) * c.nsb * 4 * N, xp_team,
+                          lf);
   }
   epoch_end(epoch, first, tm.rounds, c.me);
 }
