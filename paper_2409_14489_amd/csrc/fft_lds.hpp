@@ -195,6 +195,11 @@ struct FftShape {
     return p;
   }
   static constexpr int LDS_C = pad_c_size(N);  // float2 entries per polarisation (float4 entries in all)
+  // Two exchange buffers (passes alternate between them, so a pass needs no
+  // barrier between its reads and its writes) where they fit the LDS beside
+  // one workgroup's other use: N' <= 4096 (2 x 74 KB).
+  static constexpr bool DB = N <= 4096;
+  static constexpr int LDS_ENTRIES = DB ? 2 * LDS_C : LDS_C;  // float4 entries of the exchange
 };
 
 // Twiddle registers of pass P: NB butterflies x (R - 1) factors (one dummy
@@ -231,11 +236,15 @@ __device__ __forceinline__ void load_pass_tw(PassTwRegs<N, P>& w, const float2* 
 // through LDS with one 128-bit access.
 //   FIRST: inputs come from the owned registers (positions t + NT o)
 //   LAST : outputs go to the owned registers
-// Otherwise inputs are read from / outputs written to LDS.
-template <int N, int P, bool INV>
+// Otherwise inputs are read from / outputs written to LDS.  With DB, pass p
+// writes buffer p mod 2 and reads buffer (p - 1) mod 2: every reader of the
+// buffer a pass writes has passed the barrier that ended the previous pass.
+template <int N, int P, bool INV, bool DB>
 __device__ __forceinline__ void fft_pass(float2 (&x)[FftShape<N>::RR], float2 (&y)[FftShape<N>::RR],
                                          float4* __restrict__ lxy, const PassTwRegs<N, P>& w, int t) {
   using S = FftShape<N>;
+  const float4* rd = DB ? lxy + ((P + 1) & 1) * S::LDS_C : lxy;
+  float4* wr = DB ? lxy + (P & 1) * S::LDS_C : lxy;
   constexpr int R = S::radix(P);
   constexpr int L = S::stride(P);
   constexpr int NB = S::RR / R;           // butterflies per thread
@@ -252,12 +261,12 @@ __device__ __forceinline__ void fft_pass(float2 (&x)[FftShape<N>::RR], float2 (&
         vx[a][m] = x[a + m * NB];
         vy[a][m] = y[a + m * NB];
       } else {
-        const float4 v = lxy[pad_c(t + S::NT * a + m * NR)];
+        const float4 v = rd[pad_c(t + S::NT * a + m * NR)];
         vx[a][m] = make_float2(v.x, v.y);
         vy[a][m] = make_float2(v.z, v.w);
       }
     }
-  if constexpr (!FIRST && !LAST) __syncthreads();  // everyone has read before anyone writes
+  if constexpr (!DB && !FIRST && !LAST) __syncthreads();  // everyone has read before anyone writes
 #pragma unroll
   for (int a = 0; a < NB; ++a) {
     if constexpr (!FIRST) {
@@ -280,22 +289,22 @@ __device__ __forceinline__ void fft_pass(float2 (&x)[FftShape<N>::RR], float2 (&
         x[a + m * NB] = vx[a][m];
         y[a + m * NB] = vy[a][m];
       } else {
-        lxy[pad_c((j - k) * R + k + m * L)] = make_float4(vx[a][m].x, vx[a][m].y, vy[a][m].x, vy[a][m].y);
+        wr[pad_c((j - k) * R + k + m * L)] = make_float4(vx[a][m].x, vx[a][m].y, vy[a][m].x, vy[a][m].y);
       }
     }
   }
   if constexpr (!LAST) __syncthreads();
 }
 
-template <int N, int P, bool INV>
+template <int N, int P, bool INV, bool DB>
 __device__ __forceinline__ void fft_passes(float2 (&x)[FftShape<N>::RR], float2 (&y)[FftShape<N>::RR],
                                            float4* lxy, const float2* twt, const PassTwRegs<N, P>& w,
                                            int t) {
   if constexpr (P < FftShape<N>::passes()) {
     PassTwRegs<N, P + 1> w_next;
     load_pass_tw<N, P + 1>(w_next, twt, t);  // in flight during this pass
-    fft_pass<N, P, INV>(x, y, lxy, w, t);
-    fft_passes<N, P + 1, INV>(x, y, lxy, twt, w_next, t);
+    fft_pass<N, P, INV, DB>(x, y, lxy, w, t);
+    fft_passes<N, P + 1, INV, DB>(x, y, lxy, twt, w_next, t);
   }
 }
 
@@ -303,24 +312,29 @@ __device__ __forceinline__ void fft_passes(float2 (&x)[FftShape<N>::RR], float2 
 // of the two owned register sets; twt[n] = exp(-j 2 pi n / N) (FP64 values
 // rounded once, read through the caches one pass ahead of their use).
 // Starts with a barrier so that earlier LDS readers are done before the first
-// pass overwrites the exchange buffer (N + N/16 + N/256 + 1 float4 entries).
-template <int N, bool INV>
+// pass overwrites the exchange buffer(s): lxy holds DB ? 2 LDS_C : LDS_C
+// float4 entries (FftShape::LDS_ENTRIES); a caller with room for one buffer
+// only passes DB = false.
+template <int N, bool INV, bool DB = FftShape<N>::DB>
 __device__ __forceinline__ void fft(float2 (&x)[FftShape<N>::RR], float2 (&y)[FftShape<N>::RR], float4* lxy,
                                     const float2* twt, int t) {
   PassTwRegs<N, 0> w0;
   __syncthreads();
-  fft_passes<N, 0, INV>(x, y, lxy, twt, w0, t);
+  fft_passes<N, 0, INV, DB>(x, y, lxy, twt, w0, t);
 }
 
 // ------------------------------------------------------------- one array
 // The same Stockham transform of a single owned register set (a real
 // intensity or phase row of the frequency-domain coupled filter): identical
-// radices, twiddles and layout contract, with the exchange buffer holding one
-// float2 per position (the first 2 (N + N/8 + 1) floats of the buffer).
+// radices, twiddles and layout contract, with two exchange buffers of one
+// float2 per position (the space of one float4 buffer), alternated as in
+// fft_pass.
 template <int N, int P, bool INV>
 __device__ __forceinline__ void fft1_pass(float2 (&x)[FftShape<N>::RR], float2* __restrict__ lx,
                                           const PassTwRegs<N, P>& w, int t) {
   using S = FftShape<N>;
+  const float2* rd = lx + ((P + 1) & 1) * S::LDS_C;
+  float2* wr = lx + (P & 1) * S::LDS_C;
   constexpr int R = S::radix(P);
   constexpr int L = S::stride(P);
   constexpr int NB = S::RR / R;
@@ -335,9 +349,8 @@ __device__ __forceinline__ void fft1_pass(float2 (&x)[FftShape<N>::RR], float2* 
       if constexpr (FIRST)
         vx[a][m] = x[a + m * NB];
       else
-        vx[a][m] = lx[pad_c(t + S::NT * a + m * NR)];
+        vx[a][m] = rd[pad_c(t + S::NT * a + m * NR)];
     }
-  if constexpr (!FIRST && !LAST) __syncthreads();
 #pragma unroll
   for (int a = 0; a < NB; ++a) {
     if constexpr (!FIRST) {
@@ -355,7 +368,7 @@ __device__ __forceinline__ void fft1_pass(float2 (&x)[FftShape<N>::RR], float2* 
       if constexpr (LAST)
         x[a + m * NB] = vx[a][m];
       else
-        lx[pad_c((j - k) * R + k + m * L)] = vx[a][m];
+        wr[pad_c((j - k) * R + k + m * L)] = vx[a][m];
     }
   }
   if constexpr (!LAST) __syncthreads();

@@ -227,6 +227,9 @@ __device__ __forceinline__ void fir_row_fixed(const float* cur, int start, const
 // crow = the member's coefficient rows ([n_sb][8 n_chunks], zero padded).
 // own: this member's row at positions t + NT o; the other rows come from the
 // tagged exchange `xrow` ([n_sb][N'], round `tag`).  Result at t + NT o.
+// Rows are taken in the order me, me + 1, ... (mod n_sb): the member's own
+// row needs no exchange, so the other members' rows travel while it is
+// filtered.
 template <int N>
 __device__ __forceinline__ void coupled_fir(const TeamCtx& c, const float* __restrict__ crow, uint64_t* xrow,
                                            unsigned tag, const float (&own)[FftShape<N>::RR],
@@ -243,19 +246,8 @@ __device__ __forceinline__ void coupled_fir(const TeamCtx& c, const float* __res
 #pragma unroll
     for (int o = 0; o < RR; ++o) xput(xrow + (size_t)me * N + t + NT * o, own[o], tag);
   }
-  {
-    const bool remote0 = nsb > 1 && me != 0;
-    uint64_t w0[RR];
-    if (remote0) xissue<RR>(xrow, t, NT, w0);  // in flight across the barrier
-    __syncthreads();  // the LDS rows alias the FFT exchange buffers
-    if (remote0) {
-      float v[RR];
-      xcomplete<RR>(xrow, t, NT, tag, c.ctl, w0, v);
-      stage_row<N, RR, NT>(lf, v, t, hl, nc);
-    } else {
-      stage_row<N, RR, NT>(lf, own, t, hl, nc);
-    }
-  }
+  __syncthreads();  // the LDS rows alias the FFT exchange buffers
+  stage_row<N, RR, NT>(lf, own, t, hl, nc);
   __syncthreads();
 
   // The row of member l, circularly extended, is W[i] = cur[t RR + i] for this
@@ -270,17 +262,18 @@ __device__ __forceinline__ void coupled_fir(const TeamCtx& c, const float* __res
   float acc[RR];
 #pragma unroll
   for (int q = 0; q < RR; ++q) acc[q] = 0.0f;
-  for (int l = 0; l < nsb; ++l) {
-    const float* cur = lf + (l & 1) * PB;
-    float* nxt = lf + ((l + 1) & 1) * PB;
-    const bool more = l + 1 < nsb;
-    const bool fetch = more && (l + 1 != me);  // next row is remote
-    const uint64_t* nrow = xrow + (size_t)(l + 1) * N;
+  for (int j = 0; j < nsb; ++j) {
+    const float* cur = lf + (j & 1) * PB;
+    float* nxt = lf + ((j + 1) & 1) * PB;
+    const int l = me + j < nsb ? me + j : me + j - nsb;  // the row filtered now
+    const int ln = l + 1 < nsb ? l + 1 : 0;                // the next one (remote)
+    const bool more = j + 1 < nsb;
+    const uint64_t* nrow = xrow + (size_t)ln * N;
     const float* cl = uniform_ptr(crow + (size_t)l * tap_pad);
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       uint64_t w[QB];
-      if (fetch) xissue<QB>(nrow + NT * QB * g, t, NT, w);  // in flight during the filter
+      if (more) xissue<QB>(nrow + NT * QB * g, t, NT, w);  // in flight during the filter
       int start = t * RR + g * QB;  // = t RR + g QB + tap_pad - 8 n_chunks
       switch (c.n_chunks) {  // up to 32 taps: compile-time taps, window read once
         case 1: fir_row_fixed<1, QB>(cur, start, cl, acc + g * QB); break;
@@ -317,18 +310,9 @@ __device__ __forceinline__ void coupled_fir(const TeamCtx& c, const float* __res
         }
       }
       if (more) {  // this part of the next row into the other buffer (last read before the previous barrier)
-        if (fetch) {
-          float v[QB];
-          xcomplete<QB>(nrow + NT * QB * g, t, NT, tag, c.ctl, w, v);
-          stage_row<N, QB, NT>(nxt, v, t + NT * QB * g, hl, nc);
-        } else if constexpr (G == 1) {
-          stage_row<N, RR, NT>(nxt, own, t, hl, nc);
-        } else {
-          float v[QB];
-#pragma unroll
-          for (int o = 0; o < QB; ++o) v[o] = own[g * QB + o];
-          stage_row<N, QB, NT>(nxt, v, t + NT * QB * g, hl, nc);
-        }
+        float v[QB];
+        xcomplete<QB>(nrow + NT * QB * g, t, NT, tag, c.ctl, w, v);
+        stage_row<N, QB, NT>(nxt, v, t + NT * QB * g, hl, nc);
       }
     }
     __syncthreads();

@@ -48,6 +48,10 @@ namespace {
 
 constexpr int kRow = kStreamRow;                  // N1
 constexpr int kRowNT = FftShape<kRow>::NT;        // 512 threads per row workgroup
+// Row transforms use one LDS exchange buffer: two workgroups of 74 KB share a
+// CU, where two buffers each would leave room for one.
+constexpr bool kRowDB = false;
+constexpr int kRowLds = kRowDB ? FftShape<kRow>::LDS_ENTRIES : FftShape<kRow>::LDS_C;
 constexpr int kRowRR = FftShape<kRow>::RR;        // 8 samples per thread
 constexpr int kColThreads = 256;
 
@@ -222,7 +226,7 @@ __global__ __launch_bounds__(kRowNT, 4) void st_row_kernel(const float2* src, fl
                                                         const float2* __restrict__ h,
                                                         const float2* __restrict__ twr, int nsb, int n2,
                                                         int np) {
-  __shared__ __align__(16) float4 lxy[FftShape<kRow>::LDS_C];
+  __shared__ __align__(16) float4 lxy[kRowLds];
   const int i = blockIdx.x / n2, k2 = blockIdx.x - (blockIdx.x / n2) * n2;
   const size_t off = ((size_t)blockIdx.y * nsb + i) * 2 * np + (size_t)k2 * kRow;
   const float2* bx = src + off;
@@ -234,7 +238,7 @@ __global__ __launch_bounds__(kRowNT, 4) void st_row_kernel(const float2* src, fl
     x[o] = bx[t + kRowNT * o];
     y[o] = by[t + kRowNT * o];
   }
-  if constexpr (FWD) fft<kRow, false>(x, y, lxy, twr, t);
+  if constexpr (FWD) fft<kRow, false, kRowDB>(x, y, lxy, twr, t);
   if constexpr (GVD) {
     const float2* hr = h + (size_t)i * np + (size_t)k2 * kRow;
 #pragma unroll
@@ -244,7 +248,7 @@ __global__ __launch_bounds__(kRowNT, 4) void st_row_kernel(const float2* src, fl
       y[o] = CONJ ? cmulc(y[o], hv) : cmul(y[o], hv);
     }
   }
-  if constexpr (INV) fft<kRow, true>(x, y, lxy, twr, t);
+  if constexpr (INV) fft<kRow, true, kRowDB>(x, y, lxy, twr, t);
   float2* ox = dst + off;
   float2* oy = ox + np;
 #pragma unroll
@@ -638,7 +642,7 @@ __global__ __launch_bounds__(kRowNT, 4) void st_kweight_kernel(const float2* __r
                                                               const double* __restrict__ phase, float scale,
                                                               const float2* __restrict__ twr, int nsb, int n2,
                                                               int np) {
-  __shared__ __align__(16) float4 lxy[FftShape<kRow>::LDS_C];
+  __shared__ __align__(16) float4 lxy[kRowLds];
   const int i = blockIdx.x / n2, k2 = blockIdx.x - (blockIdx.x / n2) * n2;
   const size_t off = ((size_t)blockIdx.y * nsb + i) * 2 * np + (size_t)k2 * kRow;
   const int t = threadIdx.x;
@@ -648,7 +652,7 @@ __global__ __launch_bounds__(kRowNT, 4) void st_kweight_kernel(const float2* __r
     x[o] = src[off + t + kRowNT * o];
     y[o] = src[off + np + t + kRowNT * o];
   }
-  if constexpr (FWD) fft<kRow, false>(x, y, lxy, twr, t);
+  if constexpr (FWD) fft<kRow, false, kRowDB>(x, y, lxy, twr, t);
   const size_t hoff = (size_t)i * np + (size_t)k2 * kRow;
   const double centre = phase[(size_t)i * np + kRow / 2];  // bin N'/2 sits at position N1/2
 #pragma unroll
@@ -658,7 +662,7 @@ __global__ __launch_bounds__(kRowNT, 4) void st_kweight_kernel(const float2* __r
     x[o] = GVD ? cmul(x[o], w) : cscale(x[o], w.x);
     y[o] = GVD ? cmul(y[o], w) : cscale(y[o], w.x);
   }
-  fft<kRow, true>(x, y, lxy, twr, t);
+  fft<kRow, true, kRowDB>(x, y, lxy, twr, t);
 #pragma unroll
   for (int o = 0; o < kRowRR; ++o) {
     dst[off + t + kRowNT * o] = x[o];
@@ -838,7 +842,7 @@ __global__ __launch_bounds__(kRowNT, 2) void st_gvd_adj_kernel(float2* g, const 
                                                               double* __restrict__ part,
                                                               const float2* __restrict__ twr, int nsb, int n2,
                                                               int np) {
-  __shared__ __align__(16) float4 lxy[FftShape<kRow>::LDS_C];
+  __shared__ __align__(16) float4 lxy[kRowLds];
   __shared__ double red[kRowNT / 64];
   const int i = blockIdx.x / n2, k2 = blockIdx.x - (blockIdx.x / n2) * n2;
   const size_t off = ((size_t)blockIdx.y * nsb + i) * 2 * np + (size_t)k2 * kRow;
@@ -849,7 +853,7 @@ __global__ __launch_bounds__(kRowNT, 2) void st_gvd_adj_kernel(float2* g, const 
     gx[o] = g[off + t + kRowNT * o];
     gy[o] = g[off + np + t + kRowNT * o];
   }
-  if constexpr (G_FWD) fft<kRow, false>(gx, gy, lxy, twr, t);
+  if constexpr (G_FWD) fft<kRow, false, kRowDB>(gx, gy, lxy, twr, t);
   double acc = 0.0;
   {
     float2 x[kRowRR], y[kRowRR];
@@ -858,7 +862,7 @@ __global__ __launch_bounds__(kRowNT, 2) void st_gvd_adj_kernel(float2* g, const 
       x[o] = xs[off + t + kRowNT * o];
       y[o] = xs[off + np + t + kRowNT * o];
     }
-    if constexpr (X_FWD) fft<kRow, false>(x, y, lxy, twr, t);
+    if constexpr (X_FWD) fft<kRow, false, kRowDB>(x, y, lxy, twr, t);
     const size_t hoff = (size_t)i * np + (size_t)k2 * kRow;
 #pragma unroll
     for (int o = 0; o < kRowRR; ++o) {
@@ -882,7 +886,7 @@ __global__ __launch_bounds__(kRowNT, 2) void st_gvd_adj_kernel(float2* g, const 
     part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = sum;
   }
   if constexpr (STORE) {
-    if constexpr (INV) fft<kRow, true>(gx, gy, lxy, twr, t);
+    if constexpr (INV) fft<kRow, true, kRowDB>(gx, gy, lxy, twr, t);
 #pragma unroll
     for (int o = 0; o < kRowRR; ++o) {
       g[off + t + kRowNT * o] = gx[o];

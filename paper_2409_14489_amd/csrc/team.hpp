@@ -164,7 +164,7 @@ struct NlprLds {
 };
 template <int N>
 constexpr int lds_floats() {
-  return 4 * FftShape<N>::LDS_C > NlprLds<N>::FLOATS ? 4 * FftShape<N>::LDS_C : NlprLds<N>::FLOATS;
+  return 4 * FftShape<N>::LDS_ENTRIES > NlprLds<N>::FLOATS ? 4 * FftShape<N>::LDS_ENTRIES : NlprLds<N>::FLOATS;
 }
 
 // Writes values held at positions t + NT o (o < RR; t may include an offset
