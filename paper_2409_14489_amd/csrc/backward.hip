@@ -39,7 +39,9 @@
 //
 // The reverse step needs v, theta, A and D of its forward step.  The forward
 // sweep stores the spectrum S_s at the start of every segment of `ck_every`
-// steps, and (v, theta, A, D) of every step of the last segment; the reverse
+// steps, and (A, theta, D) of every step of the last segment (the reverse step
+// makes v = IDFT(A) again, bit for bit, rather than storing and re-reading
+// it); the reverse
 // sweep recomputes each earlier segment once from its spectrum, storing them
 // per step, and then runs that segment's reverse steps on them (one level of
 // Griewank-style checkpointing; with a single segment nothing is recomputed).
@@ -78,34 +80,30 @@ __device__ __forceinline__ void load_state(const float2* st, float2 (&x)[FftShap
   }
 }
 
-// Stored record of one step: v_x, v_y (N' complex each), theta (N' floats),
-// then the spectra A_x, A_y, D_x, D_y (N' complex each): kVtFloats N' floats.
-constexpr int kVtFloats = 13;
+// Stored record of one step, kVtFloats N' floats: the spectra A_x, A_y
+// (N' complex each), theta (N' floats), the spectra D_x, D_y.
+constexpr int kVtFloats = 9;
+constexpr int kVtTheta = 4;  // offsets in N' floats
+constexpr int kVtD = 5;
 
 template <int N>
-__device__ __forceinline__ void store_vtheta(float* st, const float2 (&x)[FftShape<N>::RR],
-                                             const float2 (&y)[FftShape<N>::RR], const float (&th)[FftShape<N>::RR],
-                                             int t) {
+__device__ __forceinline__ void store_theta(float* st, const float (&th)[FftShape<N>::RR], int t) {
   constexpr int RR = FftShape<N>::RR, NT = FftShape<N>::NT;
-  float2* v = reinterpret_cast<float2*>(st);
 #pragma unroll
-  for (int o = 0; o < RR; ++o) {
-    v[t + NT * o] = x[o];
-    v[N + t + NT * o] = y[o];
-    st[4 * N + t + NT * o] = th[o];
-  }
+  for (int o = 0; o < RR; ++o) st[kVtTheta * N + t + NT * o] = th[o];
 }
 
+// A (into x, y) and theta of a stored record.
 template <int N>
-__device__ __forceinline__ void load_vtheta(const float* st, float2 (&x)[FftShape<N>::RR],
+__device__ __forceinline__ void load_atheta(const float* st, float2 (&x)[FftShape<N>::RR],
                                             float2 (&y)[FftShape<N>::RR], float (&th)[FftShape<N>::RR], int t) {
   constexpr int RR = FftShape<N>::RR, NT = FftShape<N>::NT;
-  const float2* v = reinterpret_cast<const float2*>(st);
+  const float2* a = reinterpret_cast<const float2*>(st);
 #pragma unroll
   for (int o = 0; o < RR; ++o) {
-    x[o] = v[t + NT * o];
-    y[o] = v[N + t + NT * o];
-    th[o] = st[4 * N + t + NT * o];
+    x[o] = a[t + NT * o];
+    y[o] = a[N + t + NT * o];
+    th[o] = st[kVtTheta * N + t + NT * o];
   }
 }
 
@@ -155,25 +153,19 @@ __device__ __forceinline__ void coeff_grad(const TeamCtx& c, uint64_t* xrow, uns
   __syncthreads();
 #pragma unroll
   for (int o = 0; o < RR; ++o) th[pad_r(t + NT * o)] = tb_own[o];
-  {
-    float v[RR];
-    if (nsb > 1 && me != 0) {
-      xget<RR>(xrow, t, NT, tag, c.ctl, v);
-      stage_row<N, RR, NT>(lf, v, t, hl, nc);
-    } else {
-      stage_row<N, RR, NT>(lf, p_own, t, hl, nc);
-    }
-  }
+  stage_row<N, RR, NT>(lf, p_own, t, hl, nc);  // rows in the order me, me + 1, ... (mod n_sb)
   __syncthreads();
   float tb[RR];  // block mapping t RR + q
 #pragma unroll
   for (int q = 0; q < RR; ++q) tb[q] = th[pad_r(t * RR + q)];
 
-  for (int l = 0; l < nsb; ++l) {
-    const float* cur = lf + (l & 1) * PB;
-    const bool fetch = (l + 1 < nsb) && (l + 1 != me);
+  for (int j = 0; j < nsb; ++j) {
+    const float* cur = lf + (j & 1) * PB;
+    const int l = me + j < nsb ? me + j : me + j - nsb;  // the row used now
+    const int ln = l + 1 < nsb ? l + 1 : 0;                // the next one (remote)
+    const bool more = j + 1 < nsb;
     uint64_t w[RR];
-    if (fetch) xissue<RR>(xrow + (size_t)(l + 1) * N, t, NT, w);
+    if (more) xissue<RR>(xrow + (size_t)ln * N, t, NT, w);
     // window W[i] = cur[t RR + i]; chunk ch of taps reads W[tap_pad - 8 ch - 8 + i]
     float win[RR + kTapChunk];
     int start = t * RR;
@@ -196,14 +188,10 @@ __device__ __forceinline__ void coeff_grad(const TeamCtx& c, uint64_t* xrow, uns
         load_row4<kTapChunk, RR>(cur, start + RR, win);
       }
     }
-    if (l + 1 < nsb) {
-      if (fetch) {
-        float v[RR];
-        xcomplete<RR>(xrow + (size_t)(l + 1) * N, t, NT, tag, c.ctl, w, v);
-        stage_row<N, RR, NT>(lf + ((l + 1) & 1) * PB, v, t, hl, nc);
-      } else {
-        stage_row<N, RR, NT>(lf + ((l + 1) & 1) * PB, p_own, t, hl, nc);
-      }
+    if (more) {
+      float v[RR];
+      xcomplete<RR>(xrow + (size_t)ln * N, t, NT, tag, c.ctl, w, v);
+      stage_row<N, RR, NT>(lf + ((j + 1) & 1) * PB, v, t, hl, nc);
     }
     __syncthreads();
     for (int tau = t; tau < n_taps; tau += NT) {
@@ -289,7 +277,7 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdAr
   const int tap_pad = kTapChunk * a.n_chunks;
   const int k = a.ck_every;
   const size_t spec_sz = (size_t)2 * N;  // one member's spectra, two polarisations (float2)
-  const size_t vt_sz = (size_t)kVtFloats * N;  // one member's (v, theta, K v), floats
+  const size_t vt_sz = (size_t)kVtFloats * N;  // one member's step record (A, theta, D), floats
   float2* team_spec = a.spec + (size_t)c.team * a.n_ck * nsb * spec_sz;
   float* team_vt = a.vtheta + (size_t)c.team * k * nsb * vt_sz;
   auto sp = [&](int slot) { return team_spec + ((size_t)slot * nsb + me) * spec_sz; };
@@ -315,11 +303,11 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdAr
     double rho_acc = 0.0;
 
     // Forward step s (0-based) on x / y with its intensity exchange round;
-    // stores (v, theta) at `dst` if given, and stops after theta if !tail.
+    // stores (A, theta, D) at `dst` if given, and stops after theta if !tail.
     auto forward_step = [&](int s, float* dst, bool tail) {
       t = opaque_tid();
       apply_diag<N, false>(x, y, step_gvd(a.tab, s) + (size_t)me * N, t);
-      float2* rec = dst != nullptr ? reinterpret_cast<float2*>(dst + 5 * N) : nullptr;  // A, then D
+      float2* rec = dst != nullptr ? reinterpret_cast<float2*>(dst) : nullptr;  // A
       if (dst != nullptr) {
 #pragma unroll
         for (int o = 0; o < RR; ++o) {
@@ -336,7 +324,7 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdAr
       ++np;
       if (dst != nullptr) {
         t = opaque_tid();
-        store_vtheta<N>(dst, x, y, theta, t);
+        store_theta<N>(dst, theta, t);
         // D = DFT(e v), the transform of w - v
         float2 dx[RR], dy[RR];
 #pragma unroll
@@ -348,8 +336,8 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdAr
         fft<N, false>(dx, dy, lxy, tw, t);
 #pragma unroll
         for (int o = 0; o < RR; ++o) {
-          rec[2 * N + t + NT * o] = dx[o];
-          rec[3 * N + t + NT * o] = dy[o];
+          rec[kVtD * N / 2 + t + NT * o] = dx[o];
+          rec[kVtD * N / 2 + N + t + NT * o] = dy[o];
         }
       }
       if (tail) {
@@ -395,14 +383,15 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdAr
         t = opaque_tid();
         const float2* hs = step_gvd(a.tab, s - 1) + (size_t)me * N;
         float p[RR], theta[RR], tbar[RR];
-        const float2* rec = reinterpret_cast<const float2*>(vt(s - 1 - s0) + 5 * N);  // A, D of step s
+        const float2* rec = reinterpret_cast<const float2*>(vt(s - 1 - s0));  // A, then D at kVtD N' floats
         // keep g_S for g_A = N' g_S + E and the split-ratio terms
 #pragma unroll
         for (int o = 0; o < RR; ++o) {
           gsv[t + NT * o] = gx[o];
           gsv[N + t + NT * o] = gy[o];
         }
-        load_vtheta<N>(vt(s - 1 - s0), x, y, theta, t);  // v, theta of step s
+        load_atheta<N>(vt(s - 1 - s0), x, y, theta, t);  // A, theta of step s
+        fft<N, true>(x, y, lxy, tw, t);                   // v = IDFT(A), as in the forward sweep
         intensity<N>(x, y, p);
         // republish p for the coefficient gradient of the other members
         const unsigned tag_p = rnd++;
@@ -445,7 +434,8 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdAr
         for (int o = 0; o < RR; ++o) {
           const float w = phase_rel<N>(phase_km, t, o);
           const float2 sx = gsv[t + NT * o], sy = gsv[N + t + NT * o];
-          const float im = im_conj_mul(sx, rec[2 * N + t + NT * o]) + im_conj_mul(sy, rec[3 * N + t + NT * o]) -
+          const float im = im_conj_mul(sx, rec[kVtD * N / 2 + t + NT * o]) +
+                           im_conj_mul(sy, rec[kVtD * N / 2 + N + t + NT * o]) -
                            im_conj_mul(gx[o], rec[t + NT * o]) - im_conj_mul(gy[o], rec[N + t + NT * o]);
           rho_acc -= a.L * (double)(w * im);
           gx[o] = make_float2(fmaf((float)N, sx.x, gx[o].x), fmaf((float)N, sx.y, gx[o].y));
