@@ -33,16 +33,16 @@
 //   dL/drho = -L sum_s (G_s - G_{s-1})
 // keeps the relative accuracy of the FP32 state.  The reverse step then needs
 // no extra transform: g_A = DFT(g_w + dg) = N' g_S + E.  With free dispersion
-// segments dL/dd_j is written as well: A_j for 0 < j < N_st is the DFT of the
-// stored v of step j + 1.  The block's output stage (MUX, inverse size-N DFT)
-// is adjoint to its input stage and vice versa, so both are reused.
+// segments dL/dd_j is written as well: A_j for 0 < j < N_st is the stored A
+// of step j + 1.  The block's output stage (MUX, inverse size-N DFT) is
+// adjoint to its input stage and vice versa, so both are reused.
 //
 // The reverse step needs v, theta, A and D of its forward step.  The forward
 // sweep stores the spectrum S_s at the start of every segment of `ck_every`
-// steps, and (A, theta, D) of every step of the last segment (the reverse step
-// makes v = IDFT(A) again, bit for bit, rather than storing and re-reading
-// it); the reverse
-// sweep recomputes each earlier segment once from its spectrum, storing them
+// steps, and (A, theta, D) of every step of the last segment; the reverse
+// step makes v = IDFT(A) again, bit for bit, which costs one transform and
+// keeps the record at 9 N' floats instead of 13.  The reverse sweep
+// recomputes each earlier segment once from its spectrum, storing the records
 // per step, and then runs that segment's reverse steps on them (one level of
 // Griewank-style checkpointing; with a single segment nothing is recomputed).
 // Coefficient and split-ratio partials are written per block and reduced over
