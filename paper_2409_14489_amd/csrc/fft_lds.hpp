@@ -171,11 +171,17 @@ __host__ __device__ constexpr int pad_c_size(int n) { return n + (n >> 3) + 1; }
 __device__ __forceinline__ int pad_f(int i) { return i + (i >> 4); }
 __host__ __device__ constexpr int pad_f_size(int n) { return n + (n >> 4) + 1; }
 
-template <int N>
+// Samples per thread per polarisation of the persistent kernels.
+__host__ __device__ constexpr int default_rr(int n) { return n >= 8192 ? 16 : (n >= 512 ? 8 : n / 64); }
+
+// Shape of an N-point transform over N / RR threads, RR samples each.
+template <int N, int RRX = default_rr(N)>
 struct FftShape {
   static_assert(N >= 256 && N <= 8192 && (N & (N - 1)) == 0, "N' must be a power of two in [256, 8192]");
-  static constexpr int RR = N >= 8192 ? 16 : (N >= 512 ? 8 : N / 64);  // samples per thread per polarisation
-  static constexpr int NT = N / RR;                   // threads per workgroup
+  static_assert((RRX == 4 || RRX == 8 || RRX == 16) && N / RRX <= 1024, "samples per thread");
+  static constexpr int SIZE = N;
+  static constexpr int RR = RRX;   // samples per thread per polarisation
+  static constexpr int NT = N / RR;  // threads per workgroup
   static constexpr int radix(int p) {
     int rem = N;
     for (int q = 0; q < p; ++q) rem /= (rem < RR ? rem : RR);
@@ -204,20 +210,20 @@ struct FftShape {
 
 // Twiddle registers of pass P: NB butterflies x (R - 1) factors (one dummy
 // for passes without twiddles).
-template <int N, int P>
+template <class S, int P>
 struct PassTw {
-  static constexpr int R = FftShape<N>::radix(P);
-  static constexpr int NB = FftShape<N>::RR / R;
-  static constexpr int C = (P == 0 || P >= FftShape<N>::passes() || R < 2) ? 1 : NB * (R - 1);
+  static constexpr int R = S::radix(P);
+  static constexpr int NB = S::RR / R;
+  static constexpr int C = (P == 0 || P >= S::passes() || R < 2) ? 1 : NB * (R - 1);
 };
-template <int N, int P>
-using PassTwRegs = float2[PassTw<N, P>::C];
+template <class S, int P>
+using PassTwRegs = float2[PassTw<S, P>::C];
 
 // Loads the twiddles W_{L R}^{k m} = table[k m N / (L R)], k = j mod L, of
 // pass P.  They depend only on the thread, so they are issued one pass ahead.
-template <int N, int P>
-__device__ __forceinline__ void load_pass_tw(PassTwRegs<N, P>& w, const float2* __restrict__ twt, int t) {
-  using S = FftShape<N>;
+template <class S, int P>
+__device__ __forceinline__ void load_pass_tw(PassTwRegs<S, P>& w, const float2* __restrict__ twt, int t) {
+  constexpr int N = S::SIZE;
   if constexpr (P > 0 && P < S::passes()) {
     constexpr int R = S::radix(P);
     constexpr int L = S::stride(P);
@@ -239,10 +245,10 @@ __device__ __forceinline__ void load_pass_tw(PassTwRegs<N, P>& w, const float2* 
 // Otherwise inputs are read from / outputs written to LDS.  With DB, pass p
 // writes buffer p mod 2 and reads buffer (p - 1) mod 2: every reader of the
 // buffer a pass writes has passed the barrier that ended the previous pass.
-template <int N, int P, bool INV, bool DB>
-__device__ __forceinline__ void fft_pass(float2 (&x)[FftShape<N>::RR], float2 (&y)[FftShape<N>::RR],
-                                         float4* __restrict__ lxy, const PassTwRegs<N, P>& w, int t) {
-  using S = FftShape<N>;
+template <class S, int P, bool INV, bool DB>
+__device__ __forceinline__ void fft_pass(float2 (&x)[S::RR], float2 (&y)[S::RR], float4* __restrict__ lxy,
+                                         const PassTwRegs<S, P>& w, int t) {
+  constexpr int N = S::SIZE;
   const float4* rd = DB ? lxy + ((P + 1) & 1) * S::LDS_C : lxy;
   float4* wr = DB ? lxy + (P & 1) * S::LDS_C : lxy;
   constexpr int R = S::radix(P);
@@ -296,15 +302,14 @@ __device__ __forceinline__ void fft_pass(float2 (&x)[FftShape<N>::RR], float2 (&
   if constexpr (!LAST) __syncthreads();
 }
 
-template <int N, int P, bool INV, bool DB>
-__device__ __forceinline__ void fft_passes(float2 (&x)[FftShape<N>::RR], float2 (&y)[FftShape<N>::RR],
-                                           float4* lxy, const float2* twt, const PassTwRegs<N, P>& w,
-                                           int t) {
-  if constexpr (P < FftShape<N>::passes()) {
-    PassTwRegs<N, P + 1> w_next;
-    load_pass_tw<N, P + 1>(w_next, twt, t);  // in flight during this pass
-    fft_pass<N, P, INV, DB>(x, y, lxy, w, t);
-    fft_passes<N, P + 1, INV, DB>(x, y, lxy, twt, w_next, t);
+template <class S, int P, bool INV, bool DB>
+__device__ __forceinline__ void fft_passes(float2 (&x)[S::RR], float2 (&y)[S::RR], float4* lxy, const float2* twt,
+                                           const PassTwRegs<S, P>& w, int t) {
+  if constexpr (P < S::passes()) {
+    PassTwRegs<S, P + 1> w_next;
+    load_pass_tw<S, P + 1>(w_next, twt, t);  // in flight during this pass
+    fft_pass<S, P, INV, DB>(x, y, lxy, w, t);
+    fft_passes<S, P + 1, INV, DB>(x, y, lxy, twt, w_next, t);
   }
 }
 
@@ -314,13 +319,13 @@ __device__ __forceinline__ void fft_passes(float2 (&x)[FftShape<N>::RR], float2 
 // Starts with a barrier so that earlier LDS readers are done before the first
 // pass overwrites the exchange buffer(s): lxy holds DB ? 2 LDS_C : LDS_C
 // float4 entries (FftShape::LDS_ENTRIES); a caller with room for one buffer
-// only passes DB = false.
-template <int N, bool INV, bool DB = FftShape<N>::DB>
-__device__ __forceinline__ void fft(float2 (&x)[FftShape<N>::RR], float2 (&y)[FftShape<N>::RR], float4* lxy,
-                                    const float2* twt, int t) {
-  PassTwRegs<N, 0> w0;
+// only passes DB = false.  RRX: samples per thread (N / RRX threads).
+template <int N, bool INV, bool DB = FftShape<N>::DB, int RRX = default_rr(N)>
+__device__ __forceinline__ void fft(float2 (&x)[RRX], float2 (&y)[RRX], float4* lxy, const float2* twt, int t) {
+  using S = FftShape<N, RRX>;
+  PassTwRegs<S, 0> w0;
   __syncthreads();
-  fft_passes<N, 0, INV, DB>(x, y, lxy, twt, w0, t);
+  fft_passes<S, 0, INV, DB>(x, y, lxy, twt, w0, t);
 }
 
 // ------------------------------------------------------------- one array
@@ -329,10 +334,10 @@ __device__ __forceinline__ void fft(float2 (&x)[FftShape<N>::RR], float2 (&y)[Ff
 // radices, twiddles and layout contract, with two exchange buffers of one
 // float2 per position (the space of one float4 buffer), alternated as in
 // fft_pass.
-template <int N, int P, bool INV>
-__device__ __forceinline__ void fft1_pass(float2 (&x)[FftShape<N>::RR], float2* __restrict__ lx,
-                                          const PassTwRegs<N, P>& w, int t) {
-  using S = FftShape<N>;
+template <class S, int P, bool INV>
+__device__ __forceinline__ void fft1_pass(float2 (&x)[S::RR], float2* __restrict__ lx, const PassTwRegs<S, P>& w,
+                                          int t) {
+  constexpr int N = S::SIZE;
   const float2* rd = lx + ((P + 1) & 1) * S::LDS_C;
   float2* wr = lx + (P & 1) * S::LDS_C;
   constexpr int R = S::radix(P);
@@ -374,23 +379,24 @@ __device__ __forceinline__ void fft1_pass(float2 (&x)[FftShape<N>::RR], float2* 
   if constexpr (!LAST) __syncthreads();
 }
 
-template <int N, int P, bool INV>
-__device__ __forceinline__ void fft1_passes(float2 (&x)[FftShape<N>::RR], float2* lx, const float2* twt,
-                                            const PassTwRegs<N, P>& w, int t) {
-  if constexpr (P < FftShape<N>::passes()) {
-    PassTwRegs<N, P + 1> w_next;
-    load_pass_tw<N, P + 1>(w_next, twt, t);
-    fft1_pass<N, P, INV>(x, lx, w, t);
-    fft1_passes<N, P + 1, INV>(x, lx, twt, w_next, t);
+template <class S, int P, bool INV>
+__device__ __forceinline__ void fft1_passes(float2 (&x)[S::RR], float2* lx, const float2* twt,
+                                            const PassTwRegs<S, P>& w, int t) {
+  if constexpr (P < S::passes()) {
+    PassTwRegs<S, P + 1> w_next;
+    load_pass_tw<S, P + 1>(w_next, twt, t);
+    fft1_pass<S, P, INV>(x, lx, w, t);
+    fft1_passes<S, P + 1, INV>(x, lx, twt, w_next, t);
   }
 }
 
 // Unnormalised size-N DFT of one owned register set; same conventions as fft.
 template <int N, bool INV>
 __device__ __forceinline__ void fft1(float2 (&x)[FftShape<N>::RR], float2* lx, const float2* twt, int t) {
-  PassTwRegs<N, 0> w0;
+  using S = FftShape<N>;
+  PassTwRegs<S, 0> w0;
   __syncthreads();
-  fft1_passes<N, 0, INV>(x, lx, twt, w0, t);
+  fft1_passes<S, 0, INV>(x, lx, twt, w0, t);
 }
 
 }  // namespace cbessfm

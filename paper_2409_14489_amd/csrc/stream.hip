@@ -46,13 +46,19 @@ namespace cbessfm {
 
 namespace {
 
-constexpr int kRow = kStreamRow;                  // N1
-constexpr int kRowNT = FftShape<kRow>::NT;        // 512 threads per row workgroup
-// Row transforms use one LDS exchange buffer: two workgroups of 74 KB share a
+constexpr int kRow = kStreamRow;  // N1
+// Row transforms hold 16 samples per thread (three radix-16 passes, two LDS
+// exchanges) and use one LDS exchange buffer: two workgroups of 74 KB share a
 // CU, where two buffers each would leave room for one.
+constexpr int kRowRR = 16;
+using RowShape = FftShape<kRow, kRowRR>;
+constexpr int kRowNT = RowShape::NT;  // 256 threads per row workgroup
 constexpr bool kRowDB = false;
-constexpr int kRowLds = kRowDB ? FftShape<kRow>::LDS_ENTRIES : FftShape<kRow>::LDS_C;
-constexpr int kRowRR = FftShape<kRow>::RR;        // 8 samples per thread
+constexpr int kRowLds = kRowDB ? RowShape::LDS_ENTRIES : RowShape::LDS_C;
+// The dispersion-derivative kernel holds two row states at once and keeps 8
+// samples per thread (512 threads), which fits its registers.
+constexpr int kGvdRR = 8;
+constexpr int kGvdNT = FftShape<kRow, kGvdRR>::NT;
 constexpr int kColThreads = 256;
 
 // cos(2 pi k / 32) as an FP32 leading part and an FP32 remainder (the
@@ -222,7 +228,7 @@ __global__ __launch_bounds__(kColThreads) void st_head_kernel(StreamArgs a) {
 // when CONJ, the adjoint's filter), optional inverse size-N1 DFT.  Reads src,
 // writes dst (the same array for an in-place pass).  blockIdx.x = i N2 + k2.
 template <bool FWD, bool GVD, bool INV, bool CONJ = false>
-__global__ __launch_bounds__(kRowNT, 4) void st_row_kernel(const float2* src, float2* dst,
+__global__ __launch_bounds__(kRowNT, 2) void st_row_kernel(const float2* src, float2* dst,
                                                         const float2* __restrict__ h,
                                                         const float2* __restrict__ twr, int nsb, int n2,
                                                         int np) {
@@ -238,7 +244,7 @@ __global__ __launch_bounds__(kRowNT, 4) void st_row_kernel(const float2* src, fl
     x[o] = bx[t + kRowNT * o];
     y[o] = by[t + kRowNT * o];
   }
-  if constexpr (FWD) fft<kRow, false, kRowDB>(x, y, lxy, twr, t);
+  if constexpr (FWD) fft<kRow, false, kRowDB, kRowRR>(x, y, lxy, twr, t);
   if constexpr (GVD) {
     const float2* hr = h + (size_t)i * np + (size_t)k2 * kRow;
 #pragma unroll
@@ -248,7 +254,7 @@ __global__ __launch_bounds__(kRowNT, 4) void st_row_kernel(const float2* src, fl
       y[o] = CONJ ? cmulc(y[o], hv) : cmul(y[o], hv);
     }
   }
-  if constexpr (INV) fft<kRow, true, kRowDB>(x, y, lxy, twr, t);
+  if constexpr (INV) fft<kRow, true, kRowDB, kRowRR>(x, y, lxy, twr, t);
   float2* ox = dst + off;
   float2* oy = ox + np;
 #pragma unroll
@@ -351,7 +357,9 @@ __host__ inline size_t fir_lds_bytes(int nsb, int tap_pad) {
   return sizeof(float) * (size_t)nsb * fir_row_width(tap_pad);
 }
 
-template <int NSB>
+// NCH: the number of 8-tap chunks when known at compile time (1 .. 4, up to
+// 32 taps), else 0.
+template <int NSB, int NCH>
 __global__ __launch_bounds__(256) void st_fir_kernel(const float* __restrict__ pb, float* __restrict__ th,
                                                      const float* __restrict__ cs, int np, int nc, int tap_pad) {
   constexpr int nsb = NSB;
@@ -376,10 +384,11 @@ __global__ __launch_bounds__(256) void st_fir_kernel(const float* __restrict__ p
   for (int i = 0; i < kMaxSubbands; ++i)
 #pragma unroll
     for (int q = 0; q < kFirQ; ++q) acc[i][q] = 0.0f;
-  const int n_chunks = tap_pad / kTapChunk;
+  const int n_chunks = NCH > 0 ? NCH : tap_pad / kTapChunk;
   for (int l = 0; l < nsb; ++l) {
     const float* tl = fir_lds + l * W + t * kFirQ + tap_pad - 1 - (kTapChunk - 1);
-    for (int ch = 0; ch < n_chunks; ++ch) {
+#pragma unroll
+    for (int ch = 0; ch < (NCH > 0 ? NCH : n_chunks); ++ch) {
       // taps tau = 8 ch + u use win[q + 7 - u] for output q
       float win[kFirQ + kTapChunk - 1];
 #pragma unroll
@@ -636,7 +645,7 @@ __global__ __launch_bounds__(kColThreads) void st_col_forward_kernel(const float
 // samples of the state (K v from S(st) with h the step's filter, K g' from G
 // with scale 1 / N1, the gain of the unnormalised row pair).
 template <bool FWD, bool GVD>
-__global__ __launch_bounds__(kRowNT, 4) void st_kweight_kernel(const float2* __restrict__ src,
+__global__ __launch_bounds__(kRowNT, 2) void st_kweight_kernel(const float2* __restrict__ src,
                                                               float2* __restrict__ dst,
                                                               const float2* __restrict__ h,
                                                               const double* __restrict__ phase, float scale,
@@ -652,7 +661,7 @@ __global__ __launch_bounds__(kRowNT, 4) void st_kweight_kernel(const float2* __r
     x[o] = src[off + t + kRowNT * o];
     y[o] = src[off + np + t + kRowNT * o];
   }
-  if constexpr (FWD) fft<kRow, false, kRowDB>(x, y, lxy, twr, t);
+  if constexpr (FWD) fft<kRow, false, kRowDB, kRowRR>(x, y, lxy, twr, t);
   const size_t hoff = (size_t)i * np + (size_t)k2 * kRow;
   const double centre = phase[(size_t)i * np + kRow / 2];  // bin N'/2 sits at position N1/2
 #pragma unroll
@@ -662,7 +671,7 @@ __global__ __launch_bounds__(kRowNT, 4) void st_kweight_kernel(const float2* __r
     x[o] = GVD ? cmul(x[o], w) : cscale(x[o], w.x);
     y[o] = GVD ? cmul(y[o], w) : cscale(y[o], w.x);
   }
-  fft<kRow, true, kRowDB>(x, y, lxy, twr, t);
+  fft<kRow, true, kRowDB, kRowRR>(x, y, lxy, twr, t);
 #pragma unroll
   for (int o = 0; o < kRowRR; ++o) {
     dst[off + t + kRowNT * o] = x[o];
@@ -836,40 +845,40 @@ __global__ __launch_bounds__(256) void st_cgrad_kernel(const float* __restrict__
 // Gy = F1(g) (G_FWD) or g, X = F1(xs) (X_FWD) or xs.  STORE writes
 // conj(h) Gy back to g, through the inverse row DFT when INV.
 template <bool G_FWD, bool X_FWD, bool STORE, bool INV>
-__global__ __launch_bounds__(kRowNT, 2) void st_gvd_adj_kernel(float2* g, const float2* __restrict__ xs,
+__global__ __launch_bounds__(kGvdNT, 2) void st_gvd_adj_kernel(float2* g, const float2* __restrict__ xs,
                                                               const float2* __restrict__ h,
                                                               const double* __restrict__ phase,
                                                               double* __restrict__ part,
                                                               const float2* __restrict__ twr, int nsb, int n2,
                                                               int np) {
   __shared__ __align__(16) float4 lxy[kRowLds];
-  __shared__ double red[kRowNT / 64];
+  __shared__ double red[kGvdNT / 64];
   const int i = blockIdx.x / n2, k2 = blockIdx.x - (blockIdx.x / n2) * n2;
   const size_t off = ((size_t)blockIdx.y * nsb + i) * 2 * np + (size_t)k2 * kRow;
   const int t = threadIdx.x;
-  float2 gx[kRowRR], gy[kRowRR];
+  float2 gx[kGvdRR], gy[kGvdRR];
 #pragma unroll
-  for (int o = 0; o < kRowRR; ++o) {
-    gx[o] = g[off + t + kRowNT * o];
-    gy[o] = g[off + np + t + kRowNT * o];
+  for (int o = 0; o < kGvdRR; ++o) {
+    gx[o] = g[off + t + kGvdNT * o];
+    gy[o] = g[off + np + t + kGvdNT * o];
   }
-  if constexpr (G_FWD) fft<kRow, false, kRowDB>(gx, gy, lxy, twr, t);
+  if constexpr (G_FWD) fft<kRow, false, kRowDB, kGvdRR>(gx, gy, lxy, twr, t);
   double acc = 0.0;
   {
-    float2 x[kRowRR], y[kRowRR];
+    float2 x[kGvdRR], y[kGvdRR];
 #pragma unroll
-    for (int o = 0; o < kRowRR; ++o) {
-      x[o] = xs[off + t + kRowNT * o];
-      y[o] = xs[off + np + t + kRowNT * o];
+    for (int o = 0; o < kGvdRR; ++o) {
+      x[o] = xs[off + t + kGvdNT * o];
+      y[o] = xs[off + np + t + kGvdNT * o];
     }
-    if constexpr (X_FWD) fft<kRow, false, kRowDB>(x, y, lxy, twr, t);
+    if constexpr (X_FWD) fft<kRow, false, kRowDB, kGvdRR>(x, y, lxy, twr, t);
     const size_t hoff = (size_t)i * np + (size_t)k2 * kRow;
 #pragma unroll
-    for (int o = 0; o < kRowRR; ++o) {
-      const float2 hv = h[hoff + t + kRowNT * o];
+    for (int o = 0; o < kGvdRR; ++o) {
+      const float2 hv = h[hoff + t + kGvdNT * o];
       const float2 yx = cmul(x[o], hv), yy = cmul(y[o], hv);
       const float im = fmaf(gx[o].x, yx.y, fmaf(-gx[o].y, yx.x, fmaf(gy[o].x, yy.y, -gy[o].y * yy.x)));
-      acc += phase[hoff + t + kRowNT * o] * (double)im;
+      acc += phase[hoff + t + kGvdNT * o] * (double)im;
       if constexpr (STORE) {
         gx[o] = cmulc(gx[o], hv);
         gy[o] = cmulc(gy[o], hv);
@@ -882,15 +891,15 @@ __global__ __launch_bounds__(kRowNT, 2) void st_gvd_adj_kernel(float2* g, const 
   __syncthreads();
   if (t == 0) {
     double sum = 0.0;
-    for (int wv = 0; wv < kRowNT / 64; ++wv) sum += red[wv];
+    for (int wv = 0; wv < kGvdNT / 64; ++wv) sum += red[wv];
     part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = sum;
   }
   if constexpr (STORE) {
-    if constexpr (INV) fft<kRow, true, kRowDB>(gx, gy, lxy, twr, t);
+    if constexpr (INV) fft<kRow, true, kRowDB, kGvdRR>(gx, gy, lxy, twr, t);
 #pragma unroll
-    for (int o = 0; o < kRowRR; ++o) {
-      g[off + t + kRowNT * o] = gx[o];
-      g[off + np + t + kRowNT * o] = gy[o];
+    for (int o = 0; o < kGvdRR; ++o) {
+      g[off + t + kGvdNT * o] = gx[o];
+      g[off + np + t + kGvdNT * o] = gy[o];
     }
   }
 }
@@ -970,7 +979,13 @@ bool ok_launch() { return hipGetLastError() == hipSuccess; }
 template <int NSB>
 void fir_t(dim3 grid, size_t lds, hipStream_t s, const float* pb, float* th, const float* cs, int np, int nc,
            int tap_pad) {
-  st_fir_kernel<NSB><<<grid, 256, lds, s>>>(pb, th, cs, np, nc, tap_pad);
+  switch (tap_pad / kTapChunk) {  // compile-time chunk counts up to 32 taps
+    case 1: st_fir_kernel<NSB, 1><<<grid, 256, lds, s>>>(pb, th, cs, np, nc, tap_pad); break;
+    case 2: st_fir_kernel<NSB, 2><<<grid, 256, lds, s>>>(pb, th, cs, np, nc, tap_pad); break;
+    case 3: st_fir_kernel<NSB, 3><<<grid, 256, lds, s>>>(pb, th, cs, np, nc, tap_pad); break;
+    case 4: st_fir_kernel<NSB, 4><<<grid, 256, lds, s>>>(pb, th, cs, np, nc, tap_pad); break;
+    default: st_fir_kernel<NSB, 0><<<grid, 256, lds, s>>>(pb, th, cs, np, nc, tap_pad);
+  }
 }
 bool launch_fir(int nsb, dim3 grid, hipStream_t s, const float* pb, float* th, const float* cs, int np, int nc,
                 int tap_pad) {
@@ -1210,7 +1225,7 @@ template <bool G_FWD, bool X_FWD, bool STORE, bool INV>
 bool gvd_adj(const StreamBwdCall& c, const StreamArgs& a, const float2* xs, const float2* h, int seg) {
   const dim3 grid(a.n_sb * a.n2, a.nb);
   st_gvd_adj_kernel<G_FWD, X_FWD, STORE, INV>
-      <<<grid, kRowNT, 0, c.s>>>(c.G(), xs, h, c.p->d_phase, c.rpart(), a.twr, a.n_sb, a.n2, a.np);
+      <<<grid, kGvdNT, 0, c.s>>>(c.G(), xs, h, c.p->d_phase, c.rpart(), a.twr, a.n_sb, a.n2, a.np);
   bool ok = ok_launch();
   st_acc_sum_kernel<<<1, 256, 0, c.s>>>(c.rpart(), (int)(grid.x * grid.y), c.acc_t() + seg);
   return ok && ok_launch();
