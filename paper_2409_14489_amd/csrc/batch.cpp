@@ -6,7 +6,10 @@
 // distinct N' up to 8192; instances whose blocks exceed one CU (N' = 2^14 ..
 // 2^17, streamed block state) run on the streaming kernels after those
 // launches, concurrently on a few side streams forked from and joined back
-// to the caller's stream (so the whole run stays graph-capturable).  Its workgroups form static teams; a team has the width
+// to the caller's stream (so the whole run stays graph-capturable); those
+// that fit one wave are grouped into classes (N', n_sb, taps) whose steps
+// run as one launch per stage over all their blocks.  The persistent
+// launches' workgroups form static teams; a team has the width
 // (n_sb) of the instances it runs and keeps that width for the whole launch,
 // so the exchange protocol of the single-plan kernel carries over unchanged:
 // a team owns its exchange slots and round counter and runs its items one
@@ -16,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -313,10 +317,26 @@ struct cbessfm_batch {
   // instances whose plans stream their block state (N' >= 2^14): run by the
   // streaming kernels after the persistent launches
   std::vector<cbessfm_instance> streamed;
-  // their side streams (default priority) and fork / join events: the
-  // streamed instances run concurrently, instances of one plan on one stream
+  // Streamed instances whose blocks fit one wave of their own plan (and whose
+  // plan no other instance uses) are grouped into classes of equal N', n_sb
+  // and taps: each step of a class is one launch per stage over the blocks of
+  // all its instances still stepping (members by step count, descending, so
+  // those blocks are a prefix of the block table).  The other streamed
+  // instances run one by one.
+  struct StreamClass {
+    int log_np = 0, n_sb = 0, n_taps = 0, tap_pad = 0, max_steps = 0;
+    std::vector<int> members;     // indices into streamed
+    std::vector<int> active;      // [max_steps] blocks taking part in step s
+    cbessfm::StreamBlk* d_blks = nullptr;
+  };
+  std::vector<StreamClass> classes;
+  // units run on the side streams: a class (k < classes.size()) or the lone
+  // streamed instance k - classes.size()
+  std::vector<int> lone;     // indices into streamed
+  std::vector<int> unit_side;
+  // side streams (default priority) and fork / join events: the units run
+  // concurrently, instances of one plan on one stream
   std::vector<hipStream_t> side;
-  std::vector<int> side_of;  // per streamed instance
   hipEvent_t fork = nullptr;
   std::vector<hipEvent_t> join;
   cbessfm_batch_info info{};
@@ -635,33 +655,94 @@ int cbessfm_batch_create(cbessfm_batch_t** out, const cbessfm_instance* inst, in
     makespan += s.makespan;
     bound += s.lower_bound;
   }
-  // ---- side streams of the streamed instances: longest first onto the least
-  // loaded stream, instances sharing a plan on the same stream
+  // ---- streamed instances: classes, lone instances, side streams (units
+  // longest first onto the least loaded stream, lone instances sharing a plan
+  // on the same stream)
   if (!b->streamed.empty()) {
-    constexpr int kSideStreams = 4;
-    const int n_side = std::min<int>(kSideStreams, (int)b->streamed.size());
-    std::vector<double> cost(b->streamed.size()), load(n_side, 0.0);
-    std::vector<int> order(b->streamed.size());
-    for (size_t k = 0; k < b->streamed.size(); ++k) {
+    const size_t ns = b->streamed.size();
+    std::vector<double> cost(ns);
+    std::map<const cbessfm_plan_t*, int> uses;
+    for (size_t k = 0; k < ns; ++k) {
       const cbessfm_instance& a = b->streamed[k];
       const cbessfm_plan_t* p = a.plan;
       cost[k] = (double)a.batch * ((a.T + p->hop - 1) / p->hop) * stream_block_cost(p->log_np, p->sb.n_sb, p->steps);
-      order[k] = (int)k;
+      ++uses[p];
     }
-    std::sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
-    b->side_of.assign(b->streamed.size(), 0);
+    std::map<std::array<int, 4>, int> class_of;
+    for (size_t k = 0; k < ns; ++k) {
+      const cbessfm_instance& a = b->streamed[k];
+      const cbessfm_plan_t* p = a.plan;
+      if (uses[p] != 1 || !cbessfm::stream_single_wave(p, a.T, a.batch)) {
+        b->lone.push_back((int)k);
+        continue;
+      }
+      const std::array<int, 4> key{p->log_np, p->sb.n_sb, p->n_taps, p->tap_pad};
+      auto it = class_of.find(key);
+      if (it == class_of.end()) {
+        it = class_of.emplace(key, (int)b->classes.size()).first;
+        cbessfm_batch::StreamClass c;
+        c.log_np = key[0];
+        c.n_sb = key[1];
+        c.n_taps = key[2];
+        c.tap_pad = key[3];
+        b->classes.push_back(c);
+      }
+      b->classes[it->second].members.push_back((int)k);
+    }
+    std::vector<double> unit_cost;
+    for (auto& c : b->classes) {
+      std::stable_sort(c.members.begin(), c.members.end(), [&](int x, int y) {
+        return b->streamed[x].plan->steps > b->streamed[y].plan->steps;
+      });
+      c.max_steps = b->streamed[c.members.front()].plan->steps;
+      std::vector<cbessfm::StreamBlk> blks;
+      std::vector<int> nb_of;
+      double uc = 0.0;
+      for (int k : c.members) {
+        const cbessfm_instance& a = b->streamed[k];
+        const long long nb = (long long)a.batch * ((a.T + a.plan->hop - 1) / a.plan->hop);
+        const size_t at = blks.size();
+        blks.resize(at + (size_t)nb);
+        cbessfm::stream_blocks(a.plan, a.T, a.batch, blks.data() + at);
+        nb_of.push_back((int)nb);
+        uc += cost[k];
+      }
+      c.active.assign(c.max_steps, 0);
+      for (size_t j = 0; j < c.members.size(); ++j)
+        for (int st = 0; st < b->streamed[c.members[j]].plan->steps; ++st) c.active[st] += nb_of[j];
+      c.d_blks = static_cast<cbessfm::StreamBlk*>(alloc(blks.size() * sizeof(cbessfm::StreamBlk)));
+      if (ok && hipMemcpy(c.d_blks, blks.data(), blks.size() * sizeof(cbessfm::StreamBlk), hipMemcpyHostToDevice) !=
+                    hipSuccess)
+        ok = false;
+      unit_cost.push_back(uc);
+    }
+    for (int k : b->lone) unit_cost.push_back(cost[k]);
+    if (!ok) {
+      cbessfm_batch_destroy(b);
+      return CBESSFM_EHIP;
+    }
+    constexpr int kSideStreams = 4;
+    const int n_units = (int)unit_cost.size();
+    const int n_side = std::min<int>(kSideStreams, n_units);
+    std::vector<double> load(n_side, 0.0);
+    std::vector<int> order(n_units);
+    for (int u = 0; u < n_units; ++u) order[u] = u;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return unit_cost[x] > unit_cost[y]; });
+    b->unit_side.assign(n_units, 0);
     std::map<const cbessfm_plan_t*, int> plan_side;
-    for (int k : order) {
-      auto it = plan_side.find(b->streamed[k].plan);
+    const int n_cls = (int)b->classes.size();
+    for (int u : order) {
+      const cbessfm_plan_t* lp = u >= n_cls ? b->streamed[b->lone[u - n_cls]].plan : nullptr;
+      auto it = lp ? plan_side.find(lp) : plan_side.end();
       int sd;
       if (it != plan_side.end()) {
         sd = it->second;
       } else {
         sd = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        plan_side[b->streamed[k].plan] = sd;
+        if (lp) plan_side[lp] = sd;
       }
-      b->side_of[k] = sd;
-      load[sd] += cost[k];
+      b->unit_side[u] = sd;
+      load[sd] += unit_cost[u];
     }
     bool sok = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
     for (int k = 0; k < n_side && sok; ++k) {
@@ -705,9 +786,25 @@ int cbessfm_batch_run(cbessfm_batch_t* b, void* stream) {
   for (hipStream_t st : b->side)
     if (hipStreamWaitEvent(st, b->fork, 0) != hipSuccess) return CBESSFM_EHIP;
   int rc = CBESSFM_OK;
-  for (size_t k = 0; k < b->streamed.size() && !rc; ++k) {
-    const cbessfm_instance& a = b->streamed[k];
-    rc = cbessfm::launch_stream_forward(a.plan, a.field_in, a.field_out, a.T, a.batch, b->side[b->side_of[k]]);
+  const int n_cls = (int)b->classes.size();
+  for (int u = 0; u < (int)b->unit_side.size() && !rc; ++u) {
+    hipStream_t st = b->side[b->unit_side[u]];
+    if (u >= n_cls) {
+      const cbessfm_instance& a = b->streamed[b->lone[u - n_cls]];
+      rc = cbessfm::launch_stream_forward(a.plan, a.field_in, a.field_out, a.T, a.batch, st);
+      continue;
+    }
+    const auto& c = b->classes[u];
+    for (size_t j = 0; j < c.members.size() && !rc; ++j) {
+      const cbessfm_instance& a = b->streamed[c.members[j]];
+      rc = cbessfm::stream_input(a.plan, a.field_in, a.field_out, a.T, a.batch, st);
+    }
+    for (int step = 0; step < c.max_steps && !rc; ++step)
+      rc = cbessfm::stream_class_step(c.log_np, c.n_sb, c.n_taps, c.tap_pad, step, c.d_blks, c.active[step], st);
+    for (size_t j = 0; j < c.members.size() && !rc; ++j) {
+      const cbessfm_instance& a = b->streamed[c.members[j]];
+      rc = cbessfm::stream_output(a.plan, a.field_in, a.field_out, a.T, a.batch, st);
+    }
   }
   // join every side stream even after a failed launch
   for (size_t k = 0; k < b->side.size(); ++k)

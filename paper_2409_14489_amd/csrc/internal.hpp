@@ -115,6 +115,22 @@ struct StreamArgs {
   const float2* twr;   // [N1] exp(-j 2 pi n / N1)
 };
 
+// One block of one streamed batch instance, for the step kernels that take
+// every such block of a class of instances (same N', n_sb and taps) in one
+// launch: the block's state, intensity and phase arrays and its plan's
+// tables.  A launch over a table of these takes blockIdx.y as the entry.
+struct StreamBlk {
+  float2* st;             // [n_sb][2][N'] block state
+  float* pb;              // [n_sb][N'] intensities
+  float* th;              // [n_sb][N'] phases
+  const float2* h_first;  // dispersion filter of step 0, [n_sb][N'] (permuted order)
+  const float2* h_mid;    // of step s >= 1: h_mid + (s - 1) h_stride
+  long long h_stride;
+  const float* cpad;      // [steps][n_sb][n_sb][tap_pad] zero-padded coefficients
+  const float2* tw2;      // column twiddles
+  const float2* twr;      // row twiddles
+};
+
 // Workspace layout of one streaming adjoint call (stream.hip): byte offsets
 // of its arrays; k steps per checkpoint segment, n_ck segments, waves of nb
 // blocks, `state` complex words per block state.
@@ -231,6 +247,15 @@ int launch_batch(int log_np, const BatchArgs& a, int grid, hipStream_t s);
 void fill_inst(const cbessfm_plan_t* p, const void* in, void* out, long long T, int batch, Inst& d);
 // stream.hip
 int launch_stream_forward(cbessfm_plan_t* p, const void* in, void* out, long long T, int batch, hipStream_t s);
+// The three parts of a streaming forward whose blocks fit one wave (batch
+// instances): block input, one step over a table of blocks (any number of
+// instances of one class), block output.
+int stream_single_wave(const cbessfm_plan_t* p, long long T, int batch);
+int stream_input(cbessfm_plan_t* p, const void* in, void* out, long long T, int batch, hipStream_t s);
+int stream_output(cbessfm_plan_t* p, const void* in, void* out, long long T, int batch, hipStream_t s);
+void stream_blocks(const cbessfm_plan_t* p, long long T, int batch, StreamBlk* out);
+int stream_class_step(int log_np, int n_sb, int n_taps, int tap_pad, int step, const StreamBlk* d_blks, int nb,
+                      hipStream_t s);
 StreamBwdLayout stream_bwd_layout(const cbessfm_plan_t* p, long long T, int batch, int ck_every, bool gin);
 int launch_stream_backward(cbessfm_plan_t* p, const void* field_in, const void* grad_out, void* grad_in,
                            float* grad_c, float* grad_rho, double* grad_gvd, long long T, int batch, int ck_every,

@@ -226,15 +226,26 @@ __global__ __launch_bounds__(kColThreads) void st_head_kernel(StreamArgs a) {
 // Row pass of row k2 of array (block w, subband i): optional forward size-N1
 // DFT, optional pointwise filter h (permuted order, subband i at i N'; conj(h)
 // when CONJ, the adjoint's filter), optional inverse size-N1 DFT.  Reads src,
-// writes dst (the same array for an in-place pass).  blockIdx.x = i N2 + k2.
+// writes dst (the same array for an in-place pass).  blockIdx.x = i N2 + k2,
+// blockIdx.y = block of the wave, or, with a block table `blk`, the entry of
+// that table (in place on its state, with the filter of step `step`).
 template <bool FWD, bool GVD, bool INV, bool CONJ = false>
 __global__ __launch_bounds__(kRowNT, 2) void st_row_kernel(const float2* src, float2* dst,
                                                         const float2* __restrict__ h,
                                                         const float2* __restrict__ twr, int nsb, int n2,
-                                                        int np) {
+                                                        int np, const StreamBlk* __restrict__ blk, int step) {
   __shared__ __align__(16) float4 lxy[kRowLds];
   const int i = blockIdx.x / n2, k2 = blockIdx.x - (blockIdx.x / n2) * n2;
-  const size_t off = ((size_t)blockIdx.y * nsb + i) * 2 * np + (size_t)k2 * kRow;
+  size_t wb = blockIdx.y;
+  if (blk != nullptr) {
+    const StreamBlk& e = blk[blockIdx.y];
+    src = e.st;
+    dst = e.st;
+    h = step == 0 ? e.h_first : e.h_mid + (size_t)(step - 1) * e.h_stride;
+    twr = e.twr;
+    wb = 0;
+  }
+  const size_t off = (wb * nsb + i) * 2 * np + (size_t)k2 * kRow;
   const float2* bx = src + off;
   const float2* by = bx + np;
   const int t = threadIdx.x;
@@ -316,12 +327,20 @@ __global__ __launch_bounds__(256) void st_mix_kernel(float2* __restrict__ st, co
 template <int N2>
 __global__ __launch_bounds__(kColThreads) void st_intensity_kernel(const float2* __restrict__ st,
                                                                    float* __restrict__ pb,
-                                                                   const float2* __restrict__ tw2, int nsb) {
+                                                                   const float2* __restrict__ tw2, int nsb,
+                                                                   const StreamBlk* __restrict__ blk) {
   constexpr int NP = kRow * N2;
   constexpr int GROUPS = kRow / kColThreads;
   const int i = blockIdx.x / GROUPS;
   const int n1 = (blockIdx.x - i * GROUPS) * kColThreads + threadIdx.x;
-  const size_t arr = (size_t)blockIdx.y * nsb + i;
+  size_t arr = (size_t)blockIdx.y * nsb + i;
+  if (blk != nullptr) {  // blockIdx.y = entry of the block table
+    const StreamBlk& e = blk[blockIdx.y];
+    st = e.st;
+    pb = e.pb;
+    tw2 = e.tw2;
+    arr = i;
+  }
   float p[N2];
 #pragma unroll
   for (int k = 0; k < N2; ++k) p[k] = 0.0f;
@@ -361,12 +380,20 @@ __host__ inline size_t fir_lds_bytes(int nsb, int tap_pad) {
 // 32 taps), else 0.
 template <int NSB, int NCH>
 __global__ __launch_bounds__(256) void st_fir_kernel(const float* __restrict__ pb, float* __restrict__ th,
-                                                     const float* __restrict__ cs, int np, int nc, int tap_pad) {
+                                                     const float* __restrict__ cs, int np, int nc, int tap_pad,
+                                                     const StreamBlk* __restrict__ blk, int step) {
   constexpr int nsb = NSB;
   extern __shared__ float fir_lds[];
   const int W = fir_row_width(tap_pad);
   const int n0 = blockIdx.x * kFirOut;
-  const size_t arr0 = (size_t)blockIdx.y * nsb;
+  size_t arr0 = (size_t)blockIdx.y * nsb;
+  if (blk != nullptr) {  // blockIdx.y = entry of the block table; coefficients of step `step`
+    const StreamBlk& e = blk[blockIdx.y];
+    pb = e.pb;
+    th = e.th;
+    cs = e.cpad + (size_t)step * nsb * nsb * tap_pad;
+    arr0 = 0;
+  }
   const int hl = tap_pad - 1 - nc;
   const int span = kFirOut + tap_pad - 1;
   for (int l = 0; l < nsb; ++l) {
@@ -419,12 +446,21 @@ __global__ __launch_bounds__(256) void st_fir_kernel(const float* __restrict__ p
 template <int N2>
 __global__ __launch_bounds__(kColThreads) void st_rotate_kernel(const float2* src, float2* dst,
                                                                 const float* __restrict__ th,
-                                                                const float2* __restrict__ tw2, int nsb) {
+                                                                const float2* __restrict__ tw2, int nsb,
+                                                                const StreamBlk* __restrict__ blk) {
   constexpr int NP = kRow * N2;
   constexpr int GROUPS = kRow / kColThreads;
   const int i = blockIdx.x / GROUPS;
   const int n1 = (blockIdx.x - i * GROUPS) * kColThreads + threadIdx.x;
-  const size_t arr = (size_t)blockIdx.y * nsb + i;
+  size_t arr = (size_t)blockIdx.y * nsb + i;
+  if (blk != nullptr) {  // blockIdx.y = entry of the block table, in place
+    const StreamBlk& e = blk[blockIdx.y];
+    src = e.st;
+    dst = e.st;
+    th = e.th;
+    tw2 = e.tw2;
+    arr = i;
+  }
   float theta[N2];
   const float* tsrc = th + arr * NP + n1;
 #pragma unroll
@@ -978,27 +1014,27 @@ bool ok_launch() { return hipGetLastError() == hipSuccess; }
 // so their per-subband loops have no branches and their loads batch.
 template <int NSB>
 void fir_t(dim3 grid, size_t lds, hipStream_t s, const float* pb, float* th, const float* cs, int np, int nc,
-           int tap_pad) {
+           int tap_pad, const StreamBlk* blk, int step) {
   switch (tap_pad / kTapChunk) {  // compile-time chunk counts up to 32 taps
-    case 1: st_fir_kernel<NSB, 1><<<grid, 256, lds, s>>>(pb, th, cs, np, nc, tap_pad); break;
-    case 2: st_fir_kernel<NSB, 2><<<grid, 256, lds, s>>>(pb, th, cs, np, nc, tap_pad); break;
-    case 3: st_fir_kernel<NSB, 3><<<grid, 256, lds, s>>>(pb, th, cs, np, nc, tap_pad); break;
-    case 4: st_fir_kernel<NSB, 4><<<grid, 256, lds, s>>>(pb, th, cs, np, nc, tap_pad); break;
-    default: st_fir_kernel<NSB, 0><<<grid, 256, lds, s>>>(pb, th, cs, np, nc, tap_pad);
+    case 1: st_fir_kernel<NSB, 1><<<grid, 256, lds, s>>>(pb, th, cs, np, nc, tap_pad, blk, step); break;
+    case 2: st_fir_kernel<NSB, 2><<<grid, 256, lds, s>>>(pb, th, cs, np, nc, tap_pad, blk, step); break;
+    case 3: st_fir_kernel<NSB, 3><<<grid, 256, lds, s>>>(pb, th, cs, np, nc, tap_pad, blk, step); break;
+    case 4: st_fir_kernel<NSB, 4><<<grid, 256, lds, s>>>(pb, th, cs, np, nc, tap_pad, blk, step); break;
+    default: st_fir_kernel<NSB, 0><<<grid, 256, lds, s>>>(pb, th, cs, np, nc, tap_pad, blk, step);
   }
 }
 bool launch_fir(int nsb, dim3 grid, hipStream_t s, const float* pb, float* th, const float* cs, int np, int nc,
-                int tap_pad) {
+                int tap_pad, const StreamBlk* blk = nullptr, int step = 0) {
   const size_t lds = fir_lds_bytes(nsb, tap_pad);
   switch (nsb) {
-    case 1: fir_t<1>(grid, lds, s, pb, th, cs, np, nc, tap_pad); break;
-    case 2: fir_t<2>(grid, lds, s, pb, th, cs, np, nc, tap_pad); break;
-    case 3: fir_t<3>(grid, lds, s, pb, th, cs, np, nc, tap_pad); break;
-    case 4: fir_t<4>(grid, lds, s, pb, th, cs, np, nc, tap_pad); break;
-    case 5: fir_t<5>(grid, lds, s, pb, th, cs, np, nc, tap_pad); break;
-    case 6: fir_t<6>(grid, lds, s, pb, th, cs, np, nc, tap_pad); break;
-    case 7: fir_t<7>(grid, lds, s, pb, th, cs, np, nc, tap_pad); break;
-    case 8: fir_t<8>(grid, lds, s, pb, th, cs, np, nc, tap_pad); break;
+    case 1: fir_t<1>(grid, lds, s, pb, th, cs, np, nc, tap_pad, blk, step); break;
+    case 2: fir_t<2>(grid, lds, s, pb, th, cs, np, nc, tap_pad, blk, step); break;
+    case 3: fir_t<3>(grid, lds, s, pb, th, cs, np, nc, tap_pad, blk, step); break;
+    case 4: fir_t<4>(grid, lds, s, pb, th, cs, np, nc, tap_pad, blk, step); break;
+    case 5: fir_t<5>(grid, lds, s, pb, th, cs, np, nc, tap_pad, blk, step); break;
+    case 6: fir_t<6>(grid, lds, s, pb, th, cs, np, nc, tap_pad, blk, step); break;
+    case 7: fir_t<7>(grid, lds, s, pb, th, cs, np, nc, tap_pad, blk, step); break;
+    case 8: fir_t<8>(grid, lds, s, pb, th, cs, np, nc, tap_pad, blk, step); break;
     default: return false;
   }
   return ok_launch();
@@ -1028,7 +1064,7 @@ bool launch_cgrad(int nsb, dim3 grid, hipStream_t s, const float* tbar, const fl
 template <bool FWD, bool GVD, bool INV, bool CONJ = false>
 bool row(const StreamArgs& a, const float2* src, float2* dst, const float2* h, hipStream_t s) {
   st_row_kernel<FWD, GVD, INV, CONJ>
-      <<<dim3(a.n_sb * a.n2, a.nb), kRowNT, 0, s>>>(src, dst, h, a.twr, a.n_sb, a.n2, a.np);
+      <<<dim3(a.n_sb * a.n2, a.nb), kRowNT, 0, s>>>(src, dst, h, a.twr, a.n_sb, a.n2, a.np, nullptr, 0);
   return ok_launch();
 }
 
@@ -1064,22 +1100,21 @@ bool wave_step(const StreamArgs& a, const Tables& tb, const float* cpad, int st,
   const dim3 sb_grid(nsb * (kRow / kColThreads), a.nb);
   const float2* h = step_filter(tb, st);
   bool ok = (st == 0 && nsb > 1) ? row<false, true, true>(a, src, work, h, s) : row<true, true, true>(a, src, work, h, s);
-  st_intensity_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(work, a.pb, a.tw2, nsb);
+  st_intensity_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(work, a.pb, a.tw2, nsb, nullptr);
   ok = ok && ok_launch();
   ok = ok && launch_fir(nsb, dim3(a.np / kFirOut, a.nb), s, a.pb, theta,
                         cpad + (size_t)st * nsb * nsb * tap_pad, a.np, n_taps / 2, tap_pad);
   ok = ok && ok_launch();
-  st_rotate_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(work, dst, theta, a.tw2, nsb);
+  st_rotate_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(work, dst, theta, a.tw2, nsb, nullptr);
   return ok && ok_launch();
 }
 
+// Block output: final dispersion segment, MUX, inverse column pass, kept
+// samples.
 template <int N2>
-int run_wave(const StreamArgs& a, const Tables& tb, const float* cpad, int steps, int n_taps, int tap_pad,
-             hipStream_t s) {
+bool wave_output(const StreamArgs& a, const Tables& tb, hipStream_t s) {
   const int nsb = a.n_sb;
-  bool ok = wave_input<N2>(a, tb, s);
-  for (int st = 0; st < steps && ok; ++st)
-    ok = wave_step<N2>(a, tb, cpad, st, n_taps, tap_pad, a.st, a.st, a.th, a.st, s);
+  bool ok = true;
   if (nsb > 1) {
     StreamWsb wsb;
     for (int k = 0; k < kMaxSubbands; ++k) wsb.w[k] = tb.wsb[k];
@@ -1091,8 +1126,38 @@ int run_wave(const StreamArgs& a, const Tables& tb, const float* cpad, int steps
     ok = ok && row<true, true, true>(a, a.st, a.st, tb.h_last, s);
   }
   st_tail_kernel<N2><<<dim3((nsb * kRow + kColThreads - 1) / kColThreads, a.nb), kColThreads, 0, s>>>(a);
-  ok = ok && ok_launch();
+  return ok && ok_launch();
+}
+
+template <int N2>
+int run_wave(const StreamArgs& a, const Tables& tb, const float* cpad, int steps, int n_taps, int tap_pad,
+             hipStream_t s) {
+  bool ok = wave_input<N2>(a, tb, s);
+  for (int st = 0; st < steps && ok; ++st)
+    ok = wave_step<N2>(a, tb, cpad, st, n_taps, tap_pad, a.st, a.st, a.th, a.st, s);
+  ok = ok && wave_output<N2>(a, tb, s);
   return ok ? CBESSFM_OK : CBESSFM_EHIP;
+}
+
+// Step `step` of every block in the table blks[0 .. nb) (instances of one
+// class: same N', n_sb and taps; each entry names its own state, phase and
+// intensity arrays and its plan's tables).  The same kernels as wave_step.
+template <int N2>
+bool class_step(int nsb, int n_taps, int tap_pad, int step, const StreamBlk* blks, int nb, hipStream_t s) {
+  constexpr int NP = kRow * N2;
+  const dim3 row_grid(nsb * N2, nb), sb_grid(nsb * (kRow / kColThreads), nb);
+  if (step == 0 && nsb > 1)
+    st_row_kernel<false, true, true>
+        <<<row_grid, kRowNT, 0, s>>>(nullptr, nullptr, nullptr, nullptr, nsb, N2, NP, blks, step);
+  else
+    st_row_kernel<true, true, true><<<row_grid, kRowNT, 0, s>>>(nullptr, nullptr, nullptr, nullptr, nsb, N2, NP, blks, step);
+  bool ok = ok_launch();
+  st_intensity_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(nullptr, nullptr, nullptr, nsb, blks);
+  ok = ok && ok_launch();
+  ok = ok && launch_fir(nsb, dim3(NP / kFirOut, nb), s, nullptr, nullptr, nullptr, NP, n_taps / 2, tap_pad, blks,
+                        step);
+  st_rotate_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(nullptr, nullptr, nullptr, nullptr, nsb, blks);
+  return ok && ok_launch();
 }
 
 void fill_stream_args(const cbessfm_plan_t* p, const void* in, void* out, long long T, StreamArgs& a) {
@@ -1114,6 +1179,83 @@ void fill_stream_args(const cbessfm_plan_t* p, const void* in, void* out, long l
 }
 
 }  // namespace
+
+int stream_single_wave(const cbessfm_plan_t* p, long long T, int batch) {
+  const long long items = (long long)batch * ((T + p->hop - 1) / p->hop);
+  return p->stream && p->nlpr == CBESSFM_NLPR_AVERAGED && items <= p->st_blocks;
+}
+
+int stream_input(cbessfm_plan_t* p, const void* in, void* out, long long T, int batch, hipStream_t s) {
+  if (!stream_single_wave(p, T, batch)) return CBESSFM_EUNSUPPORTED;
+  Tables tb;
+  fill_tables(p, tb);
+  StreamArgs a;
+  fill_stream_args(p, in, out, T, a);
+  a.item0 = 0;
+  a.nb = batch * a.nblk;
+  bool ok;
+  switch (p->log_np) {
+    case 14: ok = wave_input<4>(a, tb, s); break;
+    case 15: ok = wave_input<8>(a, tb, s); break;
+    case 16: ok = wave_input<16>(a, tb, s); break;
+    case 17: ok = wave_input<32>(a, tb, s); break;
+    default: return CBESSFM_EUNSUPPORTED;
+  }
+  return ok ? CBESSFM_OK : CBESSFM_EHIP;
+}
+
+int stream_output(cbessfm_plan_t* p, const void* in, void* out, long long T, int batch, hipStream_t s) {
+  if (!stream_single_wave(p, T, batch)) return CBESSFM_EUNSUPPORTED;
+  Tables tb;
+  fill_tables(p, tb);
+  StreamArgs a;
+  fill_stream_args(p, in, out, T, a);
+  a.item0 = 0;
+  a.nb = batch * a.nblk;
+  bool ok;
+  switch (p->log_np) {
+    case 14: ok = wave_output<4>(a, tb, s); break;
+    case 15: ok = wave_output<8>(a, tb, s); break;
+    case 16: ok = wave_output<16>(a, tb, s); break;
+    case 17: ok = wave_output<32>(a, tb, s); break;
+    default: return CBESSFM_EUNSUPPORTED;
+  }
+  return ok ? CBESSFM_OK : CBESSFM_EHIP;
+}
+
+void stream_blocks(const cbessfm_plan_t* p, long long T, int batch, StreamBlk* out) {
+  Tables tb;
+  fill_tables(p, tb);
+  const int nsb = p->sb.n_sb;
+  const size_t np = (size_t)p->Np;
+  const long long nb = (long long)batch * ((T + p->hop - 1) / p->hop);
+  for (long long b = 0; b < nb; ++b) {
+    StreamBlk& e = out[b];
+    e.st = p->d_st + (size_t)b * nsb * 2 * np;
+    e.pb = p->d_pb + (size_t)b * nsb * np;
+    e.th = p->d_th + (size_t)b * nsb * np;
+    e.h_first = tb.h_first;
+    e.h_mid = tb.h_mid;
+    e.h_stride = tb.h_stride;
+    e.cpad = p->d_cpad;
+    e.tw2 = p->d_tw;
+    e.twr = p->d_tw + p->Np;
+  }
+}
+
+int stream_class_step(int log_np, int n_sb, int n_taps, int tap_pad, int step, const StreamBlk* d_blks, int nb,
+                      hipStream_t s) {
+  if (nb < 1) return CBESSFM_OK;
+  bool ok;
+  switch (log_np) {
+    case 14: ok = class_step<4>(n_sb, n_taps, tap_pad, step, d_blks, nb, s); break;
+    case 15: ok = class_step<8>(n_sb, n_taps, tap_pad, step, d_blks, nb, s); break;
+    case 16: ok = class_step<16>(n_sb, n_taps, tap_pad, step, d_blks, nb, s); break;
+    case 17: ok = class_step<32>(n_sb, n_taps, tap_pad, step, d_blks, nb, s); break;
+    default: return CBESSFM_EUNSUPPORTED;
+  }
+  return ok ? CBESSFM_OK : CBESSFM_EHIP;
+}
 
 int launch_stream_forward(cbessfm_plan_t* p, const void* in, void* out, long long T, int batch, hipStream_t s) {
   if (p->nlpr != CBESSFM_NLPR_AVERAGED) return CBESSFM_EUNSUPPORTED;

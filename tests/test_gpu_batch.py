@@ -275,3 +275,61 @@ def test_batch_with_streamed_instances_matches_oracle_block_by_block():
     b.close()
     for d in insts:
         d["plan"].close()
+
+
+def test_batch_streamed_classes_match_single_runs():
+    """Streamed instances of one class (N' = 2^14, two subbands, 7 taps) with
+    4, 2 and 3 steps run their steps as shared launches over all their blocks
+    (the blocks of the instances still stepping); two instances that share a
+    plan run one by one.  Every output equals the instance's own cbessfm_run
+    bit for bit, and the FP64 oracle to the parity bar, also after a graph
+    replay."""
+    from paper_2409_14489_amd import Batch
+    shapes = [
+        (2, 2 ** 14, 4096, 4, 0.3, 7, 40000, 1, "circular", 2),
+        (2, 2 ** 14, 2048, 2, 0.5, 7, 30000, 2, "zero", 1),
+        (2, 2 ** 14, 4096, 3, 0.4, 7, 25000, 1, "circular", 2),
+        (1, 1024, 128, 2, 0.5, 11, 9000, 1, "circular", 1),
+    ]
+    insts = make_instances(shapes, seed0=2100)
+    # a second field on the plan of instance 2: both of its instances run alone
+    x_extra = random_field((2, 25000), 777, power_w=4e-3)
+    extra = dict(plan=insts[2]["plan"], oracle=insts[2]["oracle"], x=x_extra,
+                 xt=torch.from_numpy(x_extra.astype(np.complex64)).cuda())
+    extra["yt"] = torch.empty_like(extra["xt"])
+    insts.append(extra)
+    b = Batch([(d["plan"], d["xt"], d["yt"]) for d in insts])
+    info = b.info()
+    print(info)
+    assert info["streamed"] == 4 and info["launches"] == 1
+    b.run()
+    torch.cuda.synchronize()
+    assert b.status() == 0
+    eager = [d["yt"].clone() for d in insts]
+    for k, d in enumerate(insts):
+        single = d["plan"].run(d["xt"])
+        torch.cuda.synchronize()
+        assert torch.equal(single, eager[k]), k
+    for k in (0, 1, 4):
+        d = insts[k]
+        got = eager[k].cpu().numpy().astype(np.complex128)
+        ref = oracle.run(d["x"], d["oracle"])
+        e_or, e_blk = rel_l2(got, ref), worst_block_rel_l2(got, ref, d["plan"].hop)
+        print(k, "vs oracle", e_or, "worst block", e_blk)
+        assert e_or < TOL and e_blk < TOL
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        b.run()
+    for _ in range(2):
+        for d in insts:
+            d["yt"].zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        _ = float(insts[0]["xt"].abs().sum())      # eager work between replays
+        for d, e in zip(insts, eager):
+            assert torch.equal(d["yt"], e)
+    del graph
+    assert b.status() == 0
+    b.close()
+    for d in insts[:4]:
+        d["plan"].close()
