@@ -339,6 +339,10 @@ typedef struct {
   double lower_bound_s;    /* a lower bound of makespan_s for the same item costs */
   int32_t streamed;        /* instances with N' >= 2^14, run by the streaming kernels */
   int64_t streamed_items;  /* their blocks (included in items) */
+  int32_t stream_classes;  /* classes of streamed instances (same N', n_sb, taps) whose
+                              steps run as one launch per stage over all their blocks */
+  int32_t stream_lone;     /* streamed instances run one by one (more than one wave, or a
+                              plan shared with another instance) */
 } cbessfm_batch_info;
 
 /* Builds the schedule and the device tables of a batch on the current
@@ -398,16 +402,20 @@ int cbessfm_schedule(const cbessfm_sched_job* jobs, int32_t n_jobs, int32_t slot
  * over L; Sec. III-A), rounded up to even.  Among the N' in [256, 8192] whose
  * block N = n_sb N' exceeds it, the one with the least predicted time for the
  * instance (blocks / resident teams, rounded up, times the time of one block)
- * wins.  If none of them covers the memory, the smallest streamed block
- * N' in [2^14, 2^17] that does is returned (its time from an operation-count
- * model of the streaming kernels); only if even N' = 2^17 does not cover it,
- * N' = 2^17 with N_ov = min(memory, N / 2) and covered = 0.  A streamed
- * instance needs its own plan's block-state buffers (cbessfm_plan sizes them,
- * at most 512 MB).  flags: CBESSFM_TUNE_MEASURE times each
- * candidate block shape on the current device (probe launches of one block
- * per resident team at 1 and 4 steps, linear in the step count; cached per
- * device and shape for the process); 0 uses an operation-count model and
- * touches no device.  Errors: CBESSFM_EINVAL, CBESSFM_EHIP. */
+ * is the persistent candidate.  The smallest streamed block N' in
+ * [2^14, 2^17] that covers the memory is the streamed candidate (its time:
+ * blocks times the time of one streamed block).  The streamed candidate is
+ * returned if no persistent block covers the memory, or if it is predicted
+ * faster; only if even N' = 2^17 does not cover the memory (and no
+ * persistent block does), N' = 2^17 with N_ov = min(memory, N / 2) and
+ * covered = 0.  A streamed instance needs its own plan's block-state buffers
+ * (cbessfm_plan sizes them, at most 512 MB).  flags: CBESSFM_TUNE_MEASURE
+ * times each candidate block shape on the current device (persistent: probe
+ * launches of one block per resident team; streamed: as many blocks as
+ * 256 MB of block state holds; both at 1 and 4 steps, linear in the step
+ * count, cached per device and shape for the process); 0 uses
+ * operation-count models and touches no device.  Errors: CBESSFM_EINVAL,
+ * CBESSFM_EHIP. */
 enum { CBESSFM_TUNE_MEASURE = 1 };
 
 typedef struct {

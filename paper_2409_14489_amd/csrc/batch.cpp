@@ -288,10 +288,91 @@ int item_cost(const cbessfm_link* link, int log_np, int nsb, int n_taps, int ste
 // Operation-count model of one streamed block (seconds): each step moves the
 // block state through device memory about six times (row pass in and out,
 // intensity, filter, rotation in and out) at an assumed 4 TB/s, plus the
-// input and output stages.
+// input and output stages and a small per-step share of launch latency.
 double stream_block_cost(int log_np, int nsb, int steps) {
   const double state = (double)nsb * (double)(1 << log_np) * 2.0 * sizeof(float2);
-  return (6.0 * steps + 4.0) * state / 4e12 + 20e-6 * steps;
+  return (6.0 * steps + 4.0) * state / 4e12 + 2e-6 * steps;
+}
+
+// Measured time of one streamed block (seconds), linear in the step count: a
+// probe plan runs as many blocks as 256 MB of block state holds (at most one
+// wave) at 1 and 4 steps.  Cached per device and shape like item_cost.
+std::map<CostKey, std::pair<double, double>> g_stream_cost;
+
+int stream_probe_time(const cbessfm_link* link, int log_np, int nsb, int n_taps, int steps, double* out_s) {
+  cbessfm_subbands sb{nsb, 1 << log_np, 0, CBESSFM_FIR_AUTO, 0};
+  std::vector<float> c((size_t)steps * nsb * nsb * n_taps, 0.0f);
+  for (int s = 0; s < steps; ++s)
+    for (int i = 0; i < nsb; ++i)
+      for (int l = 0; l < nsb; ++l) c[(((size_t)s * nsb + i) * nsb + l) * n_taps + n_taps / 2] = 30.0f;
+  cbessfm_coeffs co{n_taps, c.data(), 0};
+  cbessfm_plan_t* p = nullptr;
+  int rc = cbessfm_plan(&p, link, &sb, steps, 0.5, &co);
+  if (rc) return rc;
+  const long long N = (long long)nsb << log_np;
+  const double state = (double)N * 2.0 * sizeof(float2);
+  const int blocks = std::max(1, std::min<int>(p->st_blocks, (int)(256.0 * (1 << 20) / state)));
+  const long long T = (long long)blocks * N;  // no overlap: one block per N samples
+  void* buf = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  double best = 1e30;
+  rc = CBESSFM_EHIP;
+  if (hipMalloc(&buf, (size_t)2 * 2 * T * sizeof(float2)) == hipSuccess &&
+      hipMemset(buf, 0, (size_t)2 * 2 * T * sizeof(float2)) == hipSuccess && hipEventCreate(&e0) == hipSuccess &&
+      hipEventCreate(&e1) == hipSuccess) {
+    char* in = static_cast<char*>(buf);
+    char* out = in + (size_t)2 * T * sizeof(float2);
+    rc = cbessfm_run(p, in, out, T, 1, nullptr);  // warm-up
+    for (int r = 0; r < 3 && rc == CBESSFM_OK; ++r) {
+      float ms = 0.0f;
+      if (hipEventRecord(e0, nullptr) != hipSuccess) rc = CBESSFM_EHIP;
+      if (!rc) rc = cbessfm_run(p, in, out, T, 1, nullptr);
+      if (!rc && (hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                  hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = CBESSFM_EHIP;
+      if (!rc) best = std::min(best, 1e-3 * ms);
+    }
+    if (!rc) rc = cbessfm_status(p);
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (buf) (void)hipFree(buf);
+  cbessfm_destroy(p);
+  if (!rc) *out_s = best / blocks;
+  return rc;
+}
+
+int stream_item_cost(const cbessfm_link* link, int log_np, int nsb, int n_taps, int steps, bool measure,
+                     double* out) {
+  if (!measure) {
+    *out = stream_block_cost(log_np, nsb, steps);
+    return CBESSFM_OK;
+  }
+  const int n_chunks = (n_taps + cbessfm::kTapChunk - 1) / cbessfm::kTapChunk;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return CBESSFM_EHIP;
+  const CostKey key{dev, log_np, nsb, n_chunks};
+  {
+    std::lock_guard<std::mutex> g(g_cost_mu);
+    auto it = g_stream_cost.find(key);
+    if (it != g_stream_cost.end()) {
+      *out = it->second.first + steps * it->second.second;
+      return CBESSFM_OK;
+    }
+  }
+  const int taps = n_chunks * cbessfm::kTapChunk - 1;
+  double t1 = 0.0, t4 = 0.0;
+  int rc = stream_probe_time(link, log_np, nsb, taps, 1, &t1);
+  if (!rc) rc = stream_probe_time(link, log_np, nsb, taps, 4, &t4);
+  if (rc) return rc;
+  const double per_step = std::max(0.0, (t4 - t1) / 3.0);
+  const double base = std::max(0.0, t1 - per_step);
+  {
+    std::lock_guard<std::mutex> g(g_cost_mu);
+    g_stream_cost[key] = {base, per_step};
+  }
+  *out = base + steps * per_step;
+  return CBESSFM_OK;
 }
 
 long long dispersion_memory(const cbessfm_link* link) {
@@ -442,22 +523,31 @@ int cbessfm_autotune(const cbessfm_link* link, int32_t n_sb, int32_t steps, int3
       out->predicted_s = pred;
     }
   }
-  if (out->block_sb && out->covered) return CBESSFM_OK;
-  // No block of the persistent kernels covers the memory: the smallest
-  // streamed block that does (N' = 2^14 .. 2^17), else the largest with
-  // N_ov = min(memory, N / 2) and covered = 0.
+  // The smallest streamed block (N' = 2^14 .. 2^17) that covers the memory,
+  // else the largest with N_ov = min(memory, N / 2): taken when no persistent
+  // block covers the memory, or when it covers it and is predicted faster
+  // (a persistent block whose overlap is most of it does little useful work
+  // per block).
+  const bool have = out->block_sb && out->covered;
   for (int log_np = cbessfm::kStreamMinLog; log_np <= cbessfm::kStreamMaxLog; ++log_np) {
     const long long N = (long long)n_sb << log_np;
     const bool covers = mem < N;
     if (!covers && log_np < cbessfm::kStreamMaxLog) continue;
+    if (have && !covers) break;
+    if (n_taps > (1 << log_np)) break;
     long long ov = covers ? mem : std::min(mem, N / 2);
     ov &= ~1LL;
     const long long items = (long long)batch * ((T + (N - ov) - 1) / (N - ov));
-    out->block_sb = 1 << log_np;
-    out->overlap = (int32_t)ov;
-    out->covered = covers ? 1 : 0;
-    out->measured = 0;
-    out->predicted_s = (double)items * stream_block_cost(log_np, n_sb, steps);
+    double t_blk = 0.0;
+    const int rc = stream_item_cost(link, log_np, n_sb, n_taps, steps, measure, &t_blk);
+    if (rc) return rc;
+    const double pred = (double)items * t_blk;
+    if (!have || pred < best) {
+      out->block_sb = 1 << log_np;
+      out->overlap = (int32_t)ov;
+      out->covered = covers ? 1 : 0;
+      out->predicted_s = pred;
+    }
     break;
   }
   return out->block_sb ? CBESSFM_OK : CBESSFM_EUNSUPPORTED;
@@ -767,6 +857,8 @@ int cbessfm_batch_create(cbessfm_batch_t** out, const cbessfm_instance* inst, in
   b->info.lower_bound_s = bound + stream_time;
   b->info.streamed = (int32_t)b->streamed.size();
   b->info.streamed_items = stream_items;
+  b->info.stream_classes = (int32_t)b->classes.size();
+  b->info.stream_lone = (int32_t)b->lone.size();
   *out = b;
   return CBESSFM_OK;
 }

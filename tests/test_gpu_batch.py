@@ -302,6 +302,7 @@ def test_batch_streamed_classes_match_single_runs():
     info = b.info()
     print(info)
     assert info["streamed"] == 4 and info["launches"] == 1
+    assert info["stream_classes"] == 1 and info["stream_lone"] == 2
     b.run()
     torch.cuda.synchronize()
     assert b.status() == 0
