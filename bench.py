@@ -548,9 +548,10 @@ def leg_batched(args):
            "unit": "2D-symbols/s", "value": n2d / t_batch, "ms_per_run": t_batch * 1e3,
            "separate_launches": {"value": n2d / t_sep, "ms_per_run": t_sep * 1e3, "launches": len(specs)},
            "speedup_vs_separate": t_sep / t_batch, "graph_replayed": True,
-           "launches_per_run": info["launches"], "streamed_instances": info["streamed"],
+           "persistent_launches_per_run": info["launches"], "streamed_instances": info["streamed"],
            "streamed_blocks": info["streamed_items"], "stream_classes": info["stream_classes"],
-           "stream_lone": info["stream_lone"], "teams": info["teams"], "workgroups": info["workgroups"],
+           "stream_lone": info["stream_lone"], "kernel_launches_per_run": info["kernel_launches"],
+           "teams": info["teams"], "workgroups": info["workgroups"],
            "blocks": info["items"], "predicted_ms": info["makespan_s"] * 1e3,
            "lower_bound_ms": info["lower_bound_s"] * 1e3,
            "block_sb_chosen": sorted({t["block_sb"] for t in tuned}),
@@ -984,8 +985,10 @@ def headline(result):
     b = result.get("batched")
     if b:
         line["batched"] = {"value": b["value"], "speedup_vs_separate": b["speedup_vs_separate"],
-                           "launches_per_run": b["launches_per_run"], "streamed": b.get("streamed_instances"),
+                           "persistent_launches_per_run": b["persistent_launches_per_run"],
+                           "streamed": b.get("streamed_instances"),
                            "stream_classes": b.get("stream_classes"),
+                           "kernel_launches_per_run": b.get("kernel_launches_per_run"),
                            "instances_overlap_covers_memory": b["instances_overlap_covers_memory"]}
     line["legs_file"] = result.get("legs_file")
     return line

@@ -343,6 +343,8 @@ typedef struct {
                               steps run as one launch per stage over all their blocks */
   int32_t stream_lone;     /* streamed instances run one by one (more than one wave, or a
                               plan shared with another instance) */
+  int32_t kernel_launches; /* kernels one run launches in all (persistent launches, the
+                              streamed instances' input and output stages, class steps) */
 } cbessfm_batch_info;
 
 /* Builds the schedule and the device tables of a batch on the current

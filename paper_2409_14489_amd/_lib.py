@@ -67,7 +67,8 @@ class BatchInfo(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int32), ("teams", ctypes.c_int32), ("workgroups", ctypes.c_int32),
                 ("items", ctypes.c_int64), ("makespan_s", ctypes.c_double), ("lower_bound_s", ctypes.c_double),
                 ("streamed", ctypes.c_int32), ("streamed_items", ctypes.c_int64),
-                ("stream_classes", ctypes.c_int32), ("stream_lone", ctypes.c_int32)]
+                ("stream_classes", ctypes.c_int32), ("stream_lone", ctypes.c_int32),
+                ("kernel_launches", ctypes.c_int32)]
 
 
 class SchedJob(ctypes.Structure):

@@ -859,6 +859,20 @@ int cbessfm_batch_create(cbessfm_batch_t** out, const cbessfm_instance* inst, in
   b->info.streamed_items = stream_items;
   b->info.stream_classes = (int32_t)b->classes.size();
   b->info.stream_lone = (int32_t)b->lone.size();
+  {
+    long long k = (long long)b->launches.size();
+    for (const auto& c : b->classes) {
+      k += 4LL * c.max_steps;
+      for (int m : c.members) k += cbessfm::stream_launches(b->streamed[m].plan, 0);
+    }
+    for (int m : b->lone) {
+      const cbessfm_instance& a = b->streamed[m];
+      const long long items = (long long)a.batch * ((a.T + a.plan->hop - 1) / a.plan->hop);
+      const long long waves = (items + a.plan->st_blocks - 1) / a.plan->st_blocks;
+      k += waves * cbessfm::stream_launches(a.plan, a.plan->steps);
+    }
+    b->info.kernel_launches = (int32_t)std::min<long long>(k, 0x7fffffff);
+  }
   *out = b;
   return CBESSFM_OK;
 }

@@ -256,6 +256,9 @@ int stream_output(cbessfm_plan_t* p, const void* in, void* out, long long T, int
 void stream_blocks(const cbessfm_plan_t* p, long long T, int batch, StreamBlk* out);
 int stream_class_step(int log_np, int n_sb, int n_taps, int tap_pad, int step, const StreamBlk* d_blks, int nb,
                       hipStream_t s);
+// Kernel launches of one wave of a streaming forward with `steps` steps (0:
+// its block input and output only).
+int stream_launches(const cbessfm_plan_t* p, int steps);
 StreamBwdLayout stream_bwd_layout(const cbessfm_plan_t* p, long long T, int batch, int ck_every, bool gin);
 int launch_stream_backward(cbessfm_plan_t* p, const void* field_in, const void* grad_out, void* grad_in,
                            float* grad_c, float* grad_rho, double* grad_gvd, long long T, int batch, int ck_every,

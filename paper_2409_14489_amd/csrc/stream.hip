@@ -1257,6 +1257,13 @@ int stream_class_step(int log_np, int n_sb, int n_taps, int tap_pad, int step, c
   return ok ? CBESSFM_OK : CBESSFM_EHIP;
 }
 
+int stream_launches(const cbessfm_plan_t* p, int steps) {
+  const bool multi = p->sb.n_sb > 1;
+  const int in = multi ? 3 : 1;   // head [, row pass, DEMUX]
+  const int out = multi ? 4 : 2;  // [row pass, MUX,] row pass, tail
+  return in + out + 4 * steps;    // each step: row pass, intensity, filter, rotation
+}
+
 int launch_stream_forward(cbessfm_plan_t* p, const void* in, void* out, long long T, int batch, hipStream_t s) {
   if (p->nlpr != CBESSFM_NLPR_AVERAGED) return CBESSFM_EUNSUPPORTED;
   Tables tb;
