@@ -400,10 +400,11 @@ struct cbessfm_batch {
   std::vector<cbessfm_instance> streamed;
   // Streamed instances whose blocks fit one wave of their own plan (and whose
   // plan no other instance uses) are grouped into classes of equal N', n_sb
-  // and taps: each step of a class is one launch per stage over the blocks of
-  // all its instances still stepping (members by step count, descending, so
-  // those blocks are a prefix of the block table).  The other streamed
-  // instances run one by one.
+  // and taps: the block input and output of a class, and each of its steps,
+  // are one launch per stage over the blocks of all its instances (for a
+  // step, those still stepping: members by step count, descending, so their
+  // blocks are a prefix of the block table).  The other streamed instances
+  // run one by one.
   struct StreamClass {
     int log_np = 0, n_sb = 0, n_taps = 0, tap_pad = 0, max_steps = 0;
     std::vector<int> members;     // indices into streamed
@@ -793,7 +794,7 @@ int cbessfm_batch_create(cbessfm_batch_t** out, const cbessfm_instance* inst, in
         const long long nb = (long long)a.batch * ((a.T + a.plan->hop - 1) / a.plan->hop);
         const size_t at = blks.size();
         blks.resize(at + (size_t)nb);
-        cbessfm::stream_blocks(a.plan, a.T, a.batch, blks.data() + at);
+        cbessfm::stream_blocks(a.plan, a.field_in, a.field_out, a.T, a.batch, blks.data() + at);
         nb_of.push_back((int)nb);
         uc += cost[k];
       }
@@ -861,10 +862,8 @@ int cbessfm_batch_create(cbessfm_batch_t** out, const cbessfm_instance* inst, in
   b->info.stream_lone = (int32_t)b->lone.size();
   {
     long long k = (long long)b->launches.size();
-    for (const auto& c : b->classes) {
-      k += 4LL * c.max_steps;
-      for (int m : c.members) k += cbessfm::stream_launches(b->streamed[m].plan, 0);
-    }
+    for (const auto& c : b->classes)
+      k += cbessfm::stream_launches(b->streamed[c.members.front()].plan, c.max_steps);
     for (int m : b->lone) {
       const cbessfm_instance& a = b->streamed[m];
       const long long items = (long long)a.batch * ((a.T + a.plan->hop - 1) / a.plan->hop);
@@ -901,16 +900,11 @@ int cbessfm_batch_run(cbessfm_batch_t* b, void* stream) {
       continue;
     }
     const auto& c = b->classes[u];
-    for (size_t j = 0; j < c.members.size() && !rc; ++j) {
-      const cbessfm_instance& a = b->streamed[c.members[j]];
-      rc = cbessfm::stream_input(a.plan, a.field_in, a.field_out, a.T, a.batch, st);
-    }
+    const cbessfm_plan_t* p0 = b->streamed[c.members.front()].plan;
+    rc = cbessfm::stream_class_input(p0, c.d_blks, c.active.front(), st);
     for (int step = 0; step < c.max_steps && !rc; ++step)
       rc = cbessfm::stream_class_step(c.log_np, c.n_sb, c.n_taps, c.tap_pad, step, c.d_blks, c.active[step], st);
-    for (size_t j = 0; j < c.members.size() && !rc; ++j) {
-      const cbessfm_instance& a = b->streamed[c.members[j]];
-      rc = cbessfm::stream_output(a.plan, a.field_in, a.field_out, a.T, a.batch, st);
-    }
+    if (!rc) rc = cbessfm::stream_class_output(p0, c.d_blks, c.active.front(), st);
   }
   // join every side stream even after a failed launch
   for (size_t k = 0; k < b->side.size(); ++k)

@@ -125,10 +125,15 @@ struct StreamBlk {
   float* th;              // [n_sb][N'] phases
   const float2* h_first;  // dispersion filter of step 0, [n_sb][N'] (permuted order)
   const float2* h_mid;    // of step s >= 1: h_mid + (s - 1) h_stride
+  const float2* h_last;   // of the last segment (step -1 below)
   long long h_stride;
   const float* cpad;      // [steps][n_sb][n_sb][tap_pad] zero-padded coefficients
   const float2* tw2;      // column twiddles
   const float2* twr;      // row twiddles
+  const float2* poly;     // [n_sb][N'] polyphase twiddles of the DEMUX / MUX
+  const float2* in;       // the block's batch entry of the input [2][T]
+  float2* out;            // and of the output
+  int T, blk, hop, n_ov, boundary;  // length, block index in the entry, framing
 };
 
 // Workspace layout of one streaming adjoint call (stream.hip): byte offsets
@@ -247,15 +252,16 @@ int launch_batch(int log_np, const BatchArgs& a, int grid, hipStream_t s);
 void fill_inst(const cbessfm_plan_t* p, const void* in, void* out, long long T, int batch, Inst& d);
 // stream.hip
 int launch_stream_forward(cbessfm_plan_t* p, const void* in, void* out, long long T, int batch, hipStream_t s);
-// The three parts of a streaming forward whose blocks fit one wave (batch
-// instances): block input, one step over a table of blocks (any number of
-// instances of one class), block output.
+// A streaming forward whose blocks fit one wave (batch instances), over a
+// table of blocks of any number of instances of one class (same N', n_sb and
+// taps): block input, one step, block output.  p0: any plan of the class
+// (for N', n_sb and the DEMUX weights).
 int stream_single_wave(const cbessfm_plan_t* p, long long T, int batch);
-int stream_input(cbessfm_plan_t* p, const void* in, void* out, long long T, int batch, hipStream_t s);
-int stream_output(cbessfm_plan_t* p, const void* in, void* out, long long T, int batch, hipStream_t s);
-void stream_blocks(const cbessfm_plan_t* p, long long T, int batch, StreamBlk* out);
+void stream_blocks(const cbessfm_plan_t* p, const void* in, void* out, long long T, int batch, StreamBlk* out_blk);
+int stream_class_input(const cbessfm_plan_t* p0, const StreamBlk* d_blks, int nb, hipStream_t s);
 int stream_class_step(int log_np, int n_sb, int n_taps, int tap_pad, int step, const StreamBlk* d_blks, int nb,
                       hipStream_t s);
+int stream_class_output(const cbessfm_plan_t* p0, const StreamBlk* d_blks, int nb, hipStream_t s);
 // Kernel launches of one wave of a streaming forward with `steps` steps (0:
 // its block input and output only).
 int stream_launches(const cbessfm_plan_t* p, int steps);

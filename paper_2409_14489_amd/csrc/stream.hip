@@ -194,31 +194,46 @@ __device__ __forceinline__ void col_forward(const float2* __restrict__ tw2, int 
 // of every polyphase component.  Thread g: a = g mod n_sb, n1 = g / n_sb, so
 // neighbouring threads read neighbouring input samples.
 template <int N2>
-__global__ __launch_bounds__(kColThreads) void st_head_kernel(StreamArgs a) {
+__global__ __launch_bounds__(kColThreads) void st_head_kernel(StreamArgs a, const StreamBlk* __restrict__ tab) {
   constexpr int NP = kRow * N2;
   const int g = blockIdx.x * kColThreads + threadIdx.x;
   if (g >= a.n_sb * kRow) return;
-  const int w = blockIdx.y;
-  const int item = a.item0 + w;
-  const int inst = item / a.nblk, blk = item - inst * a.nblk;
   const int nsb = a.n_sb, ap = g % nsb, n1 = g / nsb;
-  const int T = a.T;
-  const float2* sx = a.in + (size_t)inst * 2 * T;
-  const int first = frame_first(blk, a.hop, a.n_ov, T, a.boundary);
+  const float2* sx;
+  float2* base;
+  const float2* tw2 = a.tw2;
+  int T, first, boundary;
+  if (tab != nullptr) {  // blockIdx.y = entry of the block table
+    const StreamBlk& e = tab[blockIdx.y];
+    T = e.T;
+    boundary = e.boundary;
+    sx = e.in;
+    first = frame_first(e.blk, e.hop, e.n_ov, T, boundary);
+    base = e.st + (size_t)ap * 2 * NP;
+    tw2 = e.tw2;
+  } else {
+    const int w = blockIdx.y;
+    const int item = a.item0 + w;
+    const int inst = item / a.nblk, blk = item - inst * a.nblk;
+    T = a.T;
+    boundary = a.boundary;
+    sx = a.in + (size_t)inst * 2 * T;
+    first = frame_first(blk, a.hop, a.n_ov, T, boundary);
+    base = a.st + ((size_t)w * nsb + ap) * 2 * NP;
+  }
   const bool short_seq = T < nsb * NP;
-  float2* base = a.st + ((size_t)w * nsb + ap) * 2 * NP;
 #pragma unroll 1
   for (int pol = 0; pol < 2; ++pol) {
     float2 v[N2];
 #pragma unroll
     for (int k = 0; k < N2; ++k) {
       const int n = ap + nsb * (n1 + kRow * k);
-      const int pos = frame_pos(first, n, T, a.boundary, short_seq);
+      const int pos = frame_pos(first, n, T, boundary, short_seq);
       float2 u = make_float2(0.f, 0.f);
       if (pos >= 0) u = sx[(size_t)pol * T + pos];
       v[k] = cscale(u, (n & 1) ? -1.0f : 1.0f);
     }
-    col_forward<N2>(a.tw2, n1, v);
+    col_forward<N2>(tw2, n1, v);
     store_col<N2>(base + (size_t)pol * NP, n1, v);
   }
 }
@@ -228,7 +243,8 @@ __global__ __launch_bounds__(kColThreads) void st_head_kernel(StreamArgs a) {
 // when CONJ, the adjoint's filter), optional inverse size-N1 DFT.  Reads src,
 // writes dst (the same array for an in-place pass).  blockIdx.x = i N2 + k2,
 // blockIdx.y = block of the wave, or, with a block table `blk`, the entry of
-// that table (in place on its state, with the filter of step `step`).
+// that table (in place on its state, with the filter of step `step`, or of
+// the last segment for step < 0).
 template <bool FWD, bool GVD, bool INV, bool CONJ = false>
 __global__ __launch_bounds__(kRowNT, 2) void st_row_kernel(const float2* src, float2* dst,
                                                         const float2* __restrict__ h,
@@ -241,7 +257,7 @@ __global__ __launch_bounds__(kRowNT, 2) void st_row_kernel(const float2* src, fl
     const StreamBlk& e = blk[blockIdx.y];
     src = e.st;
     dst = e.st;
-    h = step == 0 ? e.h_first : e.h_mid + (size_t)(step - 1) * e.h_stride;
+    h = step < 0 ? e.h_last : step == 0 ? e.h_first : e.h_mid + (size_t)(step - 1) * e.h_stride;
     twr = e.twr;
     wb = 0;
   }
@@ -281,10 +297,18 @@ __global__ __launch_bounds__(kRowNT, 2) void st_row_kernel(const float2* src, fl
 // Pointwise over the (permuted) bin position, in place.
 template <bool INV>
 __global__ __launch_bounds__(256) void st_mix_kernel(float2* __restrict__ st, const float2* __restrict__ poly,
-                                                     StreamWsb wsb, int nsb, int np) {
+                                                     StreamWsb wsb, int nsb, int np,
+                                                     const StreamBlk* __restrict__ tab) {
   const int q = blockIdx.x * 256 + threadIdx.x;
   if (q >= np) return;
-  float2* base = st + (size_t)blockIdx.y * nsb * 2 * np + q;
+  size_t wb = blockIdx.y;
+  if (tab != nullptr) {  // blockIdx.y = entry of the block table
+    const StreamBlk& e = tab[blockIdx.y];
+    st = e.st;
+    poly = e.poly;
+    wb = 0;
+  }
+  float2* base = st + wb * nsb * 2 * np + q;
   float2 vx[kMaxSubbands], vy[kMaxSubbands];
 #pragma unroll
   for (int a = 0; a < kMaxSubbands; ++a) {
@@ -484,27 +508,45 @@ __global__ __launch_bounds__(kColThreads) void st_rotate_kernel(const float2* sr
 // Block output: inverse column pass of polyphase component a, (-1)^n, kept
 // samples [n_ov/2, N - n_ov/2) that fall inside [0, T).
 template <int N2>
-__global__ __launch_bounds__(kColThreads) void st_tail_kernel(StreamArgs a) {
+__global__ __launch_bounds__(kColThreads) void st_tail_kernel(StreamArgs a, const StreamBlk* __restrict__ tab) {
   constexpr int NP = kRow * N2;
   const int g = blockIdx.x * kColThreads + threadIdx.x;
   if (g >= a.n_sb * kRow) return;
-  const int w = blockIdx.y;
-  const int item = a.item0 + w;
-  const int inst = item / a.nblk, blk = item - inst * a.nblk;
   const int nsb = a.n_sb, ap = g % nsb, n1 = g / nsb;
-  const int T = a.T;
-  const int keep_lo = a.n_ov / 2, keep_hi = nsb * NP - a.n_ov / 2;
-  float2* dx = a.out + (size_t)inst * 2 * T;
-  const float2* base = a.st + ((size_t)w * nsb + ap) * 2 * NP;
+  int T, blk, hop, n_ov;
+  float2* dx;
+  const float2* base;
+  const float2* tw2 = a.tw2;
+  if (tab != nullptr) {  // blockIdx.y = entry of the block table
+    const StreamBlk& e = tab[blockIdx.y];
+    T = e.T;
+    blk = e.blk;
+    hop = e.hop;
+    n_ov = e.n_ov;
+    dx = e.out;
+    base = e.st + (size_t)ap * 2 * NP;
+    tw2 = e.tw2;
+  } else {
+    const int w = blockIdx.y;
+    const int item = a.item0 + w;
+    const int inst = item / a.nblk;
+    blk = item - inst * a.nblk;
+    T = a.T;
+    hop = a.hop;
+    n_ov = a.n_ov;
+    dx = a.out + (size_t)inst * 2 * T;
+    base = a.st + ((size_t)w * nsb + ap) * 2 * NP;
+  }
+  const int keep_lo = n_ov / 2, keep_hi = nsb * NP - n_ov / 2;
 #pragma unroll 1
   for (int pol = 0; pol < 2; ++pol) {
     float2 v[N2];
     load_col<N2>(base + (size_t)pol * NP, n1, v);
-    col_inverse<N2>(a.tw2, n1, v);
+    col_inverse<N2>(tw2, n1, v);
 #pragma unroll
     for (int k = 0; k < N2; ++k) {
       const int n = ap + nsb * (n1 + kRow * k);
-      const int pos = blk * a.hop + n - keep_lo;
+      const int pos = blk * hop + n - keep_lo;
       if (n >= keep_lo && n < keep_hi && pos < T) dx[(size_t)pol * T + pos] = cscale(v[k], (n & 1) ? -1.0f : 1.0f);
     }
   }
@@ -1078,13 +1120,13 @@ template <int N2>
 bool wave_input(const StreamArgs& a, const Tables& tb, hipStream_t s) {
   const int nsb = a.n_sb;
   const dim3 col_grid((nsb * kRow + kColThreads - 1) / kColThreads, a.nb);
-  st_head_kernel<N2><<<col_grid, kColThreads, 0, s>>>(a);
+  st_head_kernel<N2><<<col_grid, kColThreads, 0, s>>>(a, nullptr);
   bool ok = ok_launch();
   if (nsb > 1) {
     StreamWsb wsb;
     for (int k = 0; k < kMaxSubbands; ++k) wsb.w[k] = tb.wsb[k];
     ok = ok && row<true, false, false>(a, a.st, a.st, nullptr, s);
-    st_mix_kernel<false><<<dim3(a.np / 256, a.nb), 256, 0, s>>>(a.st, tb.poly_tw, wsb, nsb, a.np);
+    st_mix_kernel<false><<<dim3(a.np / 256, a.nb), 256, 0, s>>>(a.st, tb.poly_tw, wsb, nsb, a.np, nullptr);
     ok = ok && ok_launch();
   }
   return ok;
@@ -1119,13 +1161,13 @@ bool wave_output(const StreamArgs& a, const Tables& tb, hipStream_t s) {
     StreamWsb wsb;
     for (int k = 0; k < kMaxSubbands; ++k) wsb.w[k] = tb.wsb[k];
     ok = ok && row<true, true, false>(a, a.st, a.st, tb.h_last, s);
-    st_mix_kernel<true><<<dim3(a.np / 256, a.nb), 256, 0, s>>>(a.st, tb.poly_tw, wsb, nsb, a.np);
+    st_mix_kernel<true><<<dim3(a.np / 256, a.nb), 256, 0, s>>>(a.st, tb.poly_tw, wsb, nsb, a.np, nullptr);
     ok = ok && ok_launch();
     ok = ok && row<false, false, true>(a, a.st, a.st, nullptr, s);
   } else {
     ok = ok && row<true, true, true>(a, a.st, a.st, tb.h_last, s);
   }
-  st_tail_kernel<N2><<<dim3((nsb * kRow + kColThreads - 1) / kColThreads, a.nb), kColThreads, 0, s>>>(a);
+  st_tail_kernel<N2><<<dim3((nsb * kRow + kColThreads - 1) / kColThreads, a.nb), kColThreads, 0, s>>>(a, nullptr);
   return ok && ok_launch();
 }
 
@@ -1160,6 +1202,47 @@ bool class_step(int nsb, int n_taps, int tap_pad, int step, const StreamBlk* blk
   return ok && ok_launch();
 }
 
+// Block input and output of every block in the table: the kernels of
+// wave_input and wave_output, each one launch over all the blocks.
+template <int N2>
+bool class_input(int nsb, const StreamWsb& wsb, const StreamBlk* blks, int nb, hipStream_t s) {
+  constexpr int NP = kRow * N2;
+  StreamArgs a{};
+  a.n_sb = nsb;
+  st_head_kernel<N2><<<dim3((nsb * kRow + kColThreads - 1) / kColThreads, nb), kColThreads, 0, s>>>(a, blks);
+  bool ok = ok_launch();
+  if (nsb > 1) {
+    st_row_kernel<true, false, false>
+        <<<dim3(nsb * N2, nb), kRowNT, 0, s>>>(nullptr, nullptr, nullptr, nullptr, nsb, N2, NP, blks, 0);
+    ok = ok && ok_launch();
+    st_mix_kernel<false><<<dim3(NP / 256, nb), 256, 0, s>>>(nullptr, nullptr, wsb, nsb, NP, blks);
+    ok = ok && ok_launch();
+  }
+  return ok;
+}
+
+template <int N2>
+bool class_output(int nsb, const StreamWsb& wsb, const StreamBlk* blks, int nb, hipStream_t s) {
+  constexpr int NP = kRow * N2;
+  const dim3 row_grid(nsb * N2, nb);
+  bool ok;
+  if (nsb > 1) {
+    st_row_kernel<true, true, false><<<row_grid, kRowNT, 0, s>>>(nullptr, nullptr, nullptr, nullptr, nsb, N2, NP, blks, -1);
+    ok = ok_launch();
+    st_mix_kernel<true><<<dim3(NP / 256, nb), 256, 0, s>>>(nullptr, nullptr, wsb, nsb, NP, blks);
+    ok = ok && ok_launch();
+    st_row_kernel<false, false, true><<<row_grid, kRowNT, 0, s>>>(nullptr, nullptr, nullptr, nullptr, nsb, N2, NP, blks, 0);
+    ok = ok && ok_launch();
+  } else {
+    st_row_kernel<true, true, true><<<row_grid, kRowNT, 0, s>>>(nullptr, nullptr, nullptr, nullptr, nsb, N2, NP, blks, -1);
+    ok = ok_launch();
+  }
+  StreamArgs a{};
+  a.n_sb = nsb;
+  st_tail_kernel<N2><<<dim3((nsb * kRow + kColThreads - 1) / kColThreads, nb), kColThreads, 0, s>>>(a, blks);
+  return ok && ok_launch();
+}
+
 void fill_stream_args(const cbessfm_plan_t* p, const void* in, void* out, long long T, StreamArgs& a) {
   a.in = static_cast<const float2*>(in);
   a.out = static_cast<float2*>(out);
@@ -1185,62 +1268,70 @@ int stream_single_wave(const cbessfm_plan_t* p, long long T, int batch) {
   return p->stream && p->nlpr == CBESSFM_NLPR_AVERAGED && items <= p->st_blocks;
 }
 
-int stream_input(cbessfm_plan_t* p, const void* in, void* out, long long T, int batch, hipStream_t s) {
-  if (!stream_single_wave(p, T, batch)) return CBESSFM_EUNSUPPORTED;
-  Tables tb;
-  fill_tables(p, tb);
-  StreamArgs a;
-  fill_stream_args(p, in, out, T, a);
-  a.item0 = 0;
-  a.nb = batch * a.nblk;
-  bool ok;
-  switch (p->log_np) {
-    case 14: ok = wave_input<4>(a, tb, s); break;
-    case 15: ok = wave_input<8>(a, tb, s); break;
-    case 16: ok = wave_input<16>(a, tb, s); break;
-    case 17: ok = wave_input<32>(a, tb, s); break;
-    default: return CBESSFM_EUNSUPPORTED;
-  }
-  return ok ? CBESSFM_OK : CBESSFM_EHIP;
-}
-
-int stream_output(cbessfm_plan_t* p, const void* in, void* out, long long T, int batch, hipStream_t s) {
-  if (!stream_single_wave(p, T, batch)) return CBESSFM_EUNSUPPORTED;
-  Tables tb;
-  fill_tables(p, tb);
-  StreamArgs a;
-  fill_stream_args(p, in, out, T, a);
-  a.item0 = 0;
-  a.nb = batch * a.nblk;
-  bool ok;
-  switch (p->log_np) {
-    case 14: ok = wave_output<4>(a, tb, s); break;
-    case 15: ok = wave_output<8>(a, tb, s); break;
-    case 16: ok = wave_output<16>(a, tb, s); break;
-    case 17: ok = wave_output<32>(a, tb, s); break;
-    default: return CBESSFM_EUNSUPPORTED;
-  }
-  return ok ? CBESSFM_OK : CBESSFM_EHIP;
-}
-
-void stream_blocks(const cbessfm_plan_t* p, long long T, int batch, StreamBlk* out) {
+void stream_blocks(const cbessfm_plan_t* p, const void* in, void* out, long long T, int batch, StreamBlk* out_blk) {
   Tables tb;
   fill_tables(p, tb);
   const int nsb = p->sb.n_sb;
   const size_t np = (size_t)p->Np;
-  const long long nb = (long long)batch * ((T + p->hop - 1) / p->hop);
-  for (long long b = 0; b < nb; ++b) {
-    StreamBlk& e = out[b];
+  const int nblk = (int)((T + p->hop - 1) / p->hop);
+  for (long long b = 0; b < (long long)batch * nblk; ++b) {
+    StreamBlk& e = out_blk[b];
     e.st = p->d_st + (size_t)b * nsb * 2 * np;
     e.pb = p->d_pb + (size_t)b * nsb * np;
     e.th = p->d_th + (size_t)b * nsb * np;
     e.h_first = tb.h_first;
     e.h_mid = tb.h_mid;
+    e.h_last = tb.h_last;
     e.h_stride = tb.h_stride;
     e.cpad = p->d_cpad;
     e.tw2 = p->d_tw;
     e.twr = p->d_tw + p->Np;
+    e.poly = tb.poly_tw;
+    const long long entry = b / nblk;  // batch entry
+    e.in = static_cast<const float2*>(in) + (size_t)entry * 2 * T;
+    e.out = static_cast<float2*>(out) + (size_t)entry * 2 * T;
+    e.T = (int)T;
+    e.blk = (int)(b - entry * nblk);
+    e.hop = p->hop;
+    e.n_ov = p->sb.overlap;
+    e.boundary = p->sb.boundary;
   }
+}
+
+int stream_class_input(const cbessfm_plan_t* p0, const StreamBlk* d_blks, int nb, hipStream_t s) {
+  if (nb < 1) return CBESSFM_OK;
+  Tables tb;
+  fill_tables(p0, tb);
+  StreamWsb wsb;
+  for (int k = 0; k < kMaxSubbands; ++k) wsb.w[k] = tb.wsb[k];
+  const int nsb = p0->sb.n_sb;
+  bool ok;
+  switch (p0->log_np) {
+    case 14: ok = class_input<4>(nsb, wsb, d_blks, nb, s); break;
+    case 15: ok = class_input<8>(nsb, wsb, d_blks, nb, s); break;
+    case 16: ok = class_input<16>(nsb, wsb, d_blks, nb, s); break;
+    case 17: ok = class_input<32>(nsb, wsb, d_blks, nb, s); break;
+    default: return CBESSFM_EUNSUPPORTED;
+  }
+  return ok ? CBESSFM_OK : CBESSFM_EHIP;
+}
+
+int stream_class_output(const cbessfm_plan_t* p0, const StreamBlk* d_blks, int nb, hipStream_t s) {
+  if (nb < 1) return CBESSFM_OK;
+  Tables tb;
+  fill_tables(p0, tb);
+  StreamWsb wsb;
+  for (int k = 0; k < kMaxSubbands; ++k) wsb.w[k] = tb.wsb[k];
+  const int nsb = p0->sb.n_sb;
+  bool ok;
+  switch (p0->log_np) {
+    case 14: ok = class_output<4>(nsb, wsb, d_blks, nb, s); break;
+    case 15: ok = class_output<8>(nsb, wsb, d_blks, nb, s); break;
+    case 16: ok = class_output<16>(nsb, wsb, d_blks, nb, s); break;
+    case 17: ok = class_output<32>(nsb, wsb, d_blks, nb, s); break;
+    default: return CBESSFM_EUNSUPPORTED;
+  }
+  return ok ? CBESSFM_OK : CBESSFM_EHIP;
 }
 
 int stream_class_step(int log_np, int n_sb, int n_taps, int tap_pad, int step, const StreamBlk* d_blks, int nb,
@@ -1404,7 +1495,7 @@ int bwd_wave(const StreamBwdCall& c, StreamArgs a) {
   ok = ok && ok_launch();
   if (nsb > 1) {
     ok = ok && row<true, false, false>(a, c.G(), c.G(), nullptr, s);
-    st_mix_kernel<false><<<dim3(a.np / 256, a.nb), 256, 0, s>>>(c.G(), tb.poly_tw, wsb, nsb, a.np);
+    st_mix_kernel<false><<<dim3(a.np / 256, a.nb), 256, 0, s>>>(c.G(), tb.poly_tw, wsb, nsb, a.np, nullptr);
     ok = ok && ok_launch();
     ok = ok && gvd_adj<false, true, true, true>(c, a, c.S(steps), tb.h_last, steps);
   } else {
@@ -1462,7 +1553,7 @@ int bwd_wave(const StreamBwdCall& c, StreamArgs a) {
   // adjoint of the input stage: block input cotangents
   if (c.want_gin && ok) {
     if (nsb > 1) {
-      st_mix_kernel<true><<<dim3(a.np / 256, a.nb), 256, 0, s>>>(c.G(), tb.poly_tw, wsb, nsb, a.np);
+      st_mix_kernel<true><<<dim3(a.np / 256, a.nb), 256, 0, s>>>(c.G(), tb.poly_tw, wsb, nsb, a.np, nullptr);
       ok = ok_launch() && row<false, false, true>(a, c.G(), c.G(), nullptr, s);
     }
     st_adj_head_kernel<N2><<<col_grid, kColThreads, 0, s>>>(a, c.gin());

@@ -303,9 +303,9 @@ def test_batch_streamed_classes_match_single_runs():
     print(info)
     assert info["streamed"] == 4 and info["launches"] == 1
     assert info["stream_classes"] == 1 and info["stream_lone"] == 2
-    # one persistent launch; the class: 4 steps x 4 stages + 2 x (3 input + 4 output
-    # kernels); each lone instance: 3 + 4 + 3 steps x 4
-    assert info["kernel_launches"] == 1 + (16 + 14) + 2 * 19
+    # one persistent launch; the class: 3 input + 4 output kernels + 4 steps x 4
+    # stages; each lone instance: 3 + 4 + 3 steps x 4
+    assert info["kernel_launches"] == 1 + (7 + 16) + 2 * 19
     b.run()
     torch.cuda.synchronize()
     assert b.status() == 0
