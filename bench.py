@@ -991,7 +991,19 @@ def headline(result):
                            "kernel_launches_per_run": b.get("kernel_launches_per_run"),
                            "instances_overlap_covers_memory": b["instances_overlap_covers_memory"]}
     line["legs_file"] = result.get("legs_file")
-    return line
+    return rounded(line)
+
+
+def rounded(obj, digits=5):
+    """Floats of a record to `digits` significant digits (the full values are in
+    the legs file)."""
+    if isinstance(obj, float):
+        return float(f"{obj:.{digits}g}")
+    if isinstance(obj, dict):
+        return {k: rounded(v, digits) for k, v in obj.items()}
+    if isinstance(obj, list):
+        return [rounded(v, digits) for v in obj]
+    return obj
 
 
 def main():
