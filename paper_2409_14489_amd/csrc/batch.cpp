@@ -709,7 +709,7 @@ int cbessfm_batch_create(cbessfm_batch_t** out, const cbessfm_instance* inst, in
         it.inst = (int)j;
         it.sub = (int)(id - first_item[j]);
         it.round_off = rounds;
-        rounds += cbessfm::fwd_rounds(bt.insts[j].steps, false);
+        rounds += cbessfm::fwd_rounds(bt.insts[j].steps, 1u);
         items.push_back(it);
       }
       t.rounds = rounds;

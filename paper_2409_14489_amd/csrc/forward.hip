@@ -19,6 +19,13 @@
 
 namespace cbessfm {
 
+// Exchange rounds per step: one, or two for the dual-polarisation NLPR when
+// its two filters cannot share a round (their rows do not fit the LDS).
+template <int N, bool DUAL>
+__host__ __device__ constexpr unsigned dual_rounds() {
+  return DUAL && !DualFir<N>::fits ? 2u : 1u;
+}
+
 // One overlap-and-save block of one instance, as member c.me of a team.
 // sub = batch entry * nblk + block; the team's exchange rounds for this block
 // are round0 .. round0 + steps + 1.  xs: one of the team's two spectrum slots
@@ -59,20 +66,25 @@ __device__ __forceinline__ void fwd_item(TeamCtx& c, const Inst& d, int sub, uns
     float p[RR], theta[RR];
     intensity<N>(x, y, p);
     const size_t crow = ((size_t)(s * nsb + me) * nsb) * tap_pad;
-    const unsigned round = round0 + 1u + (unsigned)s * (DUAL ? 2u : 1u);
+    const unsigned round = round0 + 1u + (unsigned)s * dual_rounds<N, DUAL>();
     uint64_t* xrow = xp_team + (size_t)(round & 1u) * nsb * 2 * N;
-    if (!DUAL && (FIR == 1 || (FIR == 2 && d.tab.chat != nullptr)))
-      coupled_fir_freq<N>(c, d.tab.chat + ((size_t)(s * nsb + me) * nsb) * N, xrow, round, p, theta, lf);
-    else
-      coupled_fir<N>(c, d.tab.cpad + crow, xrow, round, p, theta, lf);
-    if (DUAL) {
+    if constexpr (DUAL) {
       // theta^{x,y} = theta +- phi, phi_i = (1/3) sum_{l != i} C_il (*) (|x_l|^2 - |y_l|^2)
-      float phi[RR];
-      intensity_diff<N>(x, y, p);
-      uint64_t* drow = xp_team + (size_t)((round + 1u) & 1u) * nsb * 2 * N;
-      coupled_fir<N>(c, d.tab.cdpad + crow, drow, round + 1u, p, phi, lf);
+      float phi[RR], pd[RR];
+      intensity_diff<N>(x, y, pd);
+      if constexpr (DualFir<N>::fits) {
+        coupled_fir_dual<N>(c, d.tab.cpad + crow, d.tab.cdpad + crow, xrow, round, p, pd, theta, phi, lf);
+      } else {
+        coupled_fir<N>(c, d.tab.cpad + crow, xrow, round, p, theta, lf);
+        uint64_t* drow = xp_team + (size_t)((round + 1u) & 1u) * nsb * 2 * N;
+        coupled_fir<N>(c, d.tab.cdpad + crow, drow, round + 1u, pd, phi, lf);
+      }
       rotate_dual<N>(x, y, theta, phi);
     } else {
+      if (FIR == 1 || (FIR == 2 && d.tab.chat != nullptr))
+        coupled_fir_freq<N>(c, d.tab.chat + ((size_t)(s * nsb + me) * nsb) * N, xrow, round, p, theta, lf);
+      else
+        coupled_fir<N>(c, d.tab.cpad + crow, xrow, round, p, theta, lf);
       rotate<N, -1>(x, y, theta);
     }
     fft<N, false>(x, y, lxy, tw, t);
@@ -81,7 +93,7 @@ __device__ __forceinline__ void fwd_item(TeamCtx& c, const Inst& d, int sub, uns
   // ---- final GVD, recombination, inverse size-N DFT, kept samples
   t = opaque_tid();
   apply_diag<N, false>(x, y, d.tab.h_last + (size_t)me * N, t);
-  subband_to_polyphase<N>(c, xs, round0 + fwd_rounds(d.steps, DUAL) - 1u, t, x, y);
+  subband_to_polyphase<N>(c, xs, round0 + fwd_rounds(d.steps, dual_rounds<N, DUAL>()) - 1u, t, x, y);
   fft<N, true>(x, y, lxy, tw, t);
   float2* out_x = d.out + (size_t)inst * 2 * T;
   scatter_block<N>(out_x, out_x + T, blk, d.hop, d.n_ov, T, nsb, me, t, x, y);
@@ -107,7 +119,7 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void fwd_kernel(FwdArgs 
   c.ctl = a.ctl;
   c.tab = &a.inst.tab;
   const int nsb = c.nsb;
-  const unsigned rounds_per_item = fwd_rounds(a.inst.steps, DUAL);
+  const unsigned rounds_per_item = fwd_rounds(a.inst.steps, dual_rounds<N, DUAL>());
   uint64_t* xs_team = a.xspec + (size_t)c.team * 2 * nsb * 4 * N;
   uint64_t* xp_team = a.xp + (size_t)c.team * 2 * nsb * 2 * N;
   const unsigned first = epoch_begin(a.epoch + c.team, &epoch_word);

@@ -45,9 +45,9 @@ struct Inst {
   Tables tab;
 };
 
-// Exchange rounds of one block: input DEMUX, one per filter and step, output MUX.
-__host__ __device__ inline unsigned fwd_rounds(int steps, bool dual) {
-  return (unsigned)steps * (dual ? 2u : 1u) + 2u;
+// Exchange rounds of one block: input DEMUX, per_step per step, output MUX.
+__host__ __device__ inline unsigned fwd_rounds(int steps, unsigned per_step) {
+  return (unsigned)steps * per_step + 2u;
 }
 
 // Everything a single-plan forward launch needs.

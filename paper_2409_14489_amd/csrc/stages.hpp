@@ -222,6 +222,49 @@ __device__ __forceinline__ void fir_row_fixed(const float* cur, int start, const
   }
 }
 
+// acc[q] += the filter of row `cur` (LDS, circularly extended) with the
+// member's coefficient row cl (8 n_chunks taps, zero padded) at outputs
+// start + q, q < QB: compile-time taps up to 32 (the window read once), a
+// chunk loop beyond.
+template <int QB>
+__device__ __forceinline__ void fir_row(int n_chunks, const float* cur, int start, const float* __restrict__ cl,
+                                        float* acc) {
+  switch (n_chunks) {  // up to 32 taps: compile-time taps, window read once
+    case 1: fir_row_fixed<1, QB>(cur, start, cl, acc); break;
+    case 2: fir_row_fixed<2, QB>(cur, start, cl, acc); break;
+    case 3: fir_row_fixed<3, QB>(cur, start, cl, acc); break;
+    case 4: fir_row_fixed<4, QB>(cur, start, cl, acc); break;
+    default: {
+      float win[QB + kTapChunk];
+      load_row4<QB + kTapChunk, 0>(cur, start, win);
+      // the chunk's 8 coefficients, fetched one chunk ahead
+      float cf[kTapChunk];
+#pragma unroll
+      for (int tt = 0; tt < kTapChunk; ++tt) cf[tt] = cl[kTapChunk * (n_chunks - 1) + tt];
+      for (int ch = n_chunks - 1; ch >= 0; --ch) {
+        float cf_next[kTapChunk];
+        const int ch_next = ch > 0 ? ch - 1 : 0;
+#pragma unroll
+        for (int tt = 0; tt < kTapChunk; ++tt) cf_next[tt] = cl[kTapChunk * ch_next + tt];
+#pragma unroll
+        for (int tt = 0; tt < kTapChunk; ++tt) {
+#pragma unroll
+          for (int q = 0; q < QB; ++q)
+            acc[q] = fmaf(cf[tt], win[q - tt + kTapChunk - 1], acc[q]);
+        }
+        if (ch > 0) {
+#pragma unroll
+          for (int i = 0; i < QB; ++i) win[i] = win[i + kTapChunk];
+          start += kTapChunk;
+          load_row4<kTapChunk, QB>(cur, start + QB, win);
+        }
+#pragma unroll
+        for (int tt = 0; tt < kTapChunk; ++tt) cf[tt] = cf_next[tt];
+      }
+    }
+  }
+}
+
 // Coupled intensity filter of eq. (15) for member `me`, circular over N':
 //   out[k] = sum_l sum_tau crow[l][tau] in_l[(k - tau + nc) mod N'],
 // crow = the member's coefficient rows ([n_sb][8 n_chunks], zero padded).
@@ -275,40 +318,7 @@ __device__ __forceinline__ void coupled_fir(const TeamCtx& c, const float* __res
       uint64_t w[QB];
       if (more) xissue<QB>(nrow + NT * QB * g, t, NT, w);  // in flight during the filter
       int start = t * RR + g * QB;  // = t RR + g QB + tap_pad - 8 n_chunks
-      switch (c.n_chunks) {  // up to 32 taps: compile-time taps, window read once
-        case 1: fir_row_fixed<1, QB>(cur, start, cl, acc + g * QB); break;
-        case 2: fir_row_fixed<2, QB>(cur, start, cl, acc + g * QB); break;
-        case 3: fir_row_fixed<3, QB>(cur, start, cl, acc + g * QB); break;
-        case 4: fir_row_fixed<4, QB>(cur, start, cl, acc + g * QB); break;
-        default: {
-          float win[QB + kTapChunk];
-          load_row4<QB + kTapChunk, 0>(cur, start, win);
-          // the chunk's 8 coefficients, fetched one chunk ahead
-          float cf[kTapChunk];
-#pragma unroll
-          for (int tt = 0; tt < kTapChunk; ++tt) cf[tt] = cl[kTapChunk * (c.n_chunks - 1) + tt];
-          for (int ch = c.n_chunks - 1; ch >= 0; --ch) {
-            float cf_next[kTapChunk];
-            const int ch_next = ch > 0 ? ch - 1 : 0;
-#pragma unroll
-            for (int tt = 0; tt < kTapChunk; ++tt) cf_next[tt] = cl[kTapChunk * ch_next + tt];
-#pragma unroll
-            for (int tt = 0; tt < kTapChunk; ++tt) {
-#pragma unroll
-              for (int q = 0; q < QB; ++q)
-                acc[g * QB + q] = fmaf(cf[tt], win[q - tt + kTapChunk - 1], acc[g * QB + q]);
-            }
-            if (ch > 0) {
-#pragma unroll
-              for (int i = 0; i < QB; ++i) win[i] = win[i + kTapChunk];
-              start += kTapChunk;
-              load_row4<kTapChunk, QB>(cur, start + QB, win);
-            }
-#pragma unroll
-            for (int tt = 0; tt < kTapChunk; ++tt) cf[tt] = cf_next[tt];
-          }
-        }
-      }
+      fir_row<QB>(c.n_chunks, cur, start, cl, acc + g * QB);
       if (more) {  // this part of the next row into the other buffer (last read before the previous barrier)
         float v[QB];
         xcomplete<QB>(nrow + NT * QB * g, t, NT, tag, c.ctl, w, v);
@@ -324,6 +334,113 @@ __device__ __forceinline__ void coupled_fir(const TeamCtx& c, const float* __res
   __syncthreads();
 #pragma unroll
   for (int o = 0; o < RR; ++o) out[o] = th[pad_r(t + NT * o)];
+}
+
+// The two filters of the dual-polarisation NLPR (eqs. (20)-(21)) in one
+// exchange round: theta over the rows p_l = |x_l|^2 + |y_l|^2 with the
+// coefficient rows crow, phi over d_l = |x_l|^2 - |y_l|^2 with drow (both
+// [n_sb][8 n_chunks], zero padded).  Member l's two rows travel together in
+// the round's slot (p at 2 N' l, d at 2 N' l + N'), so the filter costs one
+// exchange latency instead of two.  LDS: the p rows double buffered at lf,
+// the d rows at lf + 2 PB, the output staging at lf + 4 PB.  DualFir<N>::fits
+// takes it where that fits the kernel's LDS and N' >= 4096: below, the
+// second row set pushes the kernel to one wave per SIMD, and two rounds at
+// two waves per SIMD are the better trade.  (At N' = 4096 the dual forward of
+// the 5-channel workload went from 432 to 421 us.)
+template <int N>
+struct DualFir {
+  static constexpr bool fits = N >= 4096 && 4 * NlprLds<N>::PB + NlprLds<N>::TH <= lds_floats<N>();
+};
+
+template <int N>
+__device__ __forceinline__ void coupled_fir_dual(const TeamCtx& c, const float* __restrict__ crow,
+                                                const float* __restrict__ drow, uint64_t* xrow, unsigned tag,
+                                                const float (&own_p)[FftShape<N>::RR],
+                                                const float (&own_d)[FftShape<N>::RR],
+                                                float (&theta)[FftShape<N>::RR], float (&phi)[FftShape<N>::RR],
+                                                float* lf) {
+  constexpr int RR = FftShape<N>::RR, NT = FftShape<N>::NT;
+  constexpr int PB = NlprLds<N>::PB;
+  static_assert(DualFir<N>::fits, "LDS of the one-round dual filter");
+  const int t = opaque_tid();
+  const int nsb = c.nsb, me = c.me, nc = c.nc;
+  const int tap_pad = kTapChunk * c.n_chunks;
+  const int hl = tap_pad - 1 - nc;
+  float* th = lf + 4 * PB;
+
+  if (nsb > 1) {
+    uint64_t* mine = xrow + (size_t)me * 2 * N;
+#pragma unroll
+    for (int o = 0; o < RR; ++o) xput(mine + t + NT * o, own_p[o], tag);
+#pragma unroll
+    for (int o = 0; o < RR; ++o) xput(mine + N + t + NT * o, own_d[o], tag);
+  }
+  __syncthreads();  // the LDS rows alias the FFT exchange buffers
+  stage_row<N, RR, NT>(lf, own_p, t, hl, nc);
+  stage_row<N, RR, NT>(lf + 2 * PB, own_d, t, hl, nc);
+  __syncthreads();
+
+  constexpr int QB = RR < 8 ? RR : 8;
+  constexpr int G = RR / QB;
+  float ap[RR], ad[RR];
+#pragma unroll
+  for (int q = 0; q < RR; ++q) {
+    ap[q] = 0.0f;
+    ad[q] = 0.0f;
+  }
+  for (int j = 0; j < nsb; ++j) {  // rows me, me + 1, ... (mod n_sb), as in coupled_fir
+    const float* cur_p = lf + (j & 1) * PB;
+    const float* cur_d = lf + (2 + (j & 1)) * PB;
+    float* nxt_p = lf + ((j + 1) & 1) * PB;
+    float* nxt_d = lf + (2 + ((j + 1) & 1)) * PB;
+    const int l = me + j < nsb ? me + j : me + j - nsb;
+    const int ln = l + 1 < nsb ? l + 1 : 0;
+    const bool more = j + 1 < nsb;
+    const uint64_t* nrow = xrow + (size_t)ln * 2 * N;
+    const float* cl = uniform_ptr(crow + (size_t)l * tap_pad);
+    const float* dl = uniform_ptr(drow + (size_t)l * tap_pad);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      // one row's words in flight at a time: the next p row's during this
+      // p filter, the next d row's during this d filter
+      const int start = t * RR + g * QB;
+      {
+        uint64_t w[QB];
+        if (more) xissue<QB>(nrow + NT * QB * g, t, NT, w);
+        fir_row<QB>(c.n_chunks, cur_p, start, cl, ap + g * QB);
+        if (more) {
+          float v[QB];
+          xcomplete<QB>(nrow + NT * QB * g, t, NT, tag, c.ctl, w, v);
+          stage_row<N, QB, NT>(nxt_p, v, t + NT * QB * g, hl, nc);
+        }
+      }
+      {
+        uint64_t w[QB];
+        if (more) xissue<QB>(nrow + N + NT * QB * g, t, NT, w);
+        fir_row<QB>(c.n_chunks, cur_d, start, dl, ad + g * QB);
+        if (more) {
+          float v[QB];
+          xcomplete<QB>(nrow + N + NT * QB * g, t, NT, tag, c.ctl, w, v);
+          stage_row<N, QB, NT>(nxt_d, v, t + NT * QB * g, hl, nc);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // block mapping (t RR + q) -> owned positions (t + NT o), one row after the other
+#pragma unroll
+  for (int q = 0; q < RR; q += 4)
+    *reinterpret_cast<float4*>(th + pad_r(t * RR + q)) = make_float4(ap[q], ap[q + 1], ap[q + 2], ap[q + 3]);
+  __syncthreads();
+#pragma unroll
+  for (int o = 0; o < RR; ++o) theta[o] = th[pad_r(t + NT * o)];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < RR; q += 4)
+    *reinterpret_cast<float4*>(th + pad_r(t * RR + q)) = make_float4(ad[q], ad[q + 1], ad[q + 2], ad[q + 3]);
+  __syncthreads();
+#pragma unroll
+  for (int o = 0; o < RR; ++o) phi[o] = th[pad_r(t + NT * o)];
 }
 
 // The coupled filter of eq. (15) in the frequency domain (the paper's form,
