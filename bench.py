@@ -982,6 +982,10 @@ def headline(result):
         line["cfg1"] = {"value": c1["value"], "ms_per_run": c1["ms_per_run"],
                         "parity_rel_l2": c1.get("parity_rel_l2"),
                         "cpu_baseline": (c1.get("cpu_baseline") or {}).get("value")}
+    cv = result.get("cover")
+    if cv:
+        line["cover"] = {"value": cv["value"], "ms_per_run": cv["ms_per_run"], "block_sb": cv["covering"]["block_sb"],
+                         "overlap": cv["covering"]["overlap"]}
     b = result.get("batched")
     if b:
         line["batched"] = {"value": b["value"], "speedup_vs_separate": b["speedup_vs_separate"],
