@@ -381,6 +381,8 @@ __global__ __launch_bounds__(kColThreads) void st_intensity_kernel(const float2*
   for (int k = 0; k < N2; ++k) dst[kRow * k] = p[k];
 }
 
+typedef float fir_v4 __attribute__((ext_vector_type(4)));
+
 // Coupled filter of eq. (15), circular over N':
 //   theta_i[n] = sum_l sum_tau C_s[i][l][tau] p_l[(n - tau + nc) mod N'].
 // A workgroup filters kFirOut consecutive n of one block for every subband i;
@@ -395,10 +397,10 @@ __global__ __launch_bounds__(kColThreads) void st_intensity_kernel(const float2*
 constexpr int kFirQ = 4;
 constexpr int kFirOut = 256 * kFirQ;
 
-__host__ __device__ inline int fir_row_width(int tap_pad) { return kFirOut + tap_pad - 1; }
-__host__ inline size_t fir_lds_bytes(int nsb, int tap_pad) {
-  return sizeof(float) * (size_t)nsb * fir_row_width(tap_pad);
-}
+// LDS row width in float4: the window of kFirOut + tap_pad - 1 samples from
+// the float4 group that holds its first sample (shift < 4)
+__host__ __device__ inline int fir_row_w4(int tap_pad) { return (kFirOut + tap_pad + 6) / 4; }
+__host__ inline size_t fir_lds_bytes(int nsb, int tap_pad) { return 16 * (size_t)nsb * fir_row_w4(tap_pad); }
 
 // NCH: the number of 8-tap chunks when known at compile time (1 .. 4, up to
 // 32 taps), else 0.
@@ -407,8 +409,8 @@ __global__ __launch_bounds__(256) void st_fir_kernel(const float* __restrict__ p
                                                      const float* __restrict__ cs, int np, int nc, int tap_pad,
                                                      const StreamBlk* __restrict__ blk, int step) {
   constexpr int nsb = NSB;
-  extern __shared__ float fir_lds[];
-  const int W = fir_row_width(tap_pad);
+  extern __shared__ __align__(16) float fir_lds[];
+  const int w4 = fir_row_w4(tap_pad), W = 4 * w4;
   const int n0 = blockIdx.x * kFirOut;
   size_t arr0 = (size_t)blockIdx.y * nsb;
   if (blk != nullptr) {  // blockIdx.y = entry of the block table; coefficients of step `step`
@@ -419,17 +421,29 @@ __global__ __launch_bounds__(256) void st_fir_kernel(const float* __restrict__ p
     arr0 = 0;
   }
   const int hl = tap_pad - 1 - nc;
-  const int span = kFirOut + tap_pad - 1;
-  for (int l = 0; l < nsb; ++l) {
-    const float* row = pb + (arr0 + l) * np;
-    for (int j = threadIdx.x; j < span; j += 256) {
-      int q = n0 - hl + j;
-      q = q < 0 ? q + np : (q >= np ? q - np : q);
-      fir_lds[l * W + j] = row[q];
+  const int t = threadIdx.x;
+  // row l: fir_lds[l][j] = p_l[(4 g0 + j) mod N'], sample n0 - hl at j = sh;
+  // aligned float4 loads with clamped indices, all issued before the stores
+  const int sh = ((n0 - hl) % 4 + 4) % 4;
+  const int g0 = (n0 - hl - sh) / 4, np4 = np / 4;
+  {
+    constexpr int CNT = (NSB * ((kFirOut + kMaxTaps + 1 + 6) / 4) + 255) / 256;
+    const int nall = nsb * w4;
+    fir_v4 v[CNT];
+#pragma unroll
+    for (int c = 0; c < CNT; ++c) {
+      const int idx = t + 256 * c < nall ? t + 256 * c : nall - 1;
+      const int l = idx / w4;
+      int g = g0 + idx - l * w4;
+      g = g < 0 ? g + np4 : (g >= np4 ? g - np4 : g);
+      v[c] = reinterpret_cast<const fir_v4*>(pb + (arr0 + l) * np)[g];
     }
+    fir_v4* lv = reinterpret_cast<fir_v4*>(fir_lds);
+#pragma unroll
+    for (int c = 0; c < CNT; ++c)
+      if (t + 256 * c < nall) lv[t + 256 * c] = v[c];
   }
   __syncthreads();
-  const int t = threadIdx.x;
   float acc[kMaxSubbands][kFirQ];
 #pragma unroll
   for (int i = 0; i < kMaxSubbands; ++i)
@@ -437,7 +451,7 @@ __global__ __launch_bounds__(256) void st_fir_kernel(const float* __restrict__ p
     for (int q = 0; q < kFirQ; ++q) acc[i][q] = 0.0f;
   const int n_chunks = NCH > 0 ? NCH : tap_pad / kTapChunk;
   for (int l = 0; l < nsb; ++l) {
-    const float* tl = fir_lds + l * W + t * kFirQ + tap_pad - 1 - (kTapChunk - 1);
+    const float* tl = fir_lds + l * W + sh + t * kFirQ + tap_pad - 1 - (kTapChunk - 1);
 #pragma unroll
     for (int ch = 0; ch < (NCH > 0 ? NCH : n_chunks); ++ch) {
       // taps tau = 8 ch + u use win[q + 7 - u] for output q
@@ -463,6 +477,144 @@ __global__ __launch_bounds__(256) void st_fir_kernel(const float* __restrict__ p
     if (i < nsb)
       *reinterpret_cast<float4*>(th + (arr0 + i) * np + n0 + t * kFirQ) =
           make_float4(acc[i][0], acc[i][1], acc[i][2], acc[i][3]);
+}
+
+// The same filter on the matrix cores (FP32 MFMA, 16x16x4), for up to 32
+// taps.  With R = 16 / NSB, the 16 rows of a tile are R consecutive outputs
+// of each subband (row m = R i + r; rows from NSB R on are idle) and its 16
+// columns step the output position by R, so a tile holds
+// theta_i[nb + R q + r], q < 16.  Over the window index u = r + TAPS - 1 - tau,
+//   theta_i[nb + R q + r] = sum_l sum_u A_l[R i + r][u] B_l[u][q],
+//   A_l[R i + r][u] = C[i][l][r + TAPS - 1 - u]   (zero off the taps),
+//   B_l[u][q]       = p_l[(nb + R q + u - hl) mod N'],
+// a product over K = R + TAPS - 1 (rounded up to 4) per input row l.  A is
+// the same for every tile of the step and stays in registers (NSB K / 4 per
+// lane); B is read from the LDS rows.  FP32 MFMA does twice the
+// multiply-adds per clock of the unpacked vector ALU that bounds the kernel
+// above; the zero corners of the Toeplitz A cost (R + TAPS - 1) / TAPS of the
+// direct form.  Operand layouts of v_mfma_f32_16x16x4f32 for lane j:
+// A[j mod 16][j / 16], B[j / 16][j mod 16], D[4 (j / 16) + e][j mod 16], e < 4.
+template <int NSB>
+struct FirMfma {
+  static constexpr int R = 16 / NSB;               // outputs per subband in a tile row group
+  static constexpr int TILE = 16 * R;              // output positions per tile
+  static constexpr int TW = (1024 + 4 * TILE - 1) / (4 * TILE);  // tiles per wave
+  static constexpr int OUT = 4 * TW * TILE;        // output positions per workgroup (4 waves)
+};
+__host__ inline int fir_mfma_out(int nsb) { return 4 * ((1024 + 64 * (16 / nsb) - 1) / (64 * (16 / nsb))) * 16 * (16 / nsb); }
+template <int NSB, int NCH>
+struct FirMfmaShape {
+  static constexpr int TAPS = kTapChunk * NCH;
+  static constexpr int KP = (FirMfma<NSB>::R + TAPS - 1 + 3) & ~3;  // window per row, in k-steps of 4
+  static constexpr int S = KP / 4;
+  static constexpr int W4 = (FirMfma<NSB>::OUT + KP + 3 + 3) / 4;  // LDS row width in float4 (3 for the shift)
+  static constexpr int CNT = (NSB * W4 + 255) / 256;               // float4 loads per thread
+};
+__host__ inline size_t fir_mfma_lds_bytes(int nsb, int tap_pad) {
+  const int R = 16 / nsb, kp = (R + tap_pad - 1 + 3) & ~3;
+  const int w4 = (fir_mfma_out(nsb) + kp + 6) / 4;
+  return 16 * (size_t)256 * ((nsb * w4 + 255) / 256);
+}
+
+template <int NSB, int NCH>
+__global__ __launch_bounds__(256) void st_fir_mfma_kernel(const float* __restrict__ pb, float* __restrict__ th,
+                                                          const float* __restrict__ cs, int np, int nc,
+                                                          const StreamBlk* __restrict__ blk, int step) {
+  using F = FirMfma<NSB>;
+  using G = FirMfmaShape<NSB, NCH>;
+  constexpr int R = F::R, TAPS = G::TAPS, S = G::S, W4 = G::W4, OUT = F::OUT;
+  extern __shared__ float4 fir_lds4[];
+  float* fir_lds = reinterpret_cast<float*>(fir_lds4);
+  const int n0 = blockIdx.x * OUT;
+  size_t arr0 = (size_t)blockIdx.y * NSB;
+  if (blk != nullptr) {  // blockIdx.y = entry of the block table; coefficients of step `step`
+    const StreamBlk& e = blk[blockIdx.y];
+    pb = e.pb;
+    th = e.th;
+    cs = e.cpad + (size_t)step * NSB * NSB * TAPS;
+    arr0 = 0;
+  }
+  const int t = threadIdx.x;
+  const int hl = TAPS - 1 - nc;
+  // this lane's A entries: row m = lane mod 16, window index u = 4 s + lane / 16
+  const int lane = t & 63, lq = lane & 15, kq = lane >> 4;  // lq: row of A, column of B and D
+  const int ai = lq / R, ar = lq - (lq / R) * R;
+  float a[NSB][S];
+#pragma unroll
+  for (int l = 0; l < NSB; ++l)
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int tau = ar + TAPS - 1 - (4 * s + kq);
+      const bool on = lq < NSB * R && tau >= 0 && tau < TAPS;
+      // a clamped, always valid index, so that the loads carry no branch
+      const int ic = ai < NSB ? ai : NSB - 1, tc = tau < 0 ? 0 : (tau < TAPS ? tau : TAPS - 1);
+      const float cv = cs[((size_t)ic * NSB + l) * TAPS + tc];
+      a[l][s] = on ? cv : 0.0f;
+    }
+  // LDS row l holds p_l[(4 g0 + j) mod N'], j < 4 W4, read as aligned float4
+  // (N' is a multiple of 4), all loads in flight at once; sample n0 - hl of
+  // the window is at j = sh.
+  const int sh = ((n0 - hl) % 4 + 4) % 4;
+  const int g0 = (n0 - hl - sh) / 4, np4 = np / 4;
+  // (the slots past NSB W4 take more of the last row, so that every thread
+  // has the same loads, all without a branch; g0 + W4 + 255 < 2 np4)
+  {
+    fir_v4 v[G::CNT];  // loaded first, stored after: the stores must not hold the loads back
+#pragma unroll
+    for (int c = 0; c < G::CNT; ++c) {
+      const int idx = t + 256 * c;
+      const int l = idx / W4 < NSB ? idx / W4 : NSB - 1;
+      int g = g0 + idx - l * W4;
+      g = g < 0 ? g + np4 : (g >= np4 ? g - np4 : g);
+      v[c] = reinterpret_cast<const fir_v4*>(pb + (arr0 + l) * np)[g];
+    }
+    fir_v4* lv = reinterpret_cast<fir_v4*>(fir_lds4);
+#pragma unroll
+    for (int c = 0; c < G::CNT; ++c) lv[t + 256 * c] = v[c];
+  }
+  __syncthreads();
+  const int wave = t >> 6;
+  fir_v4 res[F::TW];
+#pragma unroll
+  for (int tw = 0; tw < F::TW; ++tw) {
+    const int off = (wave * F::TW + tw) * F::TILE;
+    fir_v4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;  // two chains, even and odd k-steps
+#pragma unroll
+    for (int l = 0; l < NSB; ++l) {
+      const float* b = fir_lds + l * 4 * W4 + sh + off + R * lq + kq;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        if (s & 1)
+          acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[l][s], b[4 * s], acc1, 0, 0, 0);
+        else
+          acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[l][s], b[4 * s], acc0, 0, 0, 0);
+      }
+    }
+    res[tw] = acc0 + acc1;
+  }
+  __syncthreads();  // every wave is done with the rows; the outputs take their place
+  float* out = fir_lds;  // [NSB][OUT]
+#pragma unroll
+  for (int tw = 0; tw < F::TW; ++tw) {
+    const int off = (wave * F::TW + tw) * F::TILE;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int m = 4 * kq + e;
+      if (m < NSB * R) {
+        const int i = m / R, r = m - (m / R) * R;
+        out[i * OUT + off + R * lq + r] = res[tw][e];
+      }
+    }
+  }
+  __syncthreads();
+  constexpr int Q4 = OUT / 4;
+  for (int idx = t; idx < NSB * Q4; idx += 256) {
+    const int i = idx / Q4, c4 = idx - (idx / Q4) * Q4;
+    const int n = n0 + 4 * c4;
+    if (n < np)
+      *reinterpret_cast<float4*>(th + (arr0 + i) * np + n) =
+          *reinterpret_cast<const float4*>(out + i * OUT + 4 * c4);
+  }
 }
 
 // Rotation of eq. (3): inverse column pass of src, x, y *= exp(-j theta_i[n]),
@@ -827,8 +979,11 @@ __global__ __launch_bounds__(kColThreads) void st_adj_comm_kernel(const float2* 
 // samples (pairs x shares <= 256); the shares are added in LDS in a fixed
 // order.  Per 4 samples a thread reads theta_bar of every subband as one
 // 128-bit word (the same for all lanes of a share) and 4 intensities.  LDS
-// (dynamic): p rows with a halo of nc each side (row width rounded up to 4
-// floats), theta_bar rows, the share partials.
+// (dynamic): p rows with a halo of nc each side, read as aligned float4 from
+// the float4 group holding sample n0 - nc (row width rounded up to 4 floats,
+// the window starting at the shift psh < 4), theta_bar rows, the share
+// partials.  Every row load is issued before the first LDS store, with
+// clamped (always valid) indices, so the loads carry no branch and wait once.
 constexpr int kCgOut = 512;
 
 __host__ __device__ inline int cg_shares(int npair) {
@@ -836,7 +991,8 @@ __host__ __device__ inline int cg_shares(int npair) {
   while (2 * sh * npair <= 256 && sh < 64) sh *= 2;
   return sh;
 }
-__host__ __device__ inline int cg_pw(int n_taps) { return (kCgOut + n_taps - 1 + 3) & ~3; }
+__host__ __device__ inline int cg_pw4(int n_taps) { return (kCgOut + n_taps + 6) / 4; }  // p row, float4
+__host__ __device__ inline int cg_pw(int n_taps) { return 4 * cg_pw4(n_taps); }
 __host__ inline size_t cg_lds_bytes(int nsb, int n_taps) {
   const int npair = nsb * n_taps;
   const int sh = npair > 256 ? 1 : cg_shares(npair);
@@ -857,16 +1013,36 @@ __global__ __launch_bounds__(256) void st_cgrad_kernel(const float* __restrict__
   const int n0 = blockIdx.x * kCgOut;
   const size_t arr0 = (size_t)blockIdx.y * nsb;
   const int t = threadIdx.x;
-  const int span = kCgOut + 2 * nc;
-  for (int l = 0; l < nsb; ++l) {
-    const float* prow = pb + (arr0 + l) * np;
-    for (int j = t; j < span; j += 256) {
-      int q = n0 - nc + j;
-      q = q < 0 ? q + np : (q >= np ? q - np : q);
-      ptile[l * pw + j] = prow[q];
+  // p row l: ptile[l][j] = p_l[(4 pg0 + j) mod N'], sample n0 - nc at j = psh
+  const int psh = ((n0 - nc) % 4 + 4) % 4;
+  const int pg0 = (n0 - nc - psh) / 4, np4 = np / 4, pw4 = pw / 4;
+  {
+    constexpr int PCNT = (NSB * ((kCgOut + kMaxTaps + 6) / 4) + 255) / 256;
+    constexpr int TCNT = (NSB * (kCgOut / 4) + 255) / 256;
+    const int pn = nsb * pw4;
+    fir_v4 pv[PCNT], tv[TCNT];
+#pragma unroll
+    for (int c = 0; c < PCNT; ++c) {
+      const int idx = t + 256 * c < pn ? t + 256 * c : pn - 1;
+      const int l = idx / pw4;
+      int g = pg0 + idx - l * pw4;
+      g = g < 0 ? g + np4 : (g >= np4 ? g - np4 : g);
+      pv[c] = reinterpret_cast<const fir_v4*>(pb + (arr0 + l) * np)[g];
     }
-    const float* trow = tbar + (arr0 + l) * np + n0;
-    for (int j = t; j < kCgOut; j += 256) ttile[l * kCgOut + j] = trow[j];
+#pragma unroll
+    for (int c = 0; c < TCNT; ++c) {
+      const int idx = t + 256 * c < nsb * (kCgOut / 4) ? t + 256 * c : nsb * (kCgOut / 4) - 1;
+      const int l = idx / (kCgOut / 4);
+      tv[c] = reinterpret_cast<const fir_v4*>(tbar + (arr0 + l) * np + n0)[idx - l * (kCgOut / 4)];
+    }
+    fir_v4* p4 = reinterpret_cast<fir_v4*>(ptile);
+    fir_v4* q4 = reinterpret_cast<fir_v4*>(ttile);
+#pragma unroll
+    for (int c = 0; c < PCNT; ++c)
+      if (t + 256 * c < pn) p4[t + 256 * c] = pv[c];
+#pragma unroll
+    for (int c = 0; c < TCNT; ++c)
+      if (t + 256 * c < nsb * (kCgOut / 4)) q4[t + 256 * c] = tv[c];
   }
   __syncthreads();
   const int npair = nsb * n_taps;
@@ -880,8 +1056,8 @@ __global__ __launch_bounds__(256) void st_cgrad_kernel(const float* __restrict__
     const int pr = wide ? wi : wi % npair;
     const int sp = wide ? 0 : wi / npair;
     const int l = pr / n_taps, tau = pr - (pr / n_taps) * n_taps;
-    // p_l[n - tau + nc] sits at ptile[l][n - n0 - tau + 2 nc]
-    const float* prow = ptile + l * pw + 2 * nc - tau;
+    // p_l[n - tau + nc] sits at ptile[l][psh + n - n0 - tau + 2 nc]
+    const float* prow = ptile + l * pw + psh + 2 * nc - tau;
     float acc[kMaxSubbands];
 #pragma unroll
     for (int i = 0; i < kMaxSubbands; ++i) acc[i] = 0.0f;
@@ -1055,28 +1231,32 @@ bool ok_launch() { return hipGetLastError() == hipSuccess; }
 // The coupled-filter kernels take the subband count as a template argument,
 // so their per-subband loops have no branches and their loads batch.
 template <int NSB>
-void fir_t(dim3 grid, size_t lds, hipStream_t s, const float* pb, float* th, const float* cs, int np, int nc,
-           int tap_pad, const StreamBlk* blk, int step) {
-  switch (tap_pad / kTapChunk) {  // compile-time chunk counts up to 32 taps
-    case 1: st_fir_kernel<NSB, 1><<<grid, 256, lds, s>>>(pb, th, cs, np, nc, tap_pad, blk, step); break;
-    case 2: st_fir_kernel<NSB, 2><<<grid, 256, lds, s>>>(pb, th, cs, np, nc, tap_pad, blk, step); break;
-    case 3: st_fir_kernel<NSB, 3><<<grid, 256, lds, s>>>(pb, th, cs, np, nc, tap_pad, blk, step); break;
-    case 4: st_fir_kernel<NSB, 4><<<grid, 256, lds, s>>>(pb, th, cs, np, nc, tap_pad, blk, step); break;
-    default: st_fir_kernel<NSB, 0><<<grid, 256, lds, s>>>(pb, th, cs, np, nc, tap_pad, blk, step);
+void fir_t(int ny, hipStream_t s, const float* pb, float* th, const float* cs, int np, int nc, int tap_pad,
+           const StreamBlk* blk, int step) {
+  // up to 32 taps: the matrix-core kernel, taps a compile-time count
+  const dim3 gm((np + FirMfma<NSB>::OUT - 1) / FirMfma<NSB>::OUT, ny);
+  const size_t lm = fir_mfma_lds_bytes(NSB, tap_pad);
+  switch (tap_pad / kTapChunk) {
+    case 1: st_fir_mfma_kernel<NSB, 1><<<gm, 256, lm, s>>>(pb, th, cs, np, nc, blk, step); break;
+    case 2: st_fir_mfma_kernel<NSB, 2><<<gm, 256, lm, s>>>(pb, th, cs, np, nc, blk, step); break;
+    case 3: st_fir_mfma_kernel<NSB, 3><<<gm, 256, lm, s>>>(pb, th, cs, np, nc, blk, step); break;
+    case 4: st_fir_mfma_kernel<NSB, 4><<<gm, 256, lm, s>>>(pb, th, cs, np, nc, blk, step); break;
+    default:
+      st_fir_kernel<NSB, 0><<<dim3(np / kFirOut, ny), 256, fir_lds_bytes(NSB, tap_pad), s>>>(pb, th, cs, np, nc,
+                                                                                          tap_pad, blk, step);
   }
 }
-bool launch_fir(int nsb, dim3 grid, hipStream_t s, const float* pb, float* th, const float* cs, int np, int nc,
+bool launch_fir(int nsb, int ny, hipStream_t s, const float* pb, float* th, const float* cs, int np, int nc,
                 int tap_pad, const StreamBlk* blk = nullptr, int step = 0) {
-  const size_t lds = fir_lds_bytes(nsb, tap_pad);
   switch (nsb) {
-    case 1: fir_t<1>(grid, lds, s, pb, th, cs, np, nc, tap_pad, blk, step); break;
-    case 2: fir_t<2>(grid, lds, s, pb, th, cs, np, nc, tap_pad, blk, step); break;
-    case 3: fir_t<3>(grid, lds, s, pb, th, cs, np, nc, tap_pad, blk, step); break;
-    case 4: fir_t<4>(grid, lds, s, pb, th, cs, np, nc, tap_pad, blk, step); break;
-    case 5: fir_t<5>(grid, lds, s, pb, th, cs, np, nc, tap_pad, blk, step); break;
-    case 6: fir_t<6>(grid, lds, s, pb, th, cs, np, nc, tap_pad, blk, step); break;
-    case 7: fir_t<7>(grid, lds, s, pb, th, cs, np, nc, tap_pad, blk, step); break;
-    case 8: fir_t<8>(grid, lds, s, pb, th, cs, np, nc, tap_pad, blk, step); break;
+    case 1: fir_t<1>(ny, s, pb, th, cs, np, nc, tap_pad, blk, step); break;
+    case 2: fir_t<2>(ny, s, pb, th, cs, np, nc, tap_pad, blk, step); break;
+    case 3: fir_t<3>(ny, s, pb, th, cs, np, nc, tap_pad, blk, step); break;
+    case 4: fir_t<4>(ny, s, pb, th, cs, np, nc, tap_pad, blk, step); break;
+    case 5: fir_t<5>(ny, s, pb, th, cs, np, nc, tap_pad, blk, step); break;
+    case 6: fir_t<6>(ny, s, pb, th, cs, np, nc, tap_pad, blk, step); break;
+    case 7: fir_t<7>(ny, s, pb, th, cs, np, nc, tap_pad, blk, step); break;
+    case 8: fir_t<8>(ny, s, pb, th, cs, np, nc, tap_pad, blk, step); break;
     default: return false;
   }
   return ok_launch();
@@ -1144,7 +1324,7 @@ bool wave_step(const StreamArgs& a, const Tables& tb, const float* cpad, int st,
   bool ok = (st == 0 && nsb > 1) ? row<false, true, true>(a, src, work, h, s) : row<true, true, true>(a, src, work, h, s);
   st_intensity_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(work, a.pb, a.tw2, nsb, nullptr);
   ok = ok && ok_launch();
-  ok = ok && launch_fir(nsb, dim3(a.np / kFirOut, a.nb), s, a.pb, theta,
+  ok = ok && launch_fir(nsb, a.nb, s, a.pb, theta,
                         cpad + (size_t)st * nsb * nsb * tap_pad, a.np, n_taps / 2, tap_pad);
   ok = ok && ok_launch();
   st_rotate_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(work, dst, theta, a.tw2, nsb, nullptr);
@@ -1196,7 +1376,7 @@ bool class_step(int nsb, int n_taps, int tap_pad, int step, const StreamBlk* blk
   bool ok = ok_launch();
   st_intensity_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(nullptr, nullptr, nullptr, nsb, blks);
   ok = ok && ok_launch();
-  ok = ok && launch_fir(nsb, dim3(NP / kFirOut, nb), s, nullptr, nullptr, nullptr, NP, n_taps / 2, tap_pad, blks,
+  ok = ok && launch_fir(nsb, nb, s, nullptr, nullptr, nullptr, NP, n_taps / 2, tap_pad, blks,
                         step);
   st_rotate_kernel<N2><<<sb_grid, kColThreads, 0, s>>>(nullptr, nullptr, nullptr, nullptr, nsb, blks);
   return ok && ok_launch();
@@ -1523,7 +1703,7 @@ int bwd_wave(const StreamBwdCall& c, StreamArgs a) {
                                                               nsb);
       ok = ok && ok_launch();
       // p_bar = C^T applied to theta_bar (transposed, tap-reversed rows)
-      ok = ok && launch_fir(nsb, dim3(a.np / kFirOut, a.nb), s, c.tbar(), a.th,
+      ok = ok && launch_fir(nsb, a.nb, s, c.tbar(), a.th,
                             p->d_ctpad + (size_t)st * per_step / n_taps * tap_pad, a.np, n_taps / 2, tap_pad);
       ok = ok && ok_launch();
       ok = ok && launch_cgrad(nsb, cg_grid, s, c.tbar(), a.pb, c.cpart(), a.np, n_taps);

@@ -36,6 +36,18 @@ def test_stream_parity_multiband(n_sb, block_sb):
     assert err < TOL and worst < TOL
 
 
+@pytest.mark.parametrize("n_sb,taps", [(1, 31), (2, 23), (3, 31), (4, 15), (5, 31), (6, 7), (7, 31), (8, 23)])
+def test_stream_parity_matrix_core_filter(n_sb, taps):
+    """The coupled filter on the matrix cores (up to 32 taps) packs 16 / n_sb
+    outputs of every subband into a tile's rows: every subband count, with
+    7 to 31 taps (padded windows of 8 to 32), two steps, a ragged tail."""
+    n = n_sb * 2 ** 14
+    y, ref, hop = case(n_sb, 2 ** 14, n // 8, 2, 0.4, taps, n + 3001, seed=100 + n_sb, rate=n_sb * 64e9)
+    err, worst = rel_l2(y, ref), worst_block_rel_l2(y, ref, hop)
+    print(f"n_sb={n_sb} taps={taps}: rel L2 {err:.3e}, worst block {worst:.3e}")
+    assert err < TOL and worst < TOL
+
+
 @pytest.mark.parametrize("taps", [1, 21, 255])
 def test_stream_parity_tap_counts(taps):
     y, ref, hop = case(2, 2 ** 14, 4096, 2, 0.5, taps, 50000, seed=taps, rate=128e9)
