@@ -111,6 +111,13 @@ FLOPS_PER_2D_SYMBOL = {
 }
 
 
+def long_link_flops_per_2d_symbol(steps):
+    """The operation count per 2D symbol of the long-link workload (5 subbands,
+    N' = 2^17, the same convention as FLOPS_PER_2D_SYMBOL): 1.3e3 at one step
+    to 6.0e4 at 80, linear in the step count in between."""
+    return 1.3e3 + (6.0e4 - 1.3e3) * (steps - 1) / 79.0
+
+
 def algorithmic_flops_per_block(n_sb, n_sub, steps, n_taps):
     """Flops of one overlap-and-save block, by this convention:
     5 n log2 n per complex DFT of size n, 6 per complex multiply, 7 per
@@ -727,6 +734,11 @@ def leg_longlink(args):
                                 "bytes_per_run": moved},
                "min_bytes_frac": 2 * 2 * t_len * 8 / run_s / 1e9 / PEAK_HBM_GBS,
                "snr_db_per_channel": snr, "snr_db_central": snr[len(snr) // 2]}
+        if not edc:  # the method's operation count against the FP32 vector peak
+            fl = long_link_flops_per_2d_symbol(st) * n2d
+            row["flop_roofline"] = {"bound": "alu", "achieved": fl / run_s / 1e12, "peak": PEAK_FP32_TFLOPS,
+                                    "unit": "TFLOP/s", "frac": fl / run_s / 1e12 / PEAK_FP32_TFLOPS,
+                                    "flops_per_2d_symbol": long_link_flops_per_2d_symbol(st)}
         if not edc:
             row["snr_db_central_analytic"] = row.pop("snr_db_central")
             row["snr_db_per_channel_analytic"] = row.pop("snr_db_per_channel")
