@@ -943,22 +943,42 @@ __global__ __launch_bounds__(kColThreads) void st_adj_comm_kernel(const float2* 
     col_inverse<N2>(tw2, n1, b);
     const float2* gc = gt + base + n1;
     float2* vc = vt + base + n1;
+    // Samples in chunks: a chunk's loads all precede its stores.  (Stores
+    // count in the same in-order memory counter as loads, so a load issued
+    // after a store waits for it; sample by sample, every load waited for
+    // the previous sample's store.)
+    constexpr int CH = N2 < 8 ? N2 : 8;
 #pragma unroll
-    for (int k = 0; k < N2; ++k) {
-      float sh, ch;
-      phase_sincos(0.5f * tc[kRow * k], sh, ch);
-      const float2 e = make_float2(-2.0f * sh * sh, -2.0f * sh * ch);  // exp(-j theta) - 1
-      const float2 w = vc[kRow * k], g = gc[kRow * k];
-      const float2 ew = cmulc(w, e);                                   // conj(e) w = v - w
-      const float2 v = cadd(w, ew);
-      const float2 ge = cmulc(g, e);                                   // conj(e) g'
-      const float p2 = 2.0f * pc[kRow * k];
-      const float2 dg = make_float2(fmaf(p2, v.x, ge.x), fmaf(p2, v.y, ge.y));
-      // Im(conj(K g') e v) with e v = w - v = -conj(e) w; Im(conj(dg) K v)
-      const float t1 = -fmaf(a[k].x, ew.y, -a[k].y * ew.x);
-      const float t2 = fmaf(dg.x, b[k].y, -dg.y * b[k].x);
-      acc += (double)t1 - (double)t2;
-      vc[kRow * k] = cadd(g, dg);
+    for (int k0 = 0; k0 < N2; k0 += CH) {
+      float tv[CH], pv[CH];
+      float2 wv[CH], gv[CH];
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {
+        tv[j] = tc[kRow * (k0 + j)];
+        pv[j] = pc[kRow * (k0 + j)];
+        wv[j] = vc[kRow * (k0 + j)];
+        gv[j] = gc[kRow * (k0 + j)];
+      }
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {
+        const int k = k0 + j;
+        float sh, ch;
+        phase_sincos(0.5f * tv[j], sh, ch);
+        const float2 e = make_float2(-2.0f * sh * sh, -2.0f * sh * ch);  // exp(-j theta) - 1
+        const float2 w = wv[j], g = gv[j];
+        const float2 ew = cmulc(w, e);                                   // conj(e) w = v - w
+        const float2 v = cadd(w, ew);
+        const float2 ge = cmulc(g, e);                                   // conj(e) g'
+        const float p2 = 2.0f * pv[j];
+        const float2 dg = make_float2(fmaf(p2, v.x, ge.x), fmaf(p2, v.y, ge.y));
+        // Im(conj(K g') e v) with e v = w - v = -conj(e) w; Im(conj(dg) K v)
+        const float t1 = -fmaf(a[k].x, ew.y, -a[k].y * ew.x);
+        const float t2 = fmaf(dg.x, b[k].y, -dg.y * b[k].x);
+        acc += (double)t1 - (double)t2;
+        wv[j] = cadd(g, dg);
+      }
+#pragma unroll
+      for (int j = 0; j < CH; ++j) vc[kRow * (k0 + j)] = wv[j];
     }
   }
 #pragma unroll
