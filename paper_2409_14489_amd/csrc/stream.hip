@@ -309,16 +309,22 @@ __global__ __launch_bounds__(256) void st_mix_kernel(float2* __restrict__ st, co
     wb = 0;
   }
   float2* base = st + wb * nsb * 2 * np + q;
-  float2 vx[kMaxSubbands], vy[kMaxSubbands];
+  // every load before the first store (a load issued after a store waits for it)
+  float2 vx[kMaxSubbands], vy[kMaxSubbands], pw[kMaxSubbands];
 #pragma unroll
   for (int a = 0; a < kMaxSubbands; ++a) {
     if (a < nsb) {
       vx[a] = base[(size_t)(2 * a) * np];
       vy[a] = base[(size_t)(2 * a + 1) * np];
-      if (!INV) {
-        const float2 pw = poly[(size_t)a * np + q];
-        vx[a] = cmul(vx[a], pw);
-        vy[a] = cmul(vy[a], pw);
+      pw[a] = poly[(size_t)a * np + q];
+    }
+  }
+  if (!INV) {
+#pragma unroll
+    for (int a = 0; a < kMaxSubbands; ++a) {
+      if (a < nsb) {
+        vx[a] = cmul(vx[a], pw[a]);
+        vy[a] = cmul(vy[a], pw[a]);
       }
     }
   }
@@ -335,9 +341,8 @@ __global__ __launch_bounds__(256) void st_mix_kernel(float2* __restrict__ st, co
         }
       }
       if (INV) {
-        const float2 pw = poly[(size_t)c * np + q];
-        sx = cmulc(sx, pw);
-        sy = cmulc(sy, pw);
+        sx = cmulc(sx, pw[c]);
+        sy = cmulc(sy, pw[c]);
       }
       base[(size_t)(2 * c) * np] = sx;
       base[(size_t)(2 * c + 1) * np] = sy;
