@@ -285,6 +285,11 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdAr
   float2* gsv = a.gsave + ((size_t)c.team * nsb + me) * 2 * N;  // reused by every reverse step
   const int last0 = (a.n_ck - 1) * k;  // first step of the last segment
   uint64_t* xs_team = a.xspec + (size_t)c.team * 2 * nsb * 4 * N;
+  // the team's intensity slots (n_sb x N' words each) at the start of the
+  // region the forward kernel's team of the same index uses (2 x n_sb x 2 N'
+  // words): a word of it is only ever written by this team's rounds, which
+  // take their tags from this team's round counter
+  uint64_t* xp_team = a.xp + (size_t)c.team * 2 * nsb * 2 * N;
   const double* phase_km = a.phase + (size_t)me * N;
   const unsigned first = epoch_begin(a.epoch + c.team, &epoch_word);
 
@@ -318,7 +323,7 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdAr
       fft<N, true>(x, y, lxy, tw, t);
       float p[RR], theta[RR];
       intensity<N>(x, y, p);
-      uint64_t* xrow = a.xp + ((size_t)c.team * 2 + (np & 1u)) * nsb * N;
+      uint64_t* xrow = xp_team + (size_t)(np & 1u) * nsb * N;
       coupled_fir<N>(c, a.tab.cpad + ((size_t)(s * nsb + me) * nsb) * tap_pad, xrow, rnd, p, theta, lf);
       ++rnd;
       ++np;
@@ -395,7 +400,7 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT, 2) void bwd_kernel(BwdAr
         intensity<N>(x, y, p);
         // republish p for the coefficient gradient of the other members
         const unsigned tag_p = rnd++;
-        uint64_t* prow = a.xp + ((size_t)c.team * 2 + (np & 1u)) * nsb * N;
+        uint64_t* prow = xp_team + (size_t)(np & 1u) * nsb * N;
         ++np;
         if (nsb > 1) {
 #pragma unroll

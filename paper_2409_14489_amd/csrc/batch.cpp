@@ -425,10 +425,9 @@ struct cbessfm_batch {
   std::vector<void*> allocs;
   unsigned* d_abort = nullptr;
   int* d_err = nullptr;
-  uint64_t* d_xspec = nullptr;
   uint64_t* d_xp = nullptr;
   unsigned* d_epoch = nullptr;
-  size_t xspec_words = 0, xp_words = 0, n_epoch = 0;
+  size_t xp_words = 0, n_epoch = 0;
 };
 
 namespace {
@@ -441,7 +440,6 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
 
 int reset_exchange(cbessfm_batch_t* b) {
   if (hipMemset(b->d_err, 0, sizeof(int)) != hipSuccess || hipMemset(b->d_abort, 0, sizeof(unsigned)) != hipSuccess ||
-      hipMemset(b->d_xspec, 0, b->xspec_words * sizeof(uint64_t)) != hipSuccess ||
       hipMemset(b->d_xp, 0, b->xp_words * sizeof(uint64_t)) != hipSuccess ||
       hipMemset(b->d_epoch, 0, b->n_epoch * sizeof(unsigned)) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
     return CBESSFM_EHIP;
@@ -616,7 +614,7 @@ int cbessfm_batch_create(cbessfm_batch_t** out, const cbessfm_instance* inst, in
     std::vector<Inst> insts;
   };
   std::vector<Built> built;
-  size_t xspec_words = 0, xp_words = 0, n_epoch = 0;
+  size_t xp_words = 0, n_epoch = 0;
   int rc = CBESSFM_OK;
   for (auto& kv : by_np) {
     Built bt;
@@ -642,7 +640,6 @@ int cbessfm_batch_create(cbessfm_batch_t** out, const cbessfm_instance* inst, in
     if (rc) break;
     const int np = 1 << bt.log_np;
     for (size_t tm = 0; tm < bt.s.team_width.size(); ++tm) {
-      xspec_words += (size_t)2 * bt.s.team_width[tm] * 4 * np;
       xp_words += (size_t)2 * bt.s.team_width[tm] * 2 * np;
       ++n_epoch;
     }
@@ -664,10 +661,8 @@ int cbessfm_batch_create(cbessfm_batch_t** out, const cbessfm_instance* inst, in
     if (p) b->allocs.push_back(p);
     return p;
   };
-  b->xspec_words = xspec_words;
   b->xp_words = xp_words;
   b->n_epoch = n_epoch;
-  b->d_xspec = static_cast<uint64_t*>(alloc(std::max<size_t>(1, xspec_words) * sizeof(uint64_t)));
   b->d_xp = static_cast<uint64_t*>(alloc(std::max<size_t>(1, xp_words) * sizeof(uint64_t)));
   b->d_epoch = static_cast<unsigned*>(alloc(std::max<size_t>(1, n_epoch) * sizeof(unsigned)));
   b->d_abort = static_cast<unsigned*>(alloc(sizeof(unsigned)));
@@ -676,7 +671,7 @@ int cbessfm_batch_create(cbessfm_batch_t** out, const cbessfm_instance* inst, in
     cbessfm_batch_destroy(b);
     return ok ? CBESSFM_EHIP : CBESSFM_ENOMEM;
   }
-  size_t xs_off = 0, xp_off = 0, ep_off = 0;
+  size_t xp_off = 0, ep_off = 0;
   long long total_items = 0;
   int total_teams = 0, total_wg = 0;
   double makespan = 0.0, bound = 0.0;
@@ -698,9 +693,7 @@ int cbessfm_batch_create(cbessfm_batch_t** out, const cbessfm_instance* inst, in
       t.first = (int)items.size();
       t.count = (int)s.team_items[tm].size();
       t.epoch_slot = (int)(ep_off + tm);
-      t.xspec_off = (long long)xs_off;
       t.xp_off = (long long)xp_off;
-      xs_off += (size_t)2 * t.width * 4 * np;
       xp_off += (size_t)2 * t.width * 2 * np;
       unsigned rounds = 0;
       for (long long id : s.team_items[tm]) {
@@ -734,7 +727,6 @@ int cbessfm_batch_create(cbessfm_batch_t** out, const cbessfm_instance* inst, in
     L.args.teams = d_teams;
     L.args.items = d_items;
     L.args.epoch = b->d_epoch;
-    L.args.xspec = b->d_xspec;
     L.args.xp = b->d_xp;
     L.args.ctl.abort = b->d_abort;
     L.args.ctl.err = b->d_err;

@@ -28,18 +28,16 @@ __host__ __device__ constexpr unsigned dual_rounds() {
 
 // One overlap-and-save block of one instance, as member c.me of a team.
 // sub = batch entry * nblk + block; the team's exchange rounds for this block
-// are round0 .. round0 + steps + 1.  xs: one of the team's two spectrum slots
-// (n_sb x 4 N' words), used by both the input and the output exchange of this
-// block: the step rounds between them keep the reuse rule of the exchange, and
-// the team's next block takes the other slot.  Keeping to one slot per block
-// halves the exchange memory a block touches, so more of it stays in the L2.
-// xp_team: the team's two slots of intensity rows or spectra (n_sb x 2 N'
-// words each).
+// are round0 .. round0 + fwd_rounds - 1: two for the input DEMUX (one per
+// polarisation), the steps' rounds, two for the output MUX.  Every round goes
+// through xp_team, the team's two slots of n_sb x 2 N' words (intensity rows,
+// or one polarisation's spectra), slot = round & 1, so a block touches
+// 2 n_sb x 2 N' words of exchange memory and more of it stays in the L2.
 // FIR: 0 time-domain coupled filter, 1 frequency domain, 2 as the instance's
 // tables say (batches mixing instances of both kinds).
 template <int N, bool DUAL, int FIR>
-__device__ __forceinline__ void fwd_item(TeamCtx& c, const Inst& d, int sub, unsigned round0, uint64_t* xs,
-                                         uint64_t* xp_team, float* lf) {
+__device__ __forceinline__ void fwd_item(TeamCtx& c, const Inst& d, int sub, unsigned round0, uint64_t* xp_team,
+                                         float* lf) {
   using S = FftShape<N>;
   constexpr int RR = S::RR;
   float4* lxy = reinterpret_cast<float4*>(lf);
@@ -56,7 +54,7 @@ __device__ __forceinline__ void fwd_item(TeamCtx& c, const Inst& d, int sub, uns
   // ---- block input: size-N DFT as N_sb polyphase FFTs + N_sb-point DFT
   gather_block<N, false>(in_x, in_x + T, blk, d.hop, d.n_ov, T, d.boundary, nsb, me, t, x, y);
   fft<N, false>(x, y, lxy, tw, t);
-  polyphase_to_subband<N>(c, xs, round0, t, x, y);
+  polyphase_to_subband_xp<N>(c, xp_team, round0, t, x, y);
 
   // ---- step loop (Fig. "scheme_CB-ESSFM"), spectra in subband order
   for (int s = 0; s < d.steps; ++s) {
@@ -66,7 +64,7 @@ __device__ __forceinline__ void fwd_item(TeamCtx& c, const Inst& d, int sub, uns
     float p[RR], theta[RR];
     intensity<N>(x, y, p);
     const size_t crow = ((size_t)(s * nsb + me) * nsb) * tap_pad;
-    const unsigned round = round0 + 1u + (unsigned)s * dual_rounds<N, DUAL>();
+    const unsigned round = round0 + 2u + (unsigned)s * dual_rounds<N, DUAL>();
     uint64_t* xrow = xp_team + (size_t)(round & 1u) * nsb * 2 * N;
     if constexpr (DUAL) {
       // theta^{x,y} = theta +- phi, phi_i = (1/3) sum_{l != i} C_il (*) (|x_l|^2 - |y_l|^2)
@@ -93,7 +91,7 @@ __device__ __forceinline__ void fwd_item(TeamCtx& c, const Inst& d, int sub, uns
   // ---- final GVD, recombination, inverse size-N DFT, kept samples
   t = opaque_tid();
   apply_diag<N, false>(x, y, d.tab.h_last + (size_t)me * N, t);
-  subband_to_polyphase<N>(c, xs, round0 + fwd_rounds(d.steps, dual_rounds<N, DUAL>()) - 1u, t, x, y);
+  subband_to_polyphase_xp<N>(c, xp_team, round0 + fwd_rounds(d.steps, dual_rounds<N, DUAL>()) - 2u, t, x, y);
   fft<N, true>(x, y, lxy, tw, t);
   float2* out_x = d.out + (size_t)inst * 2 * T;
   scatter_block<N>(out_x, out_x + T, blk, d.hop, d.n_ov, T, nsb, me, t, x, y);
@@ -120,13 +118,11 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void fwd_kernel(FwdArgs 
   c.tab = &a.inst.tab;
   const int nsb = c.nsb;
   const unsigned rounds_per_item = fwd_rounds(a.inst.steps, dual_rounds<N, DUAL>());
-  uint64_t* xs_team = a.xspec + (size_t)c.team * 2 * nsb * 4 * N;
   uint64_t* xp_team = a.xp + (size_t)c.team * 2 * nsb * 2 * N;
   const unsigned first = epoch_begin(a.epoch + c.team, &epoch_word);
   unsigned iter = 0;
   for (int item = c.team; item < a.n_items; item += a.n_teams, ++iter)
-    fwd_item<N, DUAL, FIR>(c, a.inst, item, first + iter * rounds_per_item,
-                           xs_team + (size_t)(iter & 1u) * nsb * 4 * N, xp_team, lf);
+    fwd_item<N, DUAL, FIR>(c, a.inst, item, first + iter * rounds_per_item, xp_team, lf);
   epoch_end(a.epoch + c.team, first, iter * rounds_per_item, c.me);
 }
 
@@ -147,7 +143,6 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void fwd_batch_kernel(Ba
   c.me = wg.y;
   c.team = wg.x;
   c.ctl = a.ctl;
-  uint64_t* xs_team = a.xspec + tm.xspec_off;
   uint64_t* xp_team = a.xp + tm.xp_off;
   unsigned* epoch = a.epoch + tm.epoch_slot;
   const unsigned first = epoch_begin(epoch, &epoch_word);
@@ -157,8 +152,7 @@ __global__ __launch_bounds__(FftShape<(1 << LOGN)>::NT) void fwd_batch_kernel(Ba
     c.n_chunks = d.n_chunks;
     c.nc = d.nc;
     c.tab = &d.tab;
-    fwd_item<N, false, 2>(c, d, it.sub, first + it.round_off, xs_team + (size_t)(k & 1) * c.nsb * 4 * N, xp_team,
-                          lf);
+    fwd_item<N, false, 2>(c, d, it.sub, first + it.round_off, xp_team, lf);
   }
   epoch_end(epoch, first, tm.rounds, c.me);
 }
@@ -397,7 +391,6 @@ int launch_forward(cbessfm_plan_t* p, const void* in, void* out, long long T, in
   const int capacity = dual ? p->team_capacity_dual : p->team_capacity;
   a.n_teams = a.n_items < capacity ? a.n_items : capacity;
   a.epoch = p->d_epoch;
-  a.xspec = p->d_xspec;
   a.xp = p->d_xp;
   a.ctl.abort = p->d_abort;
   a.ctl.err = p->d_err;

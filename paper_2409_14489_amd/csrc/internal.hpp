@@ -45,9 +45,10 @@ struct Inst {
   Tables tab;
 };
 
-// Exchange rounds of one block: input DEMUX, per_step per step, output MUX.
+// Exchange rounds of one forward block: input DEMUX (two, one per
+// polarisation), per_step per step, output MUX (two).
 __host__ __device__ inline unsigned fwd_rounds(int steps, unsigned per_step) {
-  return (unsigned)steps * per_step + 2u;
+  return (unsigned)steps * per_step + 4u;
 }
 
 // Everything a single-plan forward launch needs.
@@ -56,9 +57,9 @@ struct FwdArgs {
   int n_items;        // batch * blocks per batch entry
   int n_teams;        // persistent teams of n_sb workgroups
   unsigned* epoch;    // [teams] exchange rounds completed so far by each team (device)
-  uint64_t* xspec;    // [team_capacity][2 slots][n_sb][4 comps][N']  tagged spectra
-  uint64_t* xp;       // [team_capacity][2 slots][n_sb][2 N']         tagged intensities (N' words) or
-                      // intensity spectra (re then im, 2 N' words) per member
+  uint64_t* xp;       // [team_capacity][2 slots][n_sb][2 N'] tagged words per member: intensity rows
+                      // (N' words; two rows for the dual NLPR), the filter's intensity spectra or one
+                      // polarisation's block spectrum (re then im, 2 N' words)
   XchgCtl ctl;
 };
 
@@ -73,8 +74,7 @@ struct BatchTeam {
   int first, count;    // its items: items[first, first + count)
   unsigned rounds;     // exchange rounds of all its items
   int epoch_slot;      // index into the epoch array
-  long long xspec_off; // word offsets of its exchange buffers
-  long long xp_off;
+  long long xp_off;    // word offset of its exchange slots
 };
 struct BatchArgs {
   const Inst* insts;
@@ -82,7 +82,6 @@ struct BatchArgs {
   const BatchTeam* teams;
   const BatchItem* items;
   unsigned* epoch;
-  uint64_t* xspec;
   uint64_t* xp;
   XchgCtl ctl;
 };

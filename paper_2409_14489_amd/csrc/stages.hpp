@@ -193,6 +193,87 @@ __device__ __forceinline__ void subband_to_polyphase(const TeamCtx& c, uint64_t*
   apply_diag<N, true>(x, y, c.tab->poly_tw + (size_t)c.me * N, t);
 }
 
+// The DEMUX and MUX one polarisation at a time, through the team's two
+// intensity-row slots (n_sb x 2 N' words each; a member's spectrum takes its
+// 2 N' words, real parts then imaginary parts): x in round `round` in slot
+// round & 1, y in round + 1 in the other slot.  A member publishes y only
+// after it has consumed every member's x, which keeps the exchange's reuse
+// rule (two uses of a slot are separated by another round); the two rounds
+// touch n_sb x 2 N' words of the team's memory where one round of both
+// polarisations would need a slot of n_sb x 4 N'.
+template <int N>
+__device__ __forceinline__ void put_pol(uint64_t* dst, const float2 (&v)[FftShape<N>::RR], unsigned tag, int t) {
+  constexpr int RR = FftShape<N>::RR, NT = FftShape<N>::NT;
+#pragma unroll
+  for (int o = 0; o < RR; ++o) {
+    const int k = t + NT * o;
+    xput(dst + k, v[o].x, tag);
+    xput(dst + N + k, v[o].y, tag);
+  }
+}
+
+// v = sum over members n2 of w_n2 * (member n2's spectrum of this
+// polarisation), w_n2 = wsb[(n2 me) mod n_sb], conjugated when CONJ; the
+// member's own spectrum comes from v.
+template <int N, bool CONJ>
+__device__ __forceinline__ void combine_pol(const uint64_t* src, const TeamCtx& c, unsigned tag, int t,
+                                            float2 (&v)[FftShape<N>::RR]) {
+  constexpr int RR = FftShape<N>::RR, NT = FftShape<N>::NT;
+  {
+    const float2 w = c.tab->wsb[(c.me * c.me) % c.nsb];
+#pragma unroll
+    for (int o = 0; o < RR; ++o) v[o] = CONJ ? cmulc(v[o], w) : cmul(v[o], w);
+  }
+  for (int n2 = 0; n2 < c.nsb; ++n2) {
+    if (n2 == c.me) continue;
+    const float2 w = c.tab->wsb[(n2 * c.me) % c.nsb];
+    const uint64_t* row = src + (size_t)n2 * 2 * N;
+    uint64_t wr[RR], wi[RR];
+    float re[RR], im[RR];
+    xissue<RR>(row, t, NT, wr);
+    xissue<RR>(row + N, t, NT, wi);
+    xcomplete<RR>(row, t, NT, tag, c.ctl, wr, re);
+    xcomplete<RR>(row + N, t, NT, tag, c.ctl, wi, im);
+#pragma unroll
+    for (int o = 0; o < RR; ++o) {
+      const float2 u = make_float2(re[o], im[o]);
+      v[o] = cadd(v[o], CONJ ? cmulc(u, w) : cmul(u, w));
+    }
+  }
+}
+
+// polyphase_to_subband through the intensity-row slots xp (rounds round and
+// round + 1).
+template <int N>
+__device__ __forceinline__ void polyphase_to_subband_xp(const TeamCtx& c, uint64_t* xp, unsigned round, int t,
+                                                        float2 (&x)[FftShape<N>::RR],
+                                                        float2 (&y)[FftShape<N>::RR]) {
+  if (c.nsb == 1) return;
+  apply_diag<N, false>(x, y, c.tab->poly_tw + (size_t)c.me * N, t);
+  uint64_t* s0 = xp + (size_t)(round & 1u) * c.nsb * 2 * N;
+  put_pol<N>(s0 + (size_t)c.me * 2 * N, x, round, t);
+  combine_pol<N, false>(s0, c, round, t, x);
+  uint64_t* s1 = xp + (size_t)((round + 1u) & 1u) * c.nsb * 2 * N;
+  put_pol<N>(s1 + (size_t)c.me * 2 * N, y, round + 1u, t);
+  combine_pol<N, false>(s1, c, round + 1u, t, y);
+}
+
+// subband_to_polyphase through the intensity-row slots xp (rounds round and
+// round + 1).
+template <int N>
+__device__ __forceinline__ void subband_to_polyphase_xp(const TeamCtx& c, uint64_t* xp, unsigned round, int t,
+                                                        float2 (&x)[FftShape<N>::RR],
+                                                        float2 (&y)[FftShape<N>::RR]) {
+  if (c.nsb == 1) return;
+  uint64_t* s0 = xp + (size_t)(round & 1u) * c.nsb * 2 * N;
+  put_pol<N>(s0 + (size_t)c.me * 2 * N, x, round, t);
+  combine_pol<N, true>(s0, c, round, t, x);
+  uint64_t* s1 = xp + (size_t)((round + 1u) & 1u) * c.nsb * 2 * N;
+  put_pol<N>(s1 + (size_t)c.me * 2 * N, y, round + 1u, t);
+  combine_pol<N, true>(s1, c, round + 1u, t, y);
+  apply_diag<N, true>(x, y, c.tab->poly_tw + (size_t)c.me * N, t);
+}
+
 // A pointer every lane of the wave holds the same value of, made visible as
 // such to the compiler (so that loads through it become scalar loads).
 template <typename T>
