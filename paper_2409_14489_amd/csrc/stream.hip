@@ -799,44 +799,30 @@ __global__ __launch_bounds__(kColThreads) void st_adj_phase_kernel(float2* __res
   const int i = blockIdx.x / GROUPS;
   const int n1 = (blockIdx.x - i * GROUPS) * kColThreads + threadIdx.x;
   const size_t arr = (size_t)blockIdx.y * nsb + i;
-  {
-    float p[N2];
+  // v' and g' of a polarisation in one pass: both columns in flight, then
+  // both inverse column passes, the sums, and the stores
+  float p[N2], q[N2];
 #pragma unroll
-    for (int k = 0; k < N2; ++k) p[k] = 0.0f;
-#pragma unroll 1
-    for (int pol = 0; pol < 2; ++pol) {
-      float2 vf[N2];
-      load_col<N2>(sf + (arr * 2 + pol) * NP, n1, vf);
-      col_inverse<N2>(tw2, n1, vf);
-#pragma unroll
-      for (int k = 0; k < N2; ++k) {
-        vf[k] = cscale(vf[k], 1.0f / N2);
-        p[k] = fmaf(vf[k].x, vf[k].x, fmaf(vf[k].y, vf[k].y, p[k]));
-      }
-      store_col<N2>(vt + (arr * 2 + pol) * NP, n1, vf);
-    }
-    float* dp = pb + arr * NP + n1;
-#pragma unroll
-    for (int k = 0; k < N2; ++k) dp[kRow * k] = p[k];
-  }
-  float q[N2];
-#pragma unroll
-  for (int k = 0; k < N2; ++k) q[k] = 0.0f;
+  for (int k = 0; k < N2; ++k) p[k] = q[k] = 0.0f;
 #pragma unroll 1
   for (int pol = 0; pol < 2; ++pol) {
-    float2 vg[N2];
+    float2 vf[N2], vg[N2];
+    load_col<N2>(sf + (arr * 2 + pol) * NP, n1, vf);
     load_col<N2>(g + (arr * 2 + pol) * NP, n1, vg);
+    col_inverse<N2>(tw2, n1, vf);
     col_inverse<N2>(tw2, n1, vg);
-    const float2* vs = vt + (arr * 2 + pol) * NP + n1;
-    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int k = 0; k < N2; ++k) {
-      if ((k & 7) == 0) __builtin_amdgcn_sched_barrier(0);
-      const float2 vf = vs[kRow * k];
-      q[k] = fmaf(vg[k].x, vf.y, fmaf(-vg[k].y, vf.x, q[k]));
+      vf[k] = cscale(vf[k], 1.0f / N2);
+      p[k] = fmaf(vf[k].x, vf[k].x, fmaf(vf[k].y, vf[k].y, p[k]));
+      q[k] = fmaf(vg[k].x, vf[k].y, fmaf(-vg[k].y, vf[k].x, q[k]));
     }
+    store_col<N2>(vt + (arr * 2 + pol) * NP, n1, vf);
     store_col<N2>(g + (arr * 2 + pol) * NP, n1, vg);  // g' in place of g
   }
+  float* dp = pb + arr * NP + n1;
+#pragma unroll
+  for (int k = 0; k < N2; ++k) dp[kRow * k] = p[k];
   float* dq = tbar + arr * NP + n1;
 #pragma unroll
   for (int k = 0; k < N2; ++k) dq[kRow * k] = q[k];
