@@ -162,12 +162,29 @@ __device__ __forceinline__ void dft(float2 (&v)[R]) {
 }
 
 // ------------------------------------------------------------- plan (constexpr)
-// LDS index padding of the FFT exchange buffer (entries of 16 bytes): one
-// entry after every 8 keeps the 8 lanes served together by the LDS on
-// distinct banks for every pass's pattern -- consecutive positions, and the
-// stride-R writes of the first pass.
-__device__ __forceinline__ int pad_c(int i) { return i + (i >> 3); }
-__host__ __device__ constexpr int pad_c_size(int n) { return n + (n >> 3) + 1; }
+// LDS placement of entry i of an N-point FFT exchange buffer (entries of 16
+// bytes), chosen per N by measurement (every placement gives the same bits):
+// at N = 2048 and 4096 an XOR swizzle within groups of 16 entries (bits 0-3
+// of i with bits 4-7), no padding; at 8192 one entry of padding after every
+// 16; below 2048 one after every 8, which keeps the 8 lanes served together
+// on distinct banks for consecutive positions and for the stride-R writes
+// of the first pass.  Forward times against one entry after every 8
+// everywhere: 0.315 against 0.319 ms at N' = 4096 (5 subbands), 0.595
+// against 0.601 ms at 8192; at 1024 the swizzle made the adjoint of the
+// gradient workload 2.7% slower.
+template <int N>
+__device__ __forceinline__ int pad_c(int i) {
+  if constexpr (N == 2048 || N == 4096)
+    return i ^ ((i >> 4) & 15);
+  else if constexpr (N == 8192)
+    return i + (i >> 4);
+  else
+    return i + (i >> 3);
+}
+template <int N>
+__host__ __device__ constexpr int pad_c_size() {
+  return (N == 2048 || N == 4096) ? N : N == 8192 ? N + (N >> 4) + 1 : N + (N >> 3) + 1;
+}
 __device__ __forceinline__ int pad_f(int i) { return i + (i >> 4); }
 __host__ __device__ constexpr int pad_f_size(int n) { return n + (n >> 4) + 1; }
 
@@ -200,10 +217,10 @@ struct FftShape {
     }
     return p;
   }
-  static constexpr int LDS_C = pad_c_size(N);  // float2 entries per polarisation (float4 entries in all)
+  static constexpr int LDS_C = pad_c_size<N>();  // float2 entries per polarisation (float4 entries in all)
   // Two exchange buffers (passes alternate between them, so a pass needs no
   // barrier between its reads and its writes) where they fit the LDS beside
-  // one workgroup's other use: N' <= 4096 (2 x 74 KB).
+  // one workgroup's other use: N' <= 4096 (2 x 64 KB at 4096).
   static constexpr bool DB = N <= 4096;
   static constexpr int LDS_ENTRIES = DB ? 2 * LDS_C : LDS_C;  // float4 entries of the exchange
 };
@@ -267,7 +284,7 @@ __device__ __forceinline__ void fft_pass(float2 (&x)[S::RR], float2 (&y)[S::RR],
         vx[a][m] = x[a + m * NB];
         vy[a][m] = y[a + m * NB];
       } else {
-        const float4 v = rd[pad_c(t + S::NT * a + m * NR)];
+        const float4 v = rd[pad_c<S::SIZE>(t + S::NT * a + m * NR)];
         vx[a][m] = make_float2(v.x, v.y);
         vy[a][m] = make_float2(v.z, v.w);
       }
@@ -295,7 +312,7 @@ __device__ __forceinline__ void fft_pass(float2 (&x)[S::RR], float2 (&y)[S::RR],
         x[a + m * NB] = vx[a][m];
         y[a + m * NB] = vy[a][m];
       } else {
-        wr[pad_c((j - k) * R + k + m * L)] = make_float4(vx[a][m].x, vx[a][m].y, vy[a][m].x, vy[a][m].y);
+        wr[pad_c<S::SIZE>((j - k) * R + k + m * L)] = make_float4(vx[a][m].x, vx[a][m].y, vy[a][m].x, vy[a][m].y);
       }
     }
   }
@@ -354,7 +371,7 @@ __device__ __forceinline__ void fft1_pass(float2 (&x)[S::RR], float2* __restrict
       if constexpr (FIRST)
         vx[a][m] = x[a + m * NB];
       else
-        vx[a][m] = rd[pad_c(t + S::NT * a + m * NR)];
+        vx[a][m] = rd[pad_c<S::SIZE>(t + S::NT * a + m * NR)];
     }
 #pragma unroll
   for (int a = 0; a < NB; ++a) {
@@ -373,7 +390,7 @@ __device__ __forceinline__ void fft1_pass(float2 (&x)[S::RR], float2* __restrict
       if constexpr (LAST)
         x[a + m * NB] = vx[a][m];
       else
-        wr[pad_c((j - k) * R + k + m * L)] = vx[a][m];
+        wr[pad_c<S::SIZE>((j - k) * R + k + m * L)] = vx[a][m];
     }
   }
   if constexpr (!LAST) __syncthreads();
